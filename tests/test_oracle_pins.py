@@ -1,0 +1,342 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own formulas: each compares it with an
+independent fact (a theorem's equality, a textbook special case, a closed
+form, brute force, or the ranks of an exactly low-rank stream)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import TTICE, tt_svd, tt_full, truncation_rank, compression_ratio, relative_error
+from paper_2211_12487_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def stream(n, dims=(8, 6, 5), batch=1, seed=0, terms=4, noise=1e-3):
+    return list(synth.smooth_separable_stream(n, dims, terms, noise, batch, seed))
+
+
+# -- truncation rule (eq:deltasvd) -------------------------------------------
+
+def test_truncation_rank_hand_values():
+    s = np.array([3.0, 2.0, 1.0])          # tails: 14, 5, 1, 0
+    assert truncation_rank(s, 14.0) == 0
+    assert truncation_rank(s, 13.99) == 1
+    assert truncation_rank(s, 5.0) == 1
+    assert truncation_rank(s, 1.0) == 2
+    assert truncation_rank(s, 0.99) == 3
+    assert truncation_rank(np.zeros(0), 0.0) == 0
+
+
+# -- P1: Theorem 1 as an equality, and Corollary 1 -----------------------------
+
+@pytest.mark.parametrize("batch", [1, 3])
+def test_P1_error_equals_discarded_energy(batch):
+    eps = 0.05
+    o = TTICE((8, 6, 5), eps)
+    for Y in stream(12, batch=batch, seed=1):
+        first = o.n_total
+        info = o.update(Y)
+        Yhat = o.reconstruct(first, Y.shape[0])
+        err2 = float(np.sum((Y - Yhat) ** 2))
+        assert err2 == pytest.approx(info["achieved2"], rel=1e-9, abs=1e-24)
+        assert err2 <= eps ** 2 * info["normY2"] * (1 + 1e-12)
+
+
+# -- P2: Theorem 2, earlier tensors unchanged ------------------------------------
+
+def test_P2_earlier_reconstructions_unchanged():
+    o = TTICE((8, 6, 5), 0.05)
+    snaps = []
+    for Y in stream(15, seed=2):
+        o.update(Y)
+        snaps.append(o.reconstruct())
+    final = o.reconstruct()
+    for k, S in enumerate(snaps):
+        np.testing.assert_allclose(final[: S.shape[0]], S, rtol=0, atol=1e-12 * np.abs(S).max())
+
+
+# -- P3: orthonormal cores -------------------------------------------------------
+
+def test_P3_orthonormal_cores():
+    o = TTICE((8, 6, 5), 0.01)
+    for Y in stream(20, batch=2, seed=3):
+        o.update(Y)
+        assert o.orthogonality_error() <= 1e-12
+
+
+# -- P4: first increment on empty cores == TT-SVD of the (d+1)-way batch ----------
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_P4_first_increment_is_ttsvd(seed):
+    eps = 0.1
+    dims = (8, 6, 5)
+    Y = next(synth.smooth_separable_stream(7, dims, 4, 1e-2, 7, seed))
+    o = TTICE(dims, eps)
+    info = o.update(Y)
+    X = np.moveaxis(Y, 0, -1)                     # n_1 x ... x n_d x N
+    cores, ranks = tt_svd(X, eps)
+    assert ranks[1:-1] == o.ranks[1:]
+    assert min(info["margin"]) > 1e-8
+    Xtt = tt_full(cores)
+    Xice = np.moveaxis(o.reconstruct(), 0, -1)
+    assert relative_error(Xtt, Xice) < 1e-10
+    assert relative_error(X, Xtt) <= eps
+
+
+# -- P5: d = 1 reduces to the Eckart-Young rank of the n_1 x N matrix --------------
+
+def test_P5_order_one_is_eckart_young():
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((12, 4)) @ rng.standard_normal((4, 30)) + 1e-3 * rng.standard_normal((12, 30))
+    eps = 0.02
+    o = TTICE((12,), eps)
+    o.update(A.T)                                 # N = 30 tensors of length 12
+    lam = np.sort(np.linalg.eigvalsh(A @ A.T))[::-1]   # sigma^2 via a different routine
+    tol2 = (eps * np.linalg.norm(A)) ** 2
+    r = next(r for r in range(len(lam) + 1) if lam[r:].sum() <= tol2)
+    assert o.ranks[1] == r
+    assert relative_error(A.T, o.reconstruct()) <= eps
+
+
+# -- P6: exactly low-rank stream (App. B) -------------------------------------------
+
+def _golden_lowrank():
+    with open(os.path.join(GOLDEN, "tt_lowrank_ranks.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _golden_lowrank())
+@pytest.mark.parametrize("algo", ["plain", "star"])
+def test_P6_lowrank_stream_rank_discovery(case, algo):
+    dims, tr, eps = tuple(case["dims"]), case["tt_ranks"], case["eps"]
+    o = TTICE(dims, eps, algo=algo)
+    for k, Y in enumerate(synth.tt_lowrank_stream(dims, tr[1:-1], 40, 1, seed=7), start=1):
+        o.update(Y)
+        assert o.ranks[1:] == [tr[1], tr[2], min(k, tr[3])], (k, o.ranks)
+
+
+# -- P7: data in the span adds no rank -----------------------------------------------
+
+def test_P7_in_span_no_growth():
+    o = TTICE((8, 6, 5), 0.05)
+    for Y in stream(10, seed=4):
+        o.update(Y)
+    ranks = list(o.ranks)
+    for ell in (0, 3, 9):
+        Yhat = o.reconstruct(ell, 1)
+        info = o.update(Yhat)
+        assert info["rR"] == [0, 0, 0]
+        assert o.ranks == ranks
+        np.testing.assert_allclose(o.G[:, -1], o.G[:, ell], atol=1e-12 * np.abs(o.G[:, ell]).max())
+
+
+# -- P8: eps_upd = eps_des when every frame exceeds; then Alg. 2 == Alg. 1 ------------
+
+def test_P8_star_equals_plain_when_all_frames_exceed():
+    eps = 0.02
+    a, b = TTICE((8, 6, 5), eps), TTICE((8, 6, 5), eps, algo="star")
+    for Y in stream(12, batch=3, seed=6, terms=6):
+        ia = a.update(Y)
+        ib = b.update(Y)
+        assert all(e > eps for e in ib["rel_err_old"])
+        assert ib["eps_upd"] == pytest.approx(eps, rel=1e-12)
+        assert ia["ranks"] == ib["ranks"]
+    np.testing.assert_allclose(a.reconstruct(), b.reconstruct(), atol=1e-10 * np.abs(a.reconstruct()).max())
+
+
+# -- P9: brute force on the whole accumulation; CR by hand ----------------------------
+
+def test_P9_bruteforce_rre_and_cr():
+    eps = 0.05
+    dims = (8, 6, 5)
+    data = stream(25, dims, seed=8)
+    o = TTICE(dims, eps)
+    for Y in data:
+        o.update(Y)
+    X = np.concatenate(data)
+    Xh = o.reconstruct()
+    for b in range(X.shape[0]):
+        assert relative_error(X[b], Xh[b]) <= eps * (1 + 1e-12)
+    assert relative_error(X, Xh) <= eps
+    # CR by hand: dims (4,5,6), 7 tensors, ranks (1,2,3,4,1): 840 / 138
+    assert compression_ratio((4, 5, 6), 7, [1, 2, 3, 4, 1]) == pytest.approx(840 / 138)
+    n_params = sum(G.size for G in o.tt_cores())
+    assert compression_ratio(dims, o.n_total, o.ranks + [1]) == pytest.approx(X.size / n_params)
+
+
+# -- P10: rank bounds ----------------------------------------------------------------
+
+def test_P10_rank_bounds():
+    dims = (4, 3, 5)
+    o = TTICE(dims, 1e-3)
+    rng = np.random.default_rng(9)
+    for k in range(1, 8):
+        o.update(rng.standard_normal((1,) + dims))
+        r = o.ranks
+        for i in range(1, 4):
+            left = r[i - 1] * dims[i - 1]
+            right = int(np.prod(dims[i:])) * o.n_total
+            assert r[i] <= min(left, right)
+
+
+# -- P11: permutation of frames inside a batch ---------------------------------------
+
+def test_P11_permutation_invariance():
+    Ys = stream(12, batch=4, seed=10)
+    a, b = TTICE((8, 6, 5), 0.05), TTICE((8, 6, 5), 0.05)
+    perm = np.array([2, 0, 3, 1])
+    for Y in Ys:
+        a.update(Y)
+        b.update(Y[perm])
+        assert a.ranks == b.ranks
+    Ra, Rb = a.reconstruct(), b.reconstruct()
+    inv = np.concatenate([k * 4 + perm for k in range(3)])
+    np.testing.assert_allclose(Rb, Ra[inv], atol=1e-10 * np.abs(Ra).max())
+
+
+# -- P12: scaling ----------------------------------------------------------------------
+
+def test_P12_scaling():
+    Ys = stream(10, batch=2, seed=11)
+    a, b = TTICE((8, 6, 5), 0.05), TTICE((8, 6, 5), 0.05)
+    alpha = 37.5
+    for Y in Ys:
+        a.update(Y)
+        b.update(alpha * Y)
+        assert a.ranks == b.ranks
+    np.testing.assert_allclose(b.reconstruct(), alpha * a.reconstruct(), rtol=1e-9, atol=1e-9 * alpha)
+
+
+# -- P13: telescoping identity of the chain projection -----------------------------------
+
+def test_P13_telescoping_matches_bruteforce():
+    o = TTICE((8, 6, 5), 0.05)
+    for Y in stream(8, batch=2, seed=12):
+        o.update(Y)
+    Ynew = stream(5, batch=5, seed=99)[0]
+    _, Ytil = o.project(Ynew)
+    brute = np.array([np.sum((Ynew[b] - Ytil[b]) ** 2) for b in range(5)])
+    # sum over levels of the per-frame residual energies along the chain
+    tele = np.zeros(5)
+    Z = Ynew.reshape(5, 8, -1)
+    for i, U in enumerate(o.U):
+        C = np.einsum("rk,brc->bkc", U, Z)
+        tele += np.sum((Z - np.einsum("rk,bkc->brc", U, C)) ** 2, axis=(1, 2))
+        Z = C.reshape(5, o.ranks[i + 1] * (o.dims[i + 1] if i + 1 < 3 else 1), -1)
+    np.testing.assert_allclose(tele, brute, rtol=1e-10)
+
+
+# -- P14: tau = 1 occupancy skip is exact -------------------------------------------------
+
+def test_P14_full_core_skip_changes_nothing():
+    a = TTICE((4, 3, 5), 0.01, algo="star", tau=1.0)
+    b = TTICE((4, 3, 5), 0.01, algo="star", tau=2.0)   # never skips
+    for Y in stream(10, (4, 3, 5), batch=2, seed=13, terms=6):
+        a.update(Y)
+        b.update(Y)
+        assert a.ranks == b.ranks
+    assert a.ranks[1] == 4          # core 1 became full, so the skip was exercised
+    np.testing.assert_allclose(a.reconstruct(), b.reconstruct(), atol=1e-10)
+
+
+# -- TT-SVD itself -------------------------------------------------------------------------
+
+def test_ttsvd_recovers_exact_tt_ranks():
+    rng = np.random.default_rng(14)
+    r = [1, 2, 3, 2, 1]
+    n = [5, 6, 4, 7]
+    cores = [rng.standard_normal((r[i], n[i], r[i + 1])) for i in range(4)]
+    X = tt_full(cores)
+    c2, ranks = tt_svd(X, 1e-10)
+    assert ranks == r
+    assert relative_error(X, tt_full(c2)) < 1e-12
+
+
+def test_ttsvd_error_bound():
+    rng = np.random.default_rng(15)
+    X = rng.standard_normal((6, 5, 4, 3))
+    for eps in (0.1, 0.3, 0.6):
+        c2, _ = tt_svd(X, eps)
+        assert relative_error(X, tt_full(c2)) <= eps
+
+
+def test_reconstruct_matches_full_contraction():
+    o = TTICE((8, 6, 5), 0.05)
+    for Y in stream(6, batch=2, seed=16):
+        o.update(Y)
+    cores = o.tt_cores()
+    full = tt_full(cores[:-1] + [cores[-1]])              # (n1, n2, n3, N_total)
+    np.testing.assert_allclose(np.moveaxis(full, -1, 0), o.reconstruct(), atol=1e-12)
+
+
+# -- degenerate inputs -----------------------------------------------------------------------
+
+def test_zero_batch_and_empty_batch():
+    o = TTICE((4, 3, 5), 0.1)
+    info = o.update(np.zeros((0, 4, 3, 5)))
+    assert o.n_total == 0 and info["ranks"] == [1, 0, 0, 0, 1]
+    o.update(np.zeros((2, 4, 3, 5)))
+    assert o.ranks == [1, 0, 0, 0] and o.n_total == 2
+    assert np.all(o.reconstruct() == 0)
+    Y = stream(1, (4, 3, 5), seed=17)[0]
+    o.update(Y)
+    assert relative_error(Y, o.reconstruct(2, 1)) <= 0.1
+
+
+def test_invalid_arguments():
+    with pytest.raises(ValueError):
+        TTICE((4, 0, 3), 0.1)
+    with pytest.raises(ValueError):
+        TTICE((4, 3), 1.5)
+    o = TTICE((4, 3), 0.1)
+    with pytest.raises(ValueError):
+        o.update(np.full((1, 4, 3), np.nan))
+    with pytest.raises(ValueError):
+        o.update(np.zeros((1, 3, 4)))
+
+
+def _designed_increment():
+    """One 4x5 tensor with singular values (1, 0.1): at eps = 0.12 and d = 2,
+    eps^2 ||Y||^2 / d = 0.007272 < 0.01 (energy of the second direction), so
+    Corollary 1's tolerance keeps both directions, while a tolerance of
+    eps ||Y|| / sqrt(d-1) (0.014544 > 0.01) would drop the second."""
+    Y = np.zeros((1, 4, 5))
+    Y[0, 0, 0] = 1.0
+    Y[0, 1, 1] = 0.1
+    return Y
+
+
+def test_corollary1_tolerance_designed_spectrum():
+    Y = _designed_increment()
+    o = TTICE((4, 5), 0.12)
+    info = o.update(Y)
+    assert o.ranks == [1, 2, 1]
+    assert info["rR"] == [2, 1]
+    assert info["achieved2"] == pytest.approx(0.0, abs=1e-28)
+    np.testing.assert_allclose(o.reconstruct(), Y, atol=1e-15)
+    _, ranks = tt_svd(np.moveaxis(Y, 0, -1), 0.12)          # 4 x 5 x 1, delta = eps/sqrt(2)
+    assert ranks == [1, 2, 1, 1]
+
+
+def test_planted_wrong_tolerance_is_caught():
+    """A planted mistake in the oracle (sqrt(d-1) in place of sqrt(d) in
+    Corollary 1) changes the ranks on the designed spectrum."""
+    import oracle.ttice_oracle as m
+
+    class WrongTol(m.TTICE):
+        def update(self, Y):
+            saved = self.eps
+            self.eps = saved * math.sqrt(self.d / (self.d - 1))
+            try:
+                return super().update(Y)
+            finally:
+                self.eps = saved
+
+    o = WrongTol((4, 5), 0.12)
+    o.update(_designed_increment())
+    assert o.ranks != [1, 2, 1]
