@@ -1,0 +1,154 @@
+/*
+ * ttice.h - C ABI of the MI355X (gfx950) TT-ICE library, libttice.so.
+ *
+ * TT-ICE maintains the tensor-train (TT) decomposition of an accumulation of
+ * d-way tensors Y^1, Y^2, ... of size n_1 x ... x n_d that arrive in batches
+ * (increments).  Problem statement: Sec. 1, Problem 1 (keep every stored
+ * tensor within eps_des relative error, ||Y^l - Yhat^l||_F <= eps_des ||Y^l||_F).
+ * Algorithm 1 (TT-ICE, Sec. 3.1) expands the left-orthonormal cores with only
+ * the new orthogonal directions a new increment needs; Algorithm 2 (TT-ICE*,
+ * Sec. 3.3) adds the skip / subselect heuristics.
+ *
+ * State: unfolded cores U_i (r_{i-1} n_i x r_i), i = 1..d, r_0 = 1, and the
+ * last core G_{d+1} (r_d x N_total) whose column j is the latent vector of the
+ * j-th stored tensor (eq:lastcore, eq:last_core_latent).  All ranks start at 0.
+ *
+ * Conventions
+ *  - Every tensor buffer is C-ordered (row-major), mode n_d fastest, frames
+ *    outermost: a batch is [N][n_1]...[n_d].
+ *  - "device pointer" = memory the HIP device can read/write (hipMalloc'd,
+ *    e.g. a torch CUDA tensor's data_ptr()).  The library never frees caller
+ *    memory and never keeps a pointer past the call that received it.
+ *  - Every call is host-synchronous with respect to the library's stream: on
+ *    return, all reads of caller buffers and all writes of outputs are done.
+ *  - Status codes are negative on failure.  On ANY failure the state is left
+ *    exactly as it was before the call (transactional update).
+ *  - A state is not thread-safe: calls on one state must not overlap.
+ */
+#ifndef TTICE_H
+#define TTICE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ttice_state ttice_state;
+
+enum ttice_status {
+  TTICE_OK = 0,
+  TTICE_EINVAL = -1,  /* bad argument, or a non-finite batch */
+  TTICE_ENOMEM = -2,  /* device or host allocation failed */
+  TTICE_EDEVICE = -3, /* HIP runtime / kernel launch error */
+  TTICE_ESTATE = -4   /* null or unusable state */
+};
+
+enum ttice_dtype { TTICE_F32 = 0, TTICE_F64 = 1 };
+
+/* Arithmetic used for the bulk projections / contractions U^T Y, U (U^T Y).
+ * FP64 norms, the residual's SVD and re-orthogonalisation are FP64 always. */
+enum ttice_prec { TTICE_PREC_FP64 = 0, TTICE_PREC_FP32 = 1, TTICE_PREC_BF16X3 = 2 };
+
+/* Algorithm 1 (TT-ICE) or Algorithm 2 (TT-ICE*). */
+enum ttice_algo { TTICE_ALG_PLAIN = 0, TTICE_ALG_STAR = 1 };
+
+/* TT-ICE* skip test: mean of the per-tensor relative errors (eq:relerror,
+ * the rule Algorithm 2 uses) or the batch relative error
+ * (eq:batchrelativeerror). */
+enum ttice_skip_rule { TTICE_SKIP_MEAN = 0, TTICE_SKIP_BATCH = 1 };
+
+enum ttice_option {
+  TTICE_OPT_PREC = 1,      /* int32_t, enum ttice_prec (default FP64)          */
+  TTICE_OPT_ALGO = 2,      /* int32_t, enum ttice_algo (default PLAIN)         */
+  TTICE_OPT_SKIP_RULE = 3, /* int32_t, enum ttice_skip_rule (default MEAN)     */
+  TTICE_OPT_TAU = 4,       /* double, occupancy threshold of Algorithm 2,
+                              eq:coreoccupancy (default 1.0: skip only full
+                              cores, which cannot gain a direction)            */
+  TTICE_OPT_STREAM = 5     /* hipStream_t passed as (const void*)&stream; all
+                              device work of later calls runs on it (default:
+                              the null stream)                                 */
+};
+
+#define TTICE_MAX_D 16
+
+/* Per-update report (all arrays indexed by core i = 0..d-1 unless noted). */
+struct ttice_update_info {
+  int32_t d;
+  int32_t skipped;          /* Algorithm 2 took the skip branch               */
+  int64_t n;                /* tensors in this increment                        */
+  int64_t used;             /* tensors used to update the cores (|D| in Alg. 2) */
+  int64_t n_total;          /* stored tensors after the update                  */
+  double norm_y2;           /* ||Y||_F^2 of the increment (FP64)                */
+  double eps_core;          /* SVD truncation tolerance used at every core      */
+  double eps_upd;           /* relaxed relative tolerance (eq:epsilonmodification);
+                               equals eps for Algorithm 1                        */
+  int64_t ranks[TTICE_MAX_D + 2]; /* r_0 = 1, r_1..r_d, r_{d+1} = 1 after update */
+  int64_t r_new[TTICE_MAX_D];     /* directions appended to core i              */
+  double rho2[TTICE_MAX_D];       /* ||R_i||_F^2 (NaN when the core was skipped)  */
+  double tail2[TTICE_MAX_D];      /* discarded energy ||E_i||_F^2 (eq:svdfirst)  */
+  double margin[TTICE_MAX_D];     /* relative distance of the rank decision from
+                                     the threshold: min over r in {r_R, r_R - 1}
+                                     of |tail(r) - eps_core^2| / eps_core^2      */
+  double achieved2;               /* sum_i tail2[i] = ||Y - Yhat||_F^2 for
+                                     Algorithm 1 (Theorem 1's proof is a chain of
+                                     Pythagorean equalities); -1 for Alg. 2     */
+};
+
+/* Create an empty accumulation for d-way tensors of size dims[0..d-1] with
+ * relative tolerance eps (Corollary 1: per-core tolerance eps ||Y||_F / sqrt(d)).
+ * d in [1, TTICE_MAX_D], every dims[i] >= 1, eps in (0, 1), prod(dims) < 2^31.
+ * Selects the current HIP device.  *out receives the new state (caller frees
+ * it with ttice_destroy).  Errors: EINVAL (bad d/dims/eps/out), ENOMEM. */
+int ttice_create(int32_t d, const int64_t* dims, double eps, ttice_state** out);
+
+/* Set an option (enum ttice_option); val points to the value's type above.
+ * Options may be changed between updates.  Errors: ESTATE, EINVAL. */
+int ttice_set_option(ttice_state* st, int32_t key, const void* val);
+
+/* Incorporate one increment (Algorithm 1, or Algorithm 2 per TTICE_OPT_ALGO).
+ * batch: device pointer to n tensors, [n][n_1]...[n_d] C-order, element type
+ * dtype (TTICE_F32 or TTICE_F64); read only.  n == 0 is a no-op.
+ * info: host pointer or NULL.  Errors: EINVAL (bad args, non-finite batch),
+ * ENOMEM, EDEVICE, ESTATE; the state is unchanged on error. */
+int ttice_update(ttice_state* st, const void* batch, int64_t n, int32_t dtype,
+                 struct ttice_update_info* info);
+
+/* Write the approximations of stored tensors first .. first+count-1
+ * (eq:last_core_latent) to out: device pointer, [count][n_1]...[n_d] C-order,
+ * element type dtype.  Errors: EINVAL (range outside [0, n_total), bad
+ * dtype, null out with count > 0), ENOMEM, EDEVICE, ESTATE. */
+int ttice_reconstruct(ttice_state* st, int64_t first, int64_t count, void* out,
+                      int32_t dtype);
+
+/* Latent coefficients of new tensors under the current cores, without
+ * updating anything (Sec. 4.1, relative prediction error): coef (device,
+ * [n][r_d] FP64) and, if err2 != NULL, per-tensor squared residual
+ * ||Y(b) - Ytilde(b)||_F^2 (device, [n] FP64) and, if y2 != NULL, ||Y(b)||_F^2
+ * (device, [n] FP64).  Errors as ttice_update. */
+int ttice_project(ttice_state* st, const void* batch, int64_t n, int32_t dtype,
+                  double* coef, double* err2, double* y2);
+
+/* ranks: host array of d+2 entries (r_0 = 1, r_1..r_d, r_{d+1} = 1);
+ * n_total: host pointer (may be NULL).  Errors: ESTATE, EINVAL. */
+int ttice_ranks(const ttice_state* st, int64_t* ranks, int64_t* n_total);
+
+/* Copy core i to out (device pointer, FP64, compact row-major):
+ * i in [0, d): U_{i+1}, shape (r_i n_{i+1}) x r_{i+1};
+ * i == d: the last core TRANSPOSED, shape N_total x r_d (row j = latent
+ * vector of stored tensor j).  rows/cols (host, may be NULL) receive the
+ * shape; out may be NULL to query the shape only.  Errors: ESTATE, EINVAL,
+ * EDEVICE. */
+int ttice_get_core(ttice_state* st, int32_t i, double* out, int64_t* rows, int64_t* cols);
+
+/* Release the state and all device memory it owns.  NULL is a no-op. */
+void ttice_destroy(ttice_state* st);
+
+/* Static description of a status code. */
+const char* ttice_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTICE_H */

@@ -1,0 +1,117 @@
+// Internal interface between the TT-ICE host engine and its gfx950 kernels.
+// Not part of the public ABI (include/ttice.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ttice {
+
+constexpr int32_t kUnframed = 0x7fffffff;
+
+// A strided view of a matrix whose row and/or column index may be split into
+// "frames": element (i, j) lives at
+//   base + row_off(i) + col_off(j),
+//   row_off(i) = (i / rpf) * rfs + (i % rpf) * rs,
+//   col_off(j) = (cfidx ? cfidx[j / cpf] : j / cpf) * cfs + (j % cpf) * cs.
+// A batch of N frame-major matrices Z[b] (rows x cols, row-major, frame
+// stride fs) seen as the unfolding [Z[0] Z[1] ... Z[N-1]] (rows x N*cols) is
+// {rpf=unframed, rs=cols, cpf=cols, cfs=fs, cs=1}.  cfidx optionally
+// renumbers column frames (a gathered subset of the batch, read in place).
+struct View {
+  int32_t rpf = kUnframed;
+  int32_t cpf = kUnframed;
+  int64_t rfs = 0, rs = 0;
+  int64_t cfs = 0, cs = 0;
+  const int32_t* cfidx = nullptr;
+};
+
+inline View row_major(int64_t ld) {
+  View v;
+  v.rs = ld;
+  v.cs = 1;
+  return v;
+}
+inline View transposed(View v) {
+  View t;
+  t.rpf = v.cpf;
+  t.rfs = v.cfs;
+  t.rs = v.cs;
+  t.cpf = v.rpf;
+  t.cfs = v.rfs;
+  t.cs = v.rs;
+  t.cfidx = v.cfidx;
+  return t;
+}
+// [Z[0] ... Z[N-1]] for frame-major data, rows x (N*cols)
+inline View unfolding(int64_t cols, int64_t fs, const int32_t* fidx = nullptr) {
+  View v;
+  v.rs = cols;
+  v.cpf = (int32_t)cols;
+  v.cfs = fs;
+  v.cs = 1;
+  v.cfidx = fidx;
+  return v;
+}
+
+// D = alpha * A * B + beta * E over an M x N output, K-sum split into
+// ceil(K / kchunk) slices along grid z (slice z writes D + z*dz).  A is FP64.
+// Optional outputs: colpart[mb*N + n] = sum over the rows of output tile mb of
+// D(m, n)^2 (FP64), bnorm[n] = sum_k B(k, n)^2 (only with one K slice).
+// Any of E / D / colpart / bnorm may be null.
+template <typename TB, typename TE, typename TD>
+hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk, double alpha,
+                const double* A, View va, const TB* B, View vb, double beta, const TE* E, View ve,
+                TD* D, View vd, int64_t dz, double* colpart, double* bnorm);
+
+inline int32_t gemm_row_blocks(int32_t M) { return M > 0 ? (M + 63) / 64 : 1; }
+
+// out[f] = sum_{mb<MB} sum_{c<cpf} part[mb*ld + f*cpf + c], f < F.
+hipError_t frame_sums(hipStream_t st, const double* part, int32_t MB, int64_t ld, int32_t cpf,
+                      int32_t F, double* out);
+// out[0] = sum_{i<n} x[i] (deterministic order); out[1] = 1 if any x is not finite.
+hipError_t total_sum(hipStream_t st, const double* x, int64_t n, double* out);
+// acc[i] += x[i]
+hipError_t accumulate(hipStream_t st, double* acc, const double* x, int64_t n);
+
+// G (m x m, ld = m) = sum over S slices of the upper triangle of part
+// (slice stride m*m), mirrored to be exactly symmetric.
+hipError_t gram_reduce(hipStream_t st, const double* part, int32_t S, int32_t m, double* G);
+
+// Symmetric eigendecomposition G = V diag(w) V^T by cyclic two-sided Jacobi
+// (round-robin parallel ordering).  G (m x m, row-major, ld = m) is
+// overwritten; V (m x m row-major, column t = eigenvector t); w (m), unsorted.
+// scratch: >= 8*m doubles.  Returns the number of sweeps in *h_sweeps
+// (device int written to dsweeps).
+hipError_t sym_eig(hipStream_t st, int32_t m, double* G, double* V, double* w, int32_t* dsweeps);
+int32_t sym_eig_lds_max();
+
+// Rank selection for SVD(R, eps) from the eigenvalues w (m) of the residual's
+// Gram matrix: order[t] = index of the t-th largest eigenvalue, lam[t] its
+// value clamped to >= 0; tail[r] = sum_{t>=r} lam[t]; r_R = smallest r with
+// tail[r] <= tol2, clipped to cap.  res[0] = r_R, res[1] = tail[r_R],
+// res[2] = margin, res[3] = 1 if any eigenvalue was not finite.
+hipError_t select_rank(hipStream_t st, int32_t m, const double* w, double tol2, int64_t cap,
+                       int32_t* order, double* lam, double* tail, double* res);
+
+// W (rows x r, ld = r) = V[:, order[t]] (left case)  or
+// Vs (M x r, ld = r) = V[:, order[t]] / sqrt(lam[t]) (right case, scale = true)
+hipError_t gather_columns(hipStream_t st, int32_t rows, int32_t r, const double* V, int32_t ldv,
+                          const int32_t* order, const double* lam, bool scale, double* W);
+// Flip each column of W (rows x r, ld) so its largest-|.| entry (lowest row
+// index on ties) is positive.
+hipError_t sign_fix(hipStream_t st, int32_t rows, int32_t r, double* W, int64_t ld);
+// dst(i, j) = src(i, j) for i < rows, j < cols (both row-major)
+hipError_t copy2d(hipStream_t st, int64_t rows, int64_t cols, const double* src, int64_t lds,
+                  double* dst, int64_t ldd);
+// dst(i, j) = 0 for i < rows, j < cols
+hipError_t zero2d(hipStream_t st, int64_t rows, int64_t cols, double* dst, int64_t ldd);
+
+// Algorithm 2 decision from per-frame squared errors e2[b] (old cores) and
+// norms y2[b]: res[0] = mean relative error, res[1] = batch relative error,
+// res[2] = sum e2 over D_C (frames with rel <= eps), res[3] = ||D||^2,
+// res[4] = |D|, res[5] = ||Y||^2; dlist = indices of D in increasing order.
+hipError_t star_decide(hipStream_t st, int32_t N, const double* e2, const double* y2, double eps,
+                       int32_t* dlist, double* res);
+
+}  // namespace ttice

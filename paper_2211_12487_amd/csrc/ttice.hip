@@ -1,0 +1,835 @@
+// TT-ICE host engine and C ABI (include/ttice.h).
+//
+// The engine sequences the gfx950 kernels of kernels.hip through Algorithm 1
+// (TT-ICE) and Algorithm 2 (TT-ICE*) of arXiv 2211.12487.  Decisions that
+// shape later launches (is a core updated, how many directions are appended)
+// come back to the host as a few FP64 scalars per core.
+//
+// Device layout
+//   core U_i (i = 0..d-1): row-major FP64, (r_{i-1} n_i) rows x r_i columns,
+//     leading dimension ld >= r_i, row capacity >= rows; rows beyond the
+//     committed ones are scratch.  Zero padding (eq:ukpad) appends rows.
+//   last core: stored transposed, row j = latent vector of stored tensor j
+//     (N_total x r_d, ld >= r_d).  Padding the last core's rows with zeros
+//     (eq:lastcore) zero-fills new entries of the old rows.
+//   level data Z_i: frame-major [N][rows_i][cols_i], frame stride prod(dims);
+//     the C-order reshape of eq:project_further is free in this layout.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <limits>
+#include <vector>
+
+#include "../../include/ttice.h"
+#include "kernels.h"
+
+using namespace ttice;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Core {
+  double* p = nullptr;
+  int64_t cap_rows = 0;
+  int64_t ld = 0;
+};
+
+int status_of(hipError_t e) {
+  if (e == hipSuccess) return TTICE_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return TTICE_ENOMEM;
+  return TTICE_EDEVICE;
+}
+
+#define CK(expr)                                  \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return status_of(e_);   \
+  } while (0)
+
+#define CKS(expr)                      \
+  do {                                 \
+    int s_ = (expr);                   \
+    if (s_ != TTICE_OK) return s_;     \
+  } while (0)
+
+// grow-only scratch (contents not preserved)
+int ensure(DevBuf& b, size_t bytes) {
+  if (bytes <= b.bytes && b.p) return TTICE_OK;
+  size_t nb = std::max(bytes, b.bytes + b.bytes / 2);
+  nb = std::max<size_t>(nb, 256);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, nb);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return TTICE_ENOMEM;
+  }
+  if (b.p) {
+    (void)hipDeviceSynchronize();  // the old buffer may still be read by queued work
+    (void)hipFree(b.p);
+  }
+  b.p = p;
+  b.bytes = nb;
+  return TTICE_OK;
+}
+
+template <typename T>
+T* as(DevBuf& b) {
+  return static_cast<T*>(b.p);
+}
+
+}  // namespace
+
+struct ttice_state {
+  int32_t d = 0;
+  int64_t dims[TTICE_MAX_D] = {};
+  int64_t P = 1;  // prod(dims)
+  double eps = 0.0;
+  int32_t prec = TTICE_PREC_FP64;
+  int32_t algo = TTICE_ALG_PLAIN;
+  int32_t skip_rule = TTICE_SKIP_MEAN;
+  double tau = 1.0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  Core U[TTICE_MAX_D];
+  Core Gt;  // last core, transposed (frames x r_d)
+  int64_t rk[TTICE_MAX_D + 1] = {};  // rk[0] = 1, rk[i] = r_i (committed)
+  int64_t n_total = 0;
+
+  // workspace
+  DevBuf z[2], rbuf, colpart, bnorm, fres, fy2, e2acc, scal, gpart, gram, V, w, order, lam, tail,
+      selres, W, W2, T, S, dlist, coefscratch, sweeps;
+  double* hs = nullptr;  // pinned host scalars (64 doubles)
+
+  ~ttice_state();
+
+  int64_t cols(int i) const {  // columns per tensor at level i
+    int64_t c = 1;
+    for (int j = i + 1; j < d; ++j) c *= dims[j];
+    return c;
+  }
+  int grow_core(Core& c, int64_t need_rows, int64_t need_cols, int64_t keep_rows, int64_t keep_cols);
+  int sync_scalars(int n);
+  template <typename TIn>
+  int core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, double tol_in, int64_t* rk_pend,
+                ttice_update_info* info, bool use_occ, double* last_out, int64_t last_ld);
+  template <typename TIn>
+  int chain_project(const TIn* zin0, int64_t N, const int64_t* rks, double* coef_out, int64_t coef_ld,
+                    double* err2_out, double* y2_out, int* nonfinite);
+  template <typename TIn>
+  int update_impl(const TIn* batch, int64_t N, ttice_update_info* info);
+  template <typename TD>
+  int reconstruct_impl(int64_t first, int64_t count, TD* out);
+};
+
+ttice_state::~ttice_state() {
+  for (int i = 0; i < TTICE_MAX_D; ++i)
+    if (U[i].p) (void)hipFree(U[i].p);
+  if (Gt.p) (void)hipFree(Gt.p);
+  DevBuf* bufs[] = {&z[0], &z[1], &rbuf, &colpart, &bnorm, &fres, &fy2, &e2acc, &scal, &gpart,
+                    &gram, &V, &w, &order, &lam, &tail, &selres, &W, &W2, &T, &S, &dlist,
+                    &coefscratch, &sweeps};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (hs) (void)hipHostFree(hs);
+}
+
+// Reallocate core storage to at least need_rows x need_cols, preserving the
+// keep_rows x keep_cols leading block.
+int ttice_state::grow_core(Core& c, int64_t need_rows, int64_t need_cols, int64_t keep_rows,
+                           int64_t keep_cols) {
+  if (need_rows <= c.cap_rows && need_cols <= c.ld && c.p) return TTICE_OK;
+  int64_t nr = std::max<int64_t>(need_rows, c.cap_rows);
+  if (need_rows > c.cap_rows) nr = std::max<int64_t>(need_rows, 2 * c.cap_rows);
+  int64_t nl = std::max<int64_t>(need_cols, c.ld);
+  if (need_cols > c.ld) nl = std::max<int64_t>(need_cols, 2 * c.ld);
+  nr = std::max<int64_t>(nr, 1);
+  nl = std::max<int64_t>(nl, 1);
+  double* p = nullptr;
+  hipError_t e = hipMalloc(&p, (size_t)nr * nl * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return TTICE_ENOMEM;
+  }
+  if (c.p && keep_rows > 0 && keep_cols > 0) {
+    e = hipMemcpy2DAsync(p, nl * sizeof(double), c.p, c.ld * sizeof(double), keep_cols * sizeof(double),
+                         keep_rows, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) {
+      (void)hipFree(p);
+      return status_of(e);
+    }
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      (void)hipFree(p);
+      return status_of(e);
+    }
+  }
+  if (c.p) (void)hipFree(c.p);
+  c.p = p;
+  c.cap_rows = nr;
+  c.ld = nl;
+  return TTICE_OK;
+}
+
+int ttice_state::sync_scalars(int n) {
+  CK(hipMemcpyAsync(hs, scal.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, stream));
+  CK(hipStreamSynchronize(stream));
+  return TTICE_OK;
+}
+
+namespace {
+
+// Split the K-sum of a Gram product so the launch has a few hundred blocks.
+int32_t gram_kchunk(int32_t m, int64_t K) {
+  const int64_t tiles = (int64_t)((m + 63) / 64) * ((m + 63) / 64);
+  int64_t S = std::max<int64_t>(1, 512 / std::max<int64_t>(tiles, 1));
+  S = std::min<int64_t>(S, std::max<int64_t>(1, K / 256));
+  int64_t chunk = (K + S - 1) / S;
+  chunk = ((chunk + 15) / 16) * 16;
+  return (int32_t)std::max<int64_t>(chunk, 16);
+}
+
+}  // namespace
+
+// Levels i = 0..d-1 of Algorithm 1 (and the update loop of Algorithm 2) on
+// N frames read from zin0 (frame stride P, optional frame map fidx).
+// tol_in < 0: the per-core tolerance is eps ||Y||_F / sqrt(d) (Corollary 1)
+// with ||Y|| computed here; otherwise tol_in is the tolerance.
+// rk_pend holds the ranks being built (starts as the committed ones).
+// The last level's coefficients go to last_out (row j = frame j, stride
+// last_ld); last_out == nullptr means "into the last core after n_total".
+template <typename TIn>
+int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, double tol_in,
+                           int64_t* rk_pend, ttice_update_info* info, bool use_occ, double* last_out,
+                           int64_t last_ld) {
+  hipStream_t st = stream;
+  double tol2 = tol_in >= 0 ? tol_in * tol_in : -1.0;
+  const void* zin = zin0;
+  bool zin_is_input = true;
+  for (int i = 0; i < d; ++i) {
+    const int64_t rows = rk_pend[i] * dims[i];
+    const int64_t cols = this->cols(i);
+    const int64_t r = rk_pend[i + 1];
+    const int64_t Ncol = N * cols;
+    Core& Ui = U[i];
+    const bool last = (i == d - 1);
+    const int32_t* fmap = zin_is_input ? fidx : nullptr;
+    const View vz = unfolding(cols, P, fmap);
+
+    double* out;
+    int64_t fs_out;
+    if (!last) {
+      out = as<double>(z[i % 2]);
+      fs_out = P;
+    } else if (last_out) {
+      out = last_out;
+      fs_out = last_ld;
+    } else {
+      out = Gt.p + n_total * Gt.ld;
+      fs_out = Gt.ld;
+    }
+    const View vout = unfolding(cols, fs_out);
+    const View vUt = transposed(row_major(Ui.ld));
+    const View vU = row_major(Ui.ld);
+
+    // C = U^T Z (eq:first_resid / eq:project_further, projection part)
+    double* bn = nullptr;
+    if (i == 0) {
+      CKS(ensure(bnorm, (size_t)Ncol * sizeof(double)));
+      bn = as<double>(bnorm);
+    }
+    if (zin_is_input) {
+      CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
+                                 vUt, (const TIn*)zin, vz, 0.0, (const TIn*)nullptr, View(), out, vout,
+                                 0, nullptr, bn)));
+    } else {
+      CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0,
+                                       Ui.p, vUt, (const double*)zin, vz, 0.0, (const double*)nullptr,
+                                       View(), out, vout, 0, nullptr, bn)));
+    }
+
+    const double occupancy = rows > 0 ? (double)r / (double)rows : 1.0;
+    const bool occ_skip = use_occ && occupancy >= tau;
+    int64_t rR = 0;
+    double rho2 = std::numeric_limits<double>::quiet_NaN(), tail2 = 0.0;
+    double margin = std::numeric_limits<double>::infinity();
+
+    if (i == 0 && tol2 < 0) {
+      CKS(ensure(fy2, (size_t)N * sizeof(double)));
+      CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, as<double>(fy2)));
+      CK(total_sum(st, as<double>(fy2), N, as<double>(scal) + 2));
+    }
+
+    if (!occ_skip) {
+      // R = Z - U C with per-column energies (eq:first_resid, eq:ithresidual)
+      const int32_t MB = gemm_row_blocks((int32_t)rows);
+      CKS(ensure(colpart, (size_t)MB * Ncol * sizeof(double)));
+      CKS(ensure(fres, (size_t)N * sizeof(double)));
+      const bool small = rows * Ncol <= ((int64_t)1 << 22);
+      CKS(ensure(rbuf, (size_t)std::max<int64_t>(1, rows * Ncol) * sizeof(double)));
+      const View vr = unfolding(cols, rows * cols);
+      double* rout = small ? as<double>(rbuf) : nullptr;
+      if (zin_is_input) {
+        CK((gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r, (int32_t)std::max<int64_t>(r, 1),
+                                      -1.0, Ui.p, vU, out, vout, 1.0, (const TIn*)zin, vz, rout, vr, 0,
+                                      as<double>(colpart), nullptr)));
+      } else {
+        CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
+                                         (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, vU, out, vout, 1.0,
+                                         (const double*)zin, vz, rout, vr, 0, as<double>(colpart), nullptr)));
+      }
+      CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
+      CK(total_sum(st, as<double>(fres), N, as<double>(scal)));
+      CKS(sync_scalars(4));
+      if (i == 0 && tol2 < 0) {
+        const double ny2 = hs[2];
+        if (hs[3] != 0.0 || !isfinite(ny2)) return TTICE_EINVAL;
+        if (info) info->norm_y2 = ny2;
+        const double tol = eps * sqrt(ny2) / sqrt((double)d);
+        tol2 = tol * tol;
+        if (info) info->eps_core = tol;
+      }
+      rho2 = hs[0];
+      if (hs[1] != 0.0 || !isfinite(rho2)) return TTICE_EINVAL;
+      tail2 = rho2;
+
+      if (rho2 > tol2) {
+        if (!small) {
+          CK((zin_is_input
+                  ? gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
+                                              (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, vU, out, vout, 1.0,
+                                              (const TIn*)zin, vz, as<double>(rbuf), vr, 0, nullptr, nullptr)
+                  : gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
+                                                 (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, vU, out, vout,
+                                                 1.0, (const double*)zin, vz, as<double>(rbuf), vr, 0, nullptr,
+                                                 nullptr)));
+        }
+        // Truncated SVD of R_cat = [R(1) ... R(N)] (eq:svdfirst) via the
+        // eigendecomposition of its Gram matrix: left (rows x rows) when
+        // rows <= N*cols, else right (N*cols x N*cols).
+        const bool left = rows <= Ncol;
+        const int64_t m = left ? rows : Ncol;
+        const int64_t K = left ? Ncol : rows;
+        const View vR = vr;                   // rows x Ncol
+        const View vRt = transposed(vr);      // Ncol x rows
+        const int32_t kchunk = gram_kchunk((int32_t)m, K);
+        const int64_t Sg = (K + kchunk - 1) / kchunk;
+        const int64_t npad = m + (m & 1);
+        CKS(ensure(gpart, (size_t)Sg * m * m * sizeof(double)));
+        CKS(ensure(gram, (size_t)2 * npad * npad * sizeof(double)));
+        CKS(ensure(V, (size_t)2 * npad * npad * sizeof(double)));
+        CKS(ensure(w, (size_t)m * sizeof(double)));
+        CKS(ensure(order, (size_t)m * sizeof(int32_t)));
+        CKS(ensure(lam, (size_t)m * sizeof(double)));
+        CKS(ensure(tail, (size_t)(m + 1) * sizeof(double)));
+        CKS(ensure(sweeps, 16));
+        CK((gemm<double, double, double>(st, (int32_t)m, (int32_t)m, (int32_t)K, kchunk, 1.0, as<double>(rbuf),
+                                         left ? vR : vRt, as<double>(rbuf), left ? vRt : vR, 0.0,
+                                         (const double*)nullptr, View(), as<double>(gpart), row_major(m),
+                                         m * m, nullptr, nullptr)));
+        CK(gram_reduce(st, as<double>(gpart), (int32_t)Sg, (int32_t)m, as<double>(gram)));
+        CK(sym_eig(st, (int32_t)m, as<double>(gram), as<double>(V), as<double>(w), as<int32_t>(sweeps)));
+        const int64_t cap = rows - r;
+        CK(select_rank(st, (int32_t)m, as<double>(w), tol2, cap, as<int32_t>(order), as<double>(lam),
+                       as<double>(tail), as<double>(scal)));
+        CKS(sync_scalars(4));
+#ifdef TTICE_EMU_DEBUG
+        {
+          std::vector<double> hw(m);
+          hipMemcpy(hw.data(), w.p, m * 8, hipMemcpyDeviceToHost);
+          fprintf(stderr, "level %d rows %ld Ncol %ld left %d m %ld tol2 %g rR %g w:", i, (long)rows, (long)Ncol, (int)left, (long)m, tol2, hs[0]);
+          for (int64_t q = 0; q < m && q < 20; ++q) fprintf(stderr, " %g", hw[q]);
+          std::vector<double> hg(m * m);
+          fprintf(stderr, "\n");
+        }
+#endif
+        if (hs[3] != 0.0) return TTICE_EDEVICE;
+        rR = (int64_t)hs[0];
+        tail2 = hs[1];
+        margin = hs[2];
+        if (rR > 0) {
+          CKS(ensure(W, (size_t)rows * rR * sizeof(double)));
+          CKS(ensure(W2, (size_t)rows * rR * sizeof(double)));
+          double* Wp = as<double>(W);
+          double* W2p = as<double>(W2);
+          const View vW = row_major(rR);
+          if (left) {
+            CK(gather_columns(st, (int32_t)rows, (int32_t)rR, as<double>(V), (int32_t)m, as<int32_t>(order),
+                              as<double>(lam), false, Wp));
+          } else {
+            // U_R = R V_r Sigma_r^{-1}
+            CKS(ensure(T, (size_t)Ncol * rR * sizeof(double)));
+            CK(gather_columns(st, (int32_t)Ncol, (int32_t)rR, as<double>(V), (int32_t)m, as<int32_t>(order),
+                              as<double>(lam), true, as<double>(T)));
+            CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)rR, (int32_t)Ncol, (int32_t)Ncol, 1.0,
+                                             as<double>(rbuf), vR, as<double>(T), vW, 0.0,
+                                             (const double*)nullptr, View(), Wp, vW, 0, nullptr, nullptr)));
+          }
+          // Re-orthogonalise against U (two classical Gram-Schmidt passes)
+          if (r > 0) {
+            CKS(ensure(T, (size_t)std::max<int64_t>(r * rR, Ncol * rR) * sizeof(double)));
+            for (int pass = 0; pass < 2; ++pass) {
+              CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)rR, (int32_t)rows, (int32_t)rows, 1.0,
+                                               Ui.p, vUt, Wp, vW, 0.0, (const double*)nullptr, View(),
+                                               as<double>(T), vW, 0, nullptr, nullptr)));
+              CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)rR, (int32_t)r, (int32_t)r, -1.0,
+                                               Ui.p, vU, as<double>(T), vW, 1.0, Wp, vW, Wp, vW, 0, nullptr,
+                                               nullptr)));
+            }
+          }
+          // ... and among themselves: two Newton-Schulz steps towards the
+          // orthonormal polar factor, W <- W (3I - W^T W) / 2
+          CKS(ensure(S, (size_t)rR * rR * sizeof(double)));
+          for (int pass = 0; pass < 2; ++pass) {
+            CK((gemm<double, double, double>(st, (int32_t)rR, (int32_t)rR, (int32_t)rows, (int32_t)rows, 1.0, Wp,
+                                             transposed(vW), Wp, vW, 0.0, (const double*)nullptr, View(),
+                                             as<double>(S), vW, 0, nullptr, nullptr)));
+            CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)rR, (int32_t)rR, (int32_t)rR, -0.5, Wp,
+                                             vW, as<double>(S), vW, 1.5, Wp, vW, W2p, vW, 0, nullptr,
+                                             nullptr)));
+            std::swap(Wp, W2p);
+          }
+          CK(sign_fix(st, (int32_t)rows, (int32_t)rR, Wp, rR));
+
+          // eq:coreexpansion: U_i <- [U_i^pad, U_R]
+          CKS(grow_core(Ui, rows, r + rR, rows, r));
+          CK(copy2d(st, rows, rR, Wp, rR, Ui.p + r, Ui.ld));
+          // eq:ukpad: zero rows for the new rank slices of the next core
+          if (!last) {
+            Core& Un = U[i + 1];
+            const int64_t nrow_old = rk_pend[i + 1] * dims[i + 1];
+            const int64_t nrow_new = (rk_pend[i + 1] + rR) * dims[i + 1];
+            CKS(grow_core(Un, nrow_new, std::max<int64_t>(rk_pend[i + 2], 1), nrow_old, rk_pend[i + 2]));
+            CK(zero2d(st, nrow_new - nrow_old, Un.ld, Un.p + nrow_old * Un.ld, Un.ld));
+          } else {
+            // last core: new entries of the stored tensors' columns are zero
+            if (!last_out) {
+              CKS(grow_core(Gt, n_total + N, r + rR, n_total + N, r));
+              out = Gt.p + n_total * Gt.ld;
+              fs_out = Gt.ld;
+              CK(zero2d(st, n_total, rR, Gt.p + r, Gt.ld));
+            } else if (r + rR > last_ld) {
+              return TTICE_EDEVICE;  // caller sized last_out for the maximum rank
+            }
+          }
+          // New rows of the next level's data (eq:project_further with the
+          // appended directions): U_R^T Z below C.
+          // (U_i may have been reallocated with a new leading dimension)
+          const View vout2 = unfolding(cols, fs_out);
+          const View vUt2 = transposed(row_major(Ui.ld));
+          if (zin_is_input) {
+            CK((gemm<TIn, TIn, double>(st, (int32_t)rR, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0,
+                                       Ui.p + r, vUt2, (const TIn*)zin, vz, 0.0, (const TIn*)nullptr, View(),
+                                       out + r * cols, vout2, 0, nullptr, nullptr)));
+          } else {
+            CK((gemm<double, double, double>(st, (int32_t)rR, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0,
+                                             Ui.p + r, vUt2, (const double*)zin, vz, 0.0,
+                                             (const double*)nullptr, View(), out + r * cols, vout2, 0,
+                                             nullptr, nullptr)));
+          }
+          rk_pend[i + 1] = r + rR;
+        }
+      }
+    }
+    if (info) {
+      info->r_new[i] = rR;
+      info->rho2[i] = rho2;
+      info->tail2[i] = occ_skip ? 0.0 : tail2;
+      info->margin[i] = margin;
+    }
+    zin = out;
+    zin_is_input = false;
+  }
+  return TTICE_OK;
+}
+
+// Push N frames through the cores with ranks rks (no update): coefficients
+// into coef_out (row b = frame b, stride coef_ld), and optionally per-frame
+// residual energy sum_i ||R_i(b)||^2 (telescoping identity of the chain) and
+// per-frame ||Y(b)||^2.
+template <typename TIn>
+int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, double* coef_out,
+                               int64_t coef_ld, double* err2_out, double* y2_out, int* nonfinite) {
+  hipStream_t st = stream;
+  const void* zin = zin0;
+  bool zin_is_input = true;
+  if (err2_out) CK(hipMemsetAsync(err2_out, 0, (size_t)N * sizeof(double), st));
+  for (int i = 0; i < d; ++i) {
+    const int64_t rows = rks[i] * dims[i];
+    const int64_t cols = this->cols(i);
+    const int64_t r = rks[i + 1];
+    const int64_t Ncol = N * cols;
+    Core& Ui = U[i];
+    const bool last = (i == d - 1);
+    const View vz = unfolding(cols, P);
+    double* out = last ? coef_out : as<double>(z[i % 2]);
+    const int64_t fs_out = last ? coef_ld : P;
+    const View vout = unfolding(cols, fs_out);
+    double* bn = nullptr;
+    if (i == 0 && y2_out) {
+      CKS(ensure(bnorm, (size_t)Ncol * sizeof(double)));
+      bn = as<double>(bnorm);
+    }
+    if (zin_is_input)
+      CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
+                                 transposed(row_major(Ui.ld)), (const TIn*)zin, vz, 0.0, (const TIn*)nullptr,
+                                 View(), out, vout, 0, nullptr, bn)));
+    else
+      CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
+                                       transposed(row_major(Ui.ld)), (const double*)zin, vz, 0.0,
+                                       (const double*)nullptr, View(), out, vout, 0, nullptr, bn)));
+    if (bn) CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, y2_out));
+    if (err2_out) {
+      const int32_t MB = gemm_row_blocks((int32_t)rows);
+      CKS(ensure(colpart, (size_t)MB * Ncol * sizeof(double)));
+      CKS(ensure(fres, (size_t)N * sizeof(double)));
+      if (zin_is_input)
+        CK((gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
+                                      (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out, vout,
+                                      1.0, (const TIn*)zin, vz, (double*)nullptr, View(), 0,
+                                      as<double>(colpart), nullptr)));
+      else
+        CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
+                                         (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out,
+                                         vout, 1.0, (const double*)zin, vz, (double*)nullptr, View(), 0,
+                                         as<double>(colpart), nullptr)));
+      CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
+      CK(accumulate(st, err2_out, as<double>(fres), N));
+    }
+    zin = out;
+    zin_is_input = false;
+  }
+  if (nonfinite && y2_out) {
+    CK(total_sum(st, y2_out, N, as<double>(scal) + 2));
+    CKS(sync_scalars(4));
+    *nonfinite = (hs[3] != 0.0 || !isfinite(hs[2])) ? 1 : 0;
+  }
+  return TTICE_OK;
+}
+
+template <typename TIn>
+int ttice_state::update_impl(const TIn* batch, int64_t N, ttice_update_info* info) {
+  hipStream_t st = stream;
+  CKS(ensure(z[0], (size_t)N * P * sizeof(double)));
+  CKS(ensure(z[1], (size_t)N * P * sizeof(double)));
+  CKS(ensure(scal, 64 * sizeof(double)));
+  CKS(grow_core(Gt, n_total + N, std::max<int64_t>(rk[d], 1), n_total, rk[d]));
+
+  int64_t rkp[TTICE_MAX_D + 1];
+  for (int i = 0; i <= d; ++i) rkp[i] = rk[i];
+
+  if (algo == TTICE_ALG_PLAIN) {
+    if (info) info->eps_upd = eps;
+    CKS(core_loop<TIn>(batch, N, nullptr, -1.0, rkp, info, false, nullptr, 0));
+    if (info) {
+      double a = 0.0;
+      for (int i = 0; i < d; ++i) a += info->tail2[i];
+      info->achieved2 = a;
+    }
+  } else {
+    // Algorithm 2: relative errors with the existing cores (eq:relerror)
+    CKS(ensure(e2acc, (size_t)N * sizeof(double)));
+    CKS(ensure(fy2, (size_t)N * sizeof(double)));
+    CKS(ensure(dlist, (size_t)N * sizeof(int32_t)));
+    int nonfinite = 0;
+    CKS(chain_project<TIn>(batch, N, rkp, Gt.p + n_total * Gt.ld, Gt.ld, as<double>(e2acc), as<double>(fy2),
+                           &nonfinite));
+    if (nonfinite) return TTICE_EINVAL;
+    CK(star_decide(st, (int32_t)N, as<double>(e2acc), as<double>(fy2), eps, as<int32_t>(dlist),
+                   as<double>(scal)));
+    CKS(sync_scalars(6));
+    const double mean_rel = hs[0], batch_rel = hs[1], sdc = hs[2], nd2 = hs[3];
+    const int64_t nD = (int64_t)hs[4];
+    const double ny2 = hs[5];
+    if (info) {
+      info->norm_y2 = ny2;
+      info->achieved2 = -1.0;
+      for (int i = 0; i < d; ++i) {
+        info->r_new[i] = 0;
+        info->rho2[i] = std::numeric_limits<double>::quiet_NaN();
+        info->tail2[i] = 0.0;
+        info->margin[i] = std::numeric_limits<double>::infinity();
+      }
+    }
+    const bool skip = (skip_rule == TTICE_SKIP_MEAN) ? (mean_rel <= eps) : (batch_rel <= eps);
+    if (skip || nD == 0) {
+      // eq:appendupdate: the coefficients already sit in the last core
+      if (info) {
+        info->skipped = 1;
+        info->used = 0;
+        info->eps_upd = eps;
+        info->eps_core = 0.0;
+      }
+    } else {
+      // eq:subselectheuristic, eq:epsilonmodification
+      const double num = std::max(0.0, eps * eps * ny2 - sdc);
+      const double eps_upd = sqrt(num / nd2);
+      const double tol = eps_upd * sqrt(nd2) / sqrt((double)d);
+      if (info) {
+        info->used = nD;
+        info->eps_upd = eps_upd;
+        info->eps_core = tol;
+      }
+      // the subset's own last-level coefficients are not kept: they go to a
+      // work buffer (frame stride prod(dims) bounds any rank r_d)
+      CKS(core_loop<TIn>(batch, nD, as<int32_t>(dlist), tol, rkp, info, true,
+                         as<double>(z[(d - 1) % 2]), P));
+      // pad the last core for the appended directions of core d (zeros for
+      // the stored tensors), then re-project the whole batch (Alg. 2 project)
+      const int64_t r_old = rk[d], r_new = rkp[d];
+      CKS(grow_core(Gt, n_total + N, std::max<int64_t>(r_new, 1), n_total, r_old));
+      if (r_new > r_old) CK(zero2d(st, n_total, r_new - r_old, Gt.p + r_old, Gt.ld));
+      CKS(chain_project<TIn>(batch, N, rkp, Gt.p + n_total * Gt.ld, Gt.ld, nullptr, nullptr, nullptr));
+    }
+  }
+  CK(hipStreamSynchronize(st));
+  // commit
+  for (int i = 0; i <= d; ++i) rk[i] = rkp[i];
+  n_total += N;
+  return TTICE_OK;
+}
+
+template <typename TD>
+int ttice_state::reconstruct_impl(int64_t first, int64_t count, TD* out) {
+  hipStream_t st = stream;
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(count, ((int64_t)1 << 26) / P));
+  CKS(ensure(z[0], (size_t)chunk * P * sizeof(double)));
+  CKS(ensure(z[1], (size_t)chunk * P * sizeof(double)));
+  for (int64_t f0 = 0; f0 < count; f0 += chunk) {
+    const int64_t cnt = std::min(chunk, count - f0);
+    // level d-1 input: the last-core rows of the chosen tensors
+    View vx;
+    vx.rs = 1;
+    vx.cs = Gt.ld;
+    const double* xin = Gt.p + (first + f0) * Gt.ld;
+    for (int i = d - 1; i >= 0; --i) {
+      const int64_t rows = rk[i] * dims[i];
+      const int64_t cols = this->cols(i);
+      const int64_t r = rk[i + 1];
+      const int64_t Ncol = cnt * cols;
+      if (i == 0) {
+        TD* o = out + f0 * P;
+        CK((gemm<double, double, TD>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r, (int32_t)std::max<int64_t>(r, 1),
+                                     1.0, U[i].p, row_major(U[i].ld), xin, vx, 0.0, (const double*)nullptr,
+                                     View(), o, unfolding(cols, P), 0, nullptr, nullptr)));
+      } else {
+        double* o = as<double>(z[i % 2]);
+        CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
+                                         (int32_t)std::max<int64_t>(r, 1), 1.0, U[i].p, row_major(U[i].ld), xin,
+                                         vx, 0.0, (const double*)nullptr, View(), o, unfolding(cols, P), 0,
+                                         nullptr, nullptr)));
+        xin = o;
+        // next level reads per frame (r_i x cols_{i-1}) = (rk[i]) x (dims[i]*cols)
+        vx = unfolding(dims[i] * cols, P);
+      }
+    }
+  }
+  CK(hipStreamSynchronize(st));
+  return TTICE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI (the only symbols the library exports)
+// ---------------------------------------------------------------------------
+#pragma GCC visibility push(default)
+extern "C" {
+
+int ttice_create(int32_t d, const int64_t* dims, double eps, ttice_state** out) {
+  if (!out) return TTICE_EINVAL;
+  *out = nullptr;
+  if (d < 1 || d > TTICE_MAX_D || !dims) return TTICE_EINVAL;
+  if (!(eps > 0.0 && eps < 1.0)) return TTICE_EINVAL;
+  int64_t P = 1;
+  for (int i = 0; i < d; ++i) {
+    if (dims[i] < 1) return TTICE_EINVAL;
+    P *= dims[i];
+    if (P >= ((int64_t)1 << 31)) return TTICE_EINVAL;
+  }
+  ttice_state* s = new (std::nothrow) ttice_state();
+  if (!s) return TTICE_ENOMEM;
+  s->d = d;
+  for (int i = 0; i < d; ++i) s->dims[i] = dims[i];
+  s->P = P;
+  s->eps = eps;
+  s->rk[0] = 1;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return TTICE_EDEVICE;
+  }
+  if (hipHostMalloc((void**)&s->hs, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    s->hs = nullptr;
+    delete s;
+    return TTICE_ENOMEM;
+  }
+  // U_1 has n_1 rows from the start (r_0 = 1); others start with 0 rows.
+  if (s->grow_core(s->U[0], dims[0], 1, 0, 0) != TTICE_OK) {
+    delete s;
+    return TTICE_ENOMEM;
+  }
+  *out = s;
+  return TTICE_OK;
+}
+
+int ttice_set_option(ttice_state* st, int32_t key, const void* val) {
+  if (!st) return TTICE_ESTATE;
+  if (!val) return TTICE_EINVAL;
+  switch (key) {
+    case TTICE_OPT_PREC: {
+      const int32_t v = *(const int32_t*)val;
+      if (v != TTICE_PREC_FP64 && v != TTICE_PREC_FP32 && v != TTICE_PREC_BF16X3) return TTICE_EINVAL;
+      st->prec = v;
+      return TTICE_OK;
+    }
+    case TTICE_OPT_ALGO: {
+      const int32_t v = *(const int32_t*)val;
+      if (v != TTICE_ALG_PLAIN && v != TTICE_ALG_STAR) return TTICE_EINVAL;
+      st->algo = v;
+      return TTICE_OK;
+    }
+    case TTICE_OPT_SKIP_RULE: {
+      const int32_t v = *(const int32_t*)val;
+      if (v != TTICE_SKIP_MEAN && v != TTICE_SKIP_BATCH) return TTICE_EINVAL;
+      st->skip_rule = v;
+      return TTICE_OK;
+    }
+    case TTICE_OPT_TAU: {
+      const double v = *(const double*)val;
+      if (!(v > 0.0)) return TTICE_EINVAL;
+      st->tau = v;
+      return TTICE_OK;
+    }
+    case TTICE_OPT_STREAM:
+      st->stream = *(const hipStream_t*)val;
+      return TTICE_OK;
+    default:
+      return TTICE_EINVAL;
+  }
+}
+
+int ttice_update(ttice_state* st, const void* batch, int64_t n, int32_t dtype, ttice_update_info* info) {
+  if (!st) return TTICE_ESTATE;
+  if (n < 0 || (n > 0 && !batch)) return TTICE_EINVAL;
+  if (dtype != TTICE_F32 && dtype != TTICE_F64) return TTICE_EINVAL;
+  if (n * st->P >= ((int64_t)1 << 31)) return TTICE_EINVAL;  // 32-bit column indices
+  ttice_update_info local;
+  ttice_update_info* inf = info ? info : &local;
+  memset(inf, 0, sizeof(*inf));
+  inf->d = st->d;
+  inf->n = n;
+  inf->used = n;
+  inf->eps_upd = st->eps;
+  int rc = TTICE_OK;
+  if (n > 0) {
+    if (hipSetDevice(st->device) != hipSuccess) return TTICE_EDEVICE;
+    rc = (dtype == TTICE_F32) ? st->update_impl<float>((const float*)batch, n, inf)
+                              : st->update_impl<double>((const double*)batch, n, inf);
+    if (rc != TTICE_OK) {
+      (void)hipStreamSynchronize(st->stream);
+      (void)hipGetLastError();
+    }
+  }
+  inf->n_total = st->n_total;
+  for (int i = 0; i <= st->d; ++i) inf->ranks[i] = st->rk[i];
+  inf->ranks[st->d + 1] = 1;
+  return rc;
+}
+
+int ttice_reconstruct(ttice_state* st, int64_t first, int64_t count, void* out, int32_t dtype) {
+  if (!st) return TTICE_ESTATE;
+  if (first < 0 || count < 0 || first + count > st->n_total) return TTICE_EINVAL;
+  if (dtype != TTICE_F32 && dtype != TTICE_F64) return TTICE_EINVAL;
+  if (count == 0) return TTICE_OK;
+  if (!out) return TTICE_EINVAL;
+  if (hipSetDevice(st->device) != hipSuccess) return TTICE_EDEVICE;
+  int rc = (dtype == TTICE_F32) ? st->reconstruct_impl<float>(first, count, (float*)out)
+                                : st->reconstruct_impl<double>(first, count, (double*)out);
+  if (rc != TTICE_OK) (void)hipGetLastError();
+  return rc;
+}
+
+int ttice_project(ttice_state* st, const void* batch, int64_t n, int32_t dtype, double* coef,
+                  double* err2, double* y2) {
+  if (!st) return TTICE_ESTATE;
+  if (n < 0 || (n > 0 && (!batch || !coef))) return TTICE_EINVAL;
+  if (dtype != TTICE_F32 && dtype != TTICE_F64) return TTICE_EINVAL;
+  if (n == 0) return TTICE_OK;
+  if (hipSetDevice(st->device) != hipSuccess) return TTICE_EDEVICE;
+  int rc = ensure(st->z[0], (size_t)n * st->P * sizeof(double));
+  if (rc == TTICE_OK) rc = ensure(st->z[1], (size_t)n * st->P * sizeof(double));
+  if (rc == TTICE_OK) rc = ensure(st->scal, 64 * sizeof(double));
+  int nonfinite = 0;
+  if (rc == TTICE_OK) {
+    const int64_t rd = std::max<int64_t>(st->rk[st->d], 1);
+    rc = (dtype == TTICE_F32)
+             ? st->chain_project<float>((const float*)batch, n, st->rk, coef, rd, err2, y2, y2 ? &nonfinite : nullptr)
+             : st->chain_project<double>((const double*)batch, n, st->rk, coef, rd, err2, y2,
+                                         y2 ? &nonfinite : nullptr);
+  }
+  if (rc == TTICE_OK && hipStreamSynchronize(st->stream) != hipSuccess) rc = TTICE_EDEVICE;
+  if (rc == TTICE_OK && nonfinite) rc = TTICE_EINVAL;
+  if (rc != TTICE_OK) (void)hipGetLastError();
+  return rc;
+}
+
+int ttice_ranks(const ttice_state* st, int64_t* ranks, int64_t* n_total) {
+  if (!st) return TTICE_ESTATE;
+  if (!ranks) return TTICE_EINVAL;
+  for (int i = 0; i <= st->d; ++i) ranks[i] = st->rk[i];
+  ranks[st->d + 1] = 1;
+  if (n_total) *n_total = st->n_total;
+  return TTICE_OK;
+}
+
+int ttice_get_core(ttice_state* st, int32_t i, double* out, int64_t* rows, int64_t* cols) {
+  if (!st) return TTICE_ESTATE;
+  if (i < 0 || i > st->d) return TTICE_EINVAL;
+  int64_t r, c;
+  const Core* core;
+  if (i < st->d) {
+    r = st->rk[i] * st->dims[i];
+    c = st->rk[i + 1];
+    core = &st->U[i];
+  } else {
+    r = st->n_total;
+    c = st->rk[st->d];
+    core = &st->Gt;
+  }
+  if (rows) *rows = r;
+  if (cols) *cols = c;
+  if (!out || r == 0 || c == 0) return TTICE_OK;
+  if (hipSetDevice(st->device) != hipSuccess) return TTICE_EDEVICE;
+  hipError_t e = hipMemcpy2DAsync(out, c * sizeof(double), core->p, core->ld * sizeof(double),
+                                  c * sizeof(double), r, hipMemcpyDeviceToDevice, st->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  return status_of(e);
+}
+
+void ttice_destroy(ttice_state* st) {
+  if (!st) return;
+  (void)hipSetDevice(st->device);
+  (void)hipStreamSynchronize(st->stream);
+  delete st;
+}
+
+const char* ttice_strerror(int code) {
+  switch (code) {
+    case TTICE_OK: return "ok";
+    case TTICE_EINVAL: return "invalid argument or non-finite input";
+    case TTICE_ENOMEM: return "out of memory";
+    case TTICE_EDEVICE: return "HIP device or launch error";
+    case TTICE_ESTATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"
+#pragma GCC visibility pop

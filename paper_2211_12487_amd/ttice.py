@@ -1,0 +1,225 @@
+"""Thin ctypes binding of libttice.so (include/ttice.h).
+
+Argument marshalling only: device buffers are torch CUDA tensors whose
+data_ptr() is handed to the C ABI; every step of TT-ICE runs in the
+library's HIP kernels.  There is no CPU fallback: if the library is missing
+the import of :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import List, Optional, Sequence
+
+import torch  # loads the HIP runtime the library binds to (same soname)
+
+__all__ = ["lib", "TTICE", "TTICEError", "UpdateInfo", "library_path", "EXPORTS"]
+
+TTICE_MAX_D = 16
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+ALGO = {"plain": 0, "star": 1}
+SKIP = {"mean": 0, "batch": 1}
+OPT_PREC, OPT_ALGO, OPT_SKIP_RULE, OPT_TAU, OPT_STREAM = 1, 2, 3, 4, 5
+F32, F64 = 0, 1
+
+EXPORTS = [
+    "ttice_create",
+    "ttice_set_option",
+    "ttice_update",
+    "ttice_reconstruct",
+    "ttice_project",
+    "ttice_ranks",
+    "ttice_get_core",
+    "ttice_destroy",
+    "ttice_strerror",
+]
+
+
+class UpdateInfo(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32),
+        ("skipped", ctypes.c_int32),
+        ("n", ctypes.c_int64),
+        ("used", ctypes.c_int64),
+        ("n_total", ctypes.c_int64),
+        ("norm_y2", ctypes.c_double),
+        ("eps_core", ctypes.c_double),
+        ("eps_upd", ctypes.c_double),
+        ("ranks", ctypes.c_int64 * (TTICE_MAX_D + 2)),
+        ("r_new", ctypes.c_int64 * TTICE_MAX_D),
+        ("rho2", ctypes.c_double * TTICE_MAX_D),
+        ("tail2", ctypes.c_double * TTICE_MAX_D),
+        ("margin", ctypes.c_double * TTICE_MAX_D),
+        ("achieved2", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        d = self.d
+        return dict(
+            n=self.n, used=self.used, n_total=self.n_total, skipped=bool(self.skipped),
+            normY2=self.norm_y2, eps_core=self.eps_core, eps_upd=self.eps_upd,
+            ranks=list(self.ranks[: d + 2]), rR=list(self.r_new[:d]), rho2=list(self.rho2[:d]),
+            tail2=list(self.tail2[:d]), margin=list(self.margin[:d]),
+            achieved2=(self.achieved2 if self.achieved2 >= 0 else None),
+        )
+
+
+class TTICEError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {_strerror(code)} ({code})")
+        self.code = code
+
+
+_LIB = None
+
+
+def library_path() -> str:
+    return os.environ.get("TTICE_LIBRARY", os.path.join(_HERE, "libttice.so"))
+
+
+def lib():
+    """Load libttice.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    L.ttice_create.argtypes = [c_i32, ctypes.POINTER(c_i64), c_dbl, ctypes.POINTER(c_vp)]
+    L.ttice_set_option.argtypes = [c_vp, c_i32, c_vp]
+    L.ttice_update.argtypes = [c_vp, c_vp, c_i64, c_i32, ctypes.POINTER(UpdateInfo)]
+    L.ttice_reconstruct.argtypes = [c_vp, c_i64, c_i64, c_vp, c_i32]
+    L.ttice_project.argtypes = [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp]
+    L.ttice_ranks.argtypes = [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
+    L.ttice_get_core.argtypes = [c_vp, c_i32, c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
+    L.ttice_destroy.argtypes = [c_vp]
+    L.ttice_destroy.restype = None
+    L.ttice_strerror.argtypes = [ctypes.c_int]
+    L.ttice_strerror.restype = ctypes.c_char_p
+    for name in ("ttice_create", "ttice_set_option", "ttice_update", "ttice_reconstruct",
+                 "ttice_project", "ttice_ranks", "ttice_get_core"):
+        getattr(L, name).restype = ctypes.c_int
+    _LIB = L
+    return L
+
+
+def _strerror(code: int) -> str:
+    try:
+        return lib().ttice_strerror(code).decode()
+    except Exception:  # pragma: no cover
+        return "unknown"
+
+
+def _check(code: int, what: str) -> None:
+    if code != 0:
+        raise TTICEError(code, what)
+
+
+def _dtype_code(t: torch.dtype) -> int:
+    if t == torch.float32:
+        return F32
+    if t == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {t}")
+
+
+class TTICE:
+    """One TT-ICE accumulation living on the current HIP device."""
+
+    def __init__(self, dims: Sequence[int], eps: float, prec: str = "fp64", algo: str = "plain",
+                 skip_rule: str = "mean", tau: float = 1.0, stream: Optional[torch.cuda.Stream] = None):
+        L = lib()
+        self.dims = tuple(int(n) for n in dims)
+        self.d = len(self.dims)
+        self.eps = float(eps)
+        arr = (ctypes.c_int64 * max(self.d, 1))(*self.dims)
+        h = ctypes.c_void_p()
+        _check(L.ttice_create(self.d, arr, self.eps, ctypes.byref(h)), "ttice_create")
+        self._h = h
+        self.stream = stream
+        self.set_option(OPT_PREC, ctypes.c_int32(PREC[prec]))
+        self.set_option(OPT_ALGO, ctypes.c_int32(ALGO[algo]))
+        self.set_option(OPT_SKIP_RULE, ctypes.c_int32(SKIP[skip_rule]))
+        self.set_option(OPT_TAU, ctypes.c_double(tau))
+        if stream is not None:
+            self.set_option(OPT_STREAM, ctypes.c_void_p(stream.cuda_stream))
+
+    def set_option(self, key: int, value) -> None:
+        _check(lib().ttice_set_option(self._h, key, ctypes.byref(value)), "ttice_set_option")
+
+    def _batch(self, Y: torch.Tensor) -> torch.Tensor:
+        if not Y.is_cuda:
+            raise ValueError("batch must be a device tensor")
+        if tuple(Y.shape) == self.dims:
+            Y = Y.unsqueeze(0)
+        if tuple(Y.shape[1:]) != self.dims:
+            raise ValueError(f"batch shape {tuple(Y.shape)} does not match dims {self.dims}")
+        return Y.contiguous()
+
+    def update(self, Y: torch.Tensor) -> dict:
+        Y = self._batch(Y)
+        info = UpdateInfo()
+        _check(lib().ttice_update(self._h, ctypes.c_void_p(Y.data_ptr()), Y.shape[0],
+                                  _dtype_code(Y.dtype), ctypes.byref(info)), "ttice_update")
+        return info.as_dict()
+
+    def project(self, Y: torch.Tensor):
+        """(coef [n, r_d], err2 [n], y2 [n]) under the current cores (no update)."""
+        Y = self._batch(Y)
+        n = Y.shape[0]
+        rd = self.ranks()[self.d]
+        coef = torch.empty((n, max(rd, 1)), dtype=torch.float64, device=Y.device)
+        err2 = torch.empty(n, dtype=torch.float64, device=Y.device)
+        y2 = torch.empty(n, dtype=torch.float64, device=Y.device)
+        _check(lib().ttice_project(self._h, ctypes.c_void_p(Y.data_ptr()), n, _dtype_code(Y.dtype),
+                                   ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(err2.data_ptr()),
+                                   ctypes.c_void_p(y2.data_ptr())), "ttice_project")
+        return coef[:, :rd], err2, y2
+
+    def reconstruct(self, first: int = 0, count: Optional[int] = None,
+                    dtype: torch.dtype = torch.float64, device=None) -> torch.Tensor:
+        if count is None:
+            count = self.n_total - first
+        out = torch.empty((count,) + self.dims, dtype=dtype,
+                          device=device if device is not None else torch.device("cuda"))
+        _check(lib().ttice_reconstruct(self._h, first, count, ctypes.c_void_p(out.data_ptr()),
+                                       _dtype_code(dtype)), "ttice_reconstruct")
+        return out
+
+    def ranks(self) -> List[int]:
+        r = (ctypes.c_int64 * (self.d + 2))()
+        n = ctypes.c_int64()
+        _check(lib().ttice_ranks(self._h, r, ctypes.byref(n)), "ttice_ranks")
+        return list(r)
+
+    @property
+    def n_total(self) -> int:
+        r = (ctypes.c_int64 * (self.d + 2))()
+        n = ctypes.c_int64()
+        _check(lib().ttice_ranks(self._h, r, ctypes.byref(n)), "ttice_ranks")
+        return int(n.value)
+
+    def core(self, i: int) -> torch.Tensor:
+        """Core i (0..d-1: U_{i+1}, (r_i n_{i+1}) x r_{i+1}); i == d: last core transposed."""
+        rows, cols = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().ttice_get_core(self._h, i, None, ctypes.byref(rows), ctypes.byref(cols)), "ttice_get_core")
+        out = torch.zeros((rows.value, cols.value), dtype=torch.float64, device="cuda")
+        if out.numel():
+            _check(lib().ttice_get_core(self._h, i, ctypes.c_void_p(out.data_ptr()), None, None), "ttice_get_core")
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ttice_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,178 @@
+"""Parity cases run against the host-emulation build (tests only).
+
+Invoked by tests/test_emu.py in a subprocess that preloads the
+AddressSanitizer runtime: argv[1] = path of libttice_emu.so, argv[2:] =
+case names (default: all).  Exits non-zero on the first failure."""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, HERE)
+
+from emu_ttice import EmuError, EmuTTICE, load  # noqa: E402
+from oracle import TTICE as Oracle  # noqa: E402
+from paper_2211_12487_amd import synth  # noqa: E402
+
+L = None
+
+
+def sep(n, dims, batch, seed, terms=4, noise=1e-3, dtype=np.float64):
+    return list(synth.smooth_separable_stream(n, dims, terms, noise, batch, seed, dtype=dtype))
+
+
+def check_stream(g, o, batches, rtol=1e-10, label=""):
+    for k, Y in enumerate(batches):
+        gi = g.update(Y)
+        oi = o.update(Y.astype(np.float64))
+        assert gi["ranks"][1:-1] == oi["ranks"][1:-1], (label, k, gi["ranks"], oi["ranks"], oi["margin"])
+        if oi.get("achieved2") is not None and gi["achieved2"] is not None:
+            assert abs(gi["achieved2"] - oi["achieved2"]) <= 1e-6 * oi["achieved2"] + 1e-20, (label, k)
+    rg, ro = g.reconstruct(), o.reconstruct()
+    for b in range(ro.shape[0]):
+        rel = np.linalg.norm(rg[b] - ro[b]) / max(np.linalg.norm(ro[b]), 1e-300)
+        assert rel <= rtol, (label, b, rel)
+    for i in range(g.d):
+        U = g.core(i)
+        if U.shape[1]:
+            assert np.abs(U.T @ U - np.eye(U.shape[1])).max() <= 1e-12, (label, i)
+
+
+def case_separable():
+    dims, eps = (16, 16, 3), 0.05
+    check_stream(EmuTTICE(L, dims, eps), Oracle(dims, eps), sep(12, dims, 2, 0, terms=5), label="sep")
+
+
+def case_ragged_f32():
+    dims, eps = (37, 29, 5), 0.02
+    rng = np.random.default_rng(3)
+    sizes = [int(x) for x in rng.integers(1, 6, 5)]
+    flat = sep(sum(sizes), dims, 1, 4, terms=6, dtype=np.float32)
+    batches, k = [], 0
+    for s in sizes:
+        batches.append(np.concatenate(flat[k:k + s]))
+        k += s
+    check_stream(EmuTTICE(L, dims, eps), Oracle(dims, eps), batches, rtol=1e-9, label="ragged")
+
+
+def case_order4():
+    dims, eps = (9, 7, 11, 3), 0.03
+    check_stream(EmuTTICE(L, dims, eps), Oracle(dims, eps), sep(12, dims, 4, 5, terms=5), label="order4")
+
+
+def case_order1_order2():
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((70, 5))
+    batches = [(A @ rng.standard_normal((5, b))).T + 1e-3 * rng.standard_normal((b, 70)) for b in (50, 3, 9)]
+    check_stream(EmuTTICE(L, (70,), 0.05), Oracle((70,), 0.05), batches, label="order1")
+    check_stream(EmuTTICE(L, (40, 90), 0.05), Oracle((40, 90), 0.05), sep(12, (40, 90), 6, 7), label="order2")
+
+
+def case_star():
+    dims, eps = (12, 10, 6), 0.05
+    g, o = EmuTTICE(L, dims, eps, algo=1), Oracle(dims, eps, algo="star")
+    skipped = 0
+    rng = np.random.default_rng(8)
+    batches = [Y + 1e-3 * rng.standard_normal(Y.shape)
+               for Y in synth.tt_lowrank_stream(dims, (3, 4, 4), 40, 4, seed=8)]
+    for k, Y in enumerate(batches):
+        gi, oi = g.update(Y), o.update(Y)
+        assert gi["skipped"] == oi["skipped"] and gi["used"] == oi["used"], k
+        assert gi["ranks"][1:-1] == oi["ranks"][1:-1], (k, gi["ranks"], oi["ranks"])
+        skipped += gi["skipped"]
+    assert skipped > 0
+    rg, ro = g.reconstruct(), o.reconstruct()
+    assert np.abs(rg - ro).max() <= 1e-10 * np.abs(ro).max()
+
+
+def case_project():
+    dims, eps = (12, 10, 6), 0.05
+    g, o = EmuTTICE(L, dims, eps), Oracle(dims, eps)
+    for Y in sep(8, dims, 2, 9):
+        g.update(Y)
+        o.update(Y)
+    Yn = sep(5, dims, 5, 99)[0]
+    coef, err2, y2 = g.project(Yn)
+    oc, ot = o.project(Yn)
+    assert np.abs(coef - oc).max() <= 1e-10 * np.abs(oc).max()
+    brute = np.array([np.sum((Yn[b] - ot[b]) ** 2) for b in range(5)])
+    assert np.allclose(err2, brute, rtol=1e-8)
+
+
+def case_errors_and_degenerate():
+    dims, eps = (4, 3, 5), 0.1
+    g = EmuTTICE(L, dims, eps)
+    g.update(np.zeros((0,) + dims))
+    g.update(np.zeros((2,) + dims))
+    r, n = g.ranks()
+    assert r == [1, 0, 0, 0, 1] and n == 2
+    assert np.all(g.reconstruct() == 0)
+    Y = sep(3, dims, 3, 10)[0]
+    g.update(Y)
+    r0, n0 = g.ranks()
+    rec0 = g.reconstruct()
+    bad = Y.copy()
+    bad[1, 2, 1, 3] = np.nan
+    try:
+        g.update(bad)
+        raise AssertionError("NaN accepted")
+    except EmuError as e:
+        assert e.code == -1
+    assert g.ranks() == (r0, n0) and np.array_equal(g.reconstruct(), rec0)
+
+
+def case_alloc_failure_leaves_state():
+    """Failure injection: the k-th device allocation fails -> ENOMEM and the
+    state (ranks, stored tensors, reconstructions) is unchanged."""
+    dims, eps = (12, 10, 6), 0.02
+    data = sep(9, dims, 3, 11, terms=6) + sep(9, dims, 9, 12, terms=6)   # last increment is larger
+    ref = EmuTTICE(L, dims, eps)
+    for Y in data:
+        ref.update(Y)
+    hits = 0
+    for k in range(0, 12):
+        g = EmuTTICE(L, dims, eps)
+        for Y in data[:-1]:
+            g.update(Y)
+        r0, n0 = g.ranks()
+        rec0 = g.reconstruct()
+        L.hipemu_fail_alloc_after(k)
+        try:
+            g.update(data[-1])
+            ok = True
+        except EmuError as e:
+            assert e.code == -2, e.code
+            ok = False
+        finally:
+            L.hipemu_fail_alloc_after(-1)
+        if not ok:
+            hits += 1
+            assert g.ranks() == (r0, n0)
+            assert np.array_equal(g.reconstruct(), rec0)
+            g.update(data[-1])  # and it recovers
+        assert g.ranks() == ref.ranks()
+        assert np.allclose(g.reconstruct(), ref.reconstruct(), atol=1e-12)
+        g.close()
+    assert hits > 0
+
+
+def case_lowrank():
+    dims = (10, 15, 20)
+    g = EmuTTICE(L, dims, 1e-6)
+    for k, Y in enumerate(synth.tt_lowrank_stream(dims, (2, 3, 5), 7, 1, seed=7), start=1):
+        g.update(Y)
+        assert g.ranks()[0][1:-1] == [2, 3, min(k, 5)], (k, g.ranks())
+
+
+CASES = {k[5:]: v for k, v in globals().items() if k.startswith("case_")}
+
+if __name__ == "__main__":
+    L = load(sys.argv[1])
+    names = sys.argv[2:] or list(CASES)
+    for name in names:
+        print("emu case", name, flush=True)
+        CASES[name]()
+    print("emu cases ok", flush=True)

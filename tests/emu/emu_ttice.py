@@ -1,0 +1,129 @@
+"""ctypes wrapper of the host-emulation build of libttice (tests only).
+
+Same C ABI as the product library, but "device" pointers are host memory
+(NumPy arrays).  Import only in a process started with the AddressSanitizer
+runtime preloaded (see tests/test_emu.py)."""
+import ctypes
+import os
+
+import numpy as np
+
+TTICE_MAX_D = 16
+
+
+class UpdateInfo(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32), ("skipped", ctypes.c_int32), ("n", ctypes.c_int64),
+        ("used", ctypes.c_int64), ("n_total", ctypes.c_int64), ("norm_y2", ctypes.c_double),
+        ("eps_core", ctypes.c_double), ("eps_upd", ctypes.c_double),
+        ("ranks", ctypes.c_int64 * (TTICE_MAX_D + 2)), ("r_new", ctypes.c_int64 * TTICE_MAX_D),
+        ("rho2", ctypes.c_double * TTICE_MAX_D), ("tail2", ctypes.c_double * TTICE_MAX_D),
+        ("margin", ctypes.c_double * TTICE_MAX_D), ("achieved2", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        d = self.d
+        return dict(n=self.n, used=self.used, n_total=self.n_total, skipped=bool(self.skipped),
+                    normY2=self.norm_y2, eps_core=self.eps_core, eps_upd=self.eps_upd,
+                    ranks=list(self.ranks[: d + 2]), rR=list(self.r_new[:d]), rho2=list(self.rho2[:d]),
+                    tail2=list(self.tail2[:d]), margin=list(self.margin[:d]),
+                    achieved2=(self.achieved2 if self.achieved2 >= 0 else None))
+
+
+class EmuError(RuntimeError):
+    def __init__(self, code):
+        super().__init__(f"status {code}")
+        self.code = code
+
+
+def load(path):
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.ttice_create.argtypes = [i32, ctypes.POINTER(i64), dbl, ctypes.POINTER(vp)]
+    L.ttice_set_option.argtypes = [vp, i32, vp]
+    L.ttice_update.argtypes = [vp, vp, i64, i32, ctypes.POINTER(UpdateInfo)]
+    L.ttice_reconstruct.argtypes = [vp, i64, i64, vp, i32]
+    L.ttice_project.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+    L.ttice_ranks.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.ttice_get_core.argtypes = [vp, i32, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.ttice_destroy.argtypes = [vp]
+    L.ttice_destroy.restype = None
+    L.hipemu_fail_alloc_after.argtypes = [ctypes.c_longlong]
+    L.hipemu_fail_alloc_after.restype = None
+    return L
+
+
+class EmuTTICE:
+    def __init__(self, L, dims, eps, algo=0, prec=0, tau=None, skip_rule=None):
+        self.L = L
+        self.dims = tuple(dims)
+        self.d = len(dims)
+        h = ctypes.c_void_p()
+        arr = (ctypes.c_int64 * self.d)(*dims)
+        rc = L.ttice_create(self.d, arr, eps, ctypes.byref(h))
+        if rc:
+            raise EmuError(rc)
+        self.h = h
+        self._opt(2, ctypes.c_int32(algo))
+        self._opt(1, ctypes.c_int32(prec))
+        if tau is not None:
+            self._opt(4, ctypes.c_double(tau))
+        if skip_rule is not None:
+            self._opt(3, ctypes.c_int32(skip_rule))
+
+    def _opt(self, k, v):
+        rc = self.L.ttice_set_option(self.h, k, ctypes.byref(v))
+        if rc:
+            raise EmuError(rc)
+
+    def update(self, Y):
+        Y = np.ascontiguousarray(Y)
+        code = 1 if Y.dtype == np.float64 else 0
+        info = UpdateInfo()
+        rc = self.L.ttice_update(self.h, Y.ctypes.data_as(ctypes.c_void_p), Y.shape[0], code, ctypes.byref(info))
+        if rc:
+            raise EmuError(rc)
+        return info.as_dict()
+
+    def ranks(self):
+        r = (ctypes.c_int64 * (self.d + 2))()
+        n = ctypes.c_int64()
+        self.L.ttice_ranks(self.h, r, ctypes.byref(n))
+        return list(r), n.value
+
+    def reconstruct(self, first=0, count=None):
+        _, nt = self.ranks()
+        if count is None:
+            count = nt - first
+        out = np.zeros((count,) + self.dims)
+        rc = self.L.ttice_reconstruct(self.h, first, count, out.ctypes.data_as(ctypes.c_void_p), 1)
+        if rc:
+            raise EmuError(rc)
+        return out
+
+    def project(self, Y):
+        Y = np.ascontiguousarray(Y, dtype=np.float64)
+        r, _ = self.ranks()
+        n = Y.shape[0]
+        coef = np.zeros((n, max(r[self.d], 1)))
+        err2 = np.zeros(n)
+        y2 = np.zeros(n)
+        rc = self.L.ttice_project(self.h, Y.ctypes.data_as(ctypes.c_void_p), n, 1,
+                                  coef.ctypes.data_as(ctypes.c_void_p), err2.ctypes.data_as(ctypes.c_void_p),
+                                  y2.ctypes.data_as(ctypes.c_void_p))
+        if rc:
+            raise EmuError(rc)
+        return coef[:, : r[self.d]], err2, y2
+
+    def core(self, i):
+        rows, cols = ctypes.c_int64(), ctypes.c_int64()
+        self.L.ttice_get_core(self.h, i, None, ctypes.byref(rows), ctypes.byref(cols))
+        out = np.zeros((rows.value, cols.value))
+        if out.size:
+            self.L.ttice_get_core(self.h, i, out.ctypes.data_as(ctypes.c_void_p), None, None)
+        return out
+
+    def close(self):
+        if self.h:
+            self.L.ttice_destroy(self.h)
+            self.h = None

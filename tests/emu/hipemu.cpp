@@ -1,0 +1,184 @@
+// Implementation of the CPU emulation layer declared in hipemu.h (tests only).
+// The threads of a block run as user-space fibers (ucontext) on one OS
+// thread; __syncthreads switches back to a scheduler that resumes every
+// fiber in turn, so a barrier completes when all fibers have reached it.
+#include "hipemu.h"
+
+#include <ucontext.h>
+
+#if defined(__SANITIZE_ADDRESS__)
+#include <sanitizer/common_interface_defs.h>
+#define EMU_ASAN 1
+#else
+#define EMU_ASAN 0
+#endif
+
+namespace hipemu {
+
+thread_local dim3 tl_threadIdx, tl_blockIdx;
+dim3 g_blockDim, g_gridDim;
+long long g_fail_alloc_after = -1;
+
+namespace {
+constexpr size_t kStack = 256 * 1024;
+struct Fiber {
+  ucontext_t ctx;
+  char* stack = nullptr;
+  bool done = false;
+};
+ucontext_t sched_ctx;
+std::vector<Fiber> fibers;
+unsigned cur = 0;
+unsigned nthreads = 1;
+const std::function<void()>* g_body = nullptr;
+std::vector<double> shfl_buf;
+std::vector<unsigned char> dyn;
+#if EMU_ASAN
+void* sched_fake = nullptr;
+const void* sched_bottom = nullptr;
+size_t sched_size = 0;
+#endif
+
+void to_scheduler(bool finishing) {
+#if EMU_ASAN
+  void* fake = nullptr;
+  __sanitizer_start_switch_fiber(finishing ? nullptr : &fake, sched_bottom, sched_size);
+#endif
+  swapcontext(&fibers[cur].ctx, &sched_ctx);
+#if EMU_ASAN
+  __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+#endif
+}
+
+void fiber_entry() {
+#if EMU_ASAN
+  __sanitizer_finish_switch_fiber(nullptr, &sched_bottom, &sched_size);
+#endif
+  (*g_body)();
+  fibers[cur].done = true;
+  to_scheduler(true);
+}
+
+void resume(unsigned t) {
+  cur = t;
+  const dim3 b = g_blockDim;
+  tl_threadIdx = dim3(t % b.x, (t / b.x) % b.y, t / (b.x * b.y));
+#if EMU_ASAN
+  __sanitizer_start_switch_fiber(&sched_fake, fibers[t].stack, kStack);
+#endif
+  swapcontext(&sched_ctx, &fibers[t].ctx);
+#if EMU_ASAN
+  __sanitizer_finish_switch_fiber(sched_fake, nullptr, nullptr);
+#endif
+}
+}  // namespace
+
+void barrier() { to_scheduler(false); }
+
+double shfl_down(double v, int off) {
+  const unsigned tid = cur;
+  shfl_buf[tid] = v;
+  barrier();
+  const unsigned lane = tid & 63u;
+  const double r = (lane + (unsigned)off < 64u && tid + (unsigned)off < nthreads) ? shfl_buf[tid + off] : v;
+  barrier();
+  return r;
+}
+
+void* dyn_lds() { return dyn.data(); }
+
+void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body) {
+  g_gridDim = grid;
+  g_blockDim = block;
+  const unsigned nt = block.x * block.y * block.z;
+  nthreads = nt;
+  g_body = &body;
+  shfl_buf.assign(nt, 0.0);
+  if (fibers.size() < nt) fibers.resize(nt);
+  for (unsigned t = 0; t < nt; ++t)
+    if (!fibers[t].stack) fibers[t].stack = (char*)malloc(kStack);
+  for (unsigned bz = 0; bz < grid.z; ++bz)
+    for (unsigned by = 0; by < grid.y; ++by)
+      for (unsigned bx = 0; bx < grid.x; ++bx) {
+        tl_blockIdx = dim3(bx, by, bz);
+        dyn.assign(shmem ? shmem : 8, 0xff);  // LDS is not zeroed on the device
+        for (unsigned t = 0; t < nt; ++t) {
+          getcontext(&fibers[t].ctx);
+          fibers[t].ctx.uc_stack.ss_sp = fibers[t].stack;
+          fibers[t].ctx.uc_stack.ss_size = kStack;
+          fibers[t].ctx.uc_link = nullptr;
+          fibers[t].done = false;
+          makecontext(&fibers[t].ctx, fiber_entry, 0);
+        }
+        for (;;) {
+          unsigned alive = 0, finished = 0;
+          for (unsigned t = 0; t < nt; ++t) {
+            if (fibers[t].done) continue;
+            resume(t);
+            if (fibers[t].done) ++finished; else ++alive;
+          }
+          if (alive == 0) break;
+          if (finished != 0) {
+            fprintf(stderr, "hipemu: %u threads exited while %u wait at a barrier\n", finished, alive);
+            abort();
+          }
+        }
+      }
+}
+
+}  // namespace hipemu
+
+static long long g_allocs = 0;
+
+hipError_t hipMalloc(void** p, size_t n) {
+  if (hipemu::g_fail_alloc_after >= 0 && g_allocs++ >= hipemu::g_fail_alloc_after) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  *p = malloc(n ? n : 1);
+  if (*p) memset(*p, 0xff, n);  // device memory is not zeroed
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+hipError_t hipFree(void* p) {
+  free(p);
+  return hipSuccess;
+}
+hipError_t hipHostMalloc(void** p, size_t n, unsigned) {
+  *p = malloc(n ? n : 1);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+hipError_t hipHostFree(void* p) {
+  free(p);
+  return hipSuccess;
+}
+hipError_t hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind, hipStream_t) {
+  memmove(dst, src, n);
+  return hipSuccess;
+}
+hipError_t hipMemcpy(void* dst, const void* src, size_t n, hipMemcpyKind) {
+  memmove(dst, src, n);
+  return hipSuccess;
+}
+hipError_t hipMemcpy2DAsync(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
+                            size_t height, hipMemcpyKind, hipStream_t) {
+  for (size_t r = 0; r < height; ++r) memmove((char*)dst + r * dpitch, (const char*)src + r * spitch, width);
+  return hipSuccess;
+}
+hipError_t hipMemsetAsync(void* dst, int v, size_t n, hipStream_t) {
+  memset(dst, v, n);
+  return hipSuccess;
+}
+hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t hipDeviceSynchronize() { return hipSuccess; }
+hipError_t hipGetLastError() { return hipSuccess; }
+hipError_t hipGetDevice(int* d) {
+  *d = 0;
+  return hipSuccess;
+}
+hipError_t hipSetDevice(int) { return hipSuccess; }
+hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
+
+extern "C" void hipemu_fail_alloc_after(long long k) {
+  hipemu::g_fail_alloc_after = k;
+  g_allocs = 0;
+}

@@ -1,0 +1,104 @@
+// CPU emulation of the small HIP subset used by the library's sources, for
+// host-side testing only (logic and bounds checks under AddressSanitizer).
+// Never part of the product: the shipped library is built by hipcc for
+// gfx950.  Each block runs as blockDim host threads; __syncthreads is a
+// barrier over them; blocks run one after another; "device" memory is host
+// memory.  Wave operations (__shfl_down) assume 64-lane waves and are only
+// valid where the whole block calls them together (as the kernels do).
+#pragma once
+
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <functional>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+#define HIP_DYNAMIC_SHARED(type, name) type* name = (type*)hipemu::dyn_lds()
+
+struct dim3 {
+  unsigned x, y, z;
+  constexpr dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+
+typedef int hipError_t;
+typedef void* hipStream_t;
+enum {
+  hipSuccess = 0,
+  hipErrorOutOfMemory = 2,
+  hipErrorMemoryAllocation = 2,
+  hipErrorInvalidValue = 1,
+};
+enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyDefault };
+enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize = 8 };
+#define hipHostMallocDefault 0
+
+namespace hipemu {
+extern thread_local dim3 tl_threadIdx, tl_blockIdx;
+extern dim3 g_blockDim, g_gridDim;
+void barrier();
+double shfl_down(double v, int off);
+void* dyn_lds();
+void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body);
+extern long long g_fail_alloc_after;  // failure injection: fail the k-th allocation (-1: never)
+}  // namespace hipemu
+
+#define threadIdx (hipemu::tl_threadIdx)
+#define blockIdx (hipemu::tl_blockIdx)
+#define blockDim (hipemu::g_blockDim)
+#define gridDim (hipemu::g_gridDim)
+
+inline void __syncthreads() { hipemu::barrier(); }
+inline void __threadfence_block() {}
+inline void __threadfence() {}
+inline double __shfl_down(double v, int off, int = 64) { return hipemu::shfl_down(v, off); }
+
+using std::fma;
+using std::fabs;
+using std::sqrt;
+using std::isfinite;
+inline int min(int a, int b) { return a < b ? a : b; }
+inline int max(int a, int b) { return a > b ? a : b; }
+inline long long min(long long a, long long b) { return a < b ? a : b; }
+inline long long max(long long a, long long b) { return a > b ? a : b; }
+inline long min(long a, long b) { return a < b ? a : b; }
+inline long max(long a, long b) { return a > b ? a : b; }
+
+#define hipLaunchKernelGGL(kern, grid, block, shmem, stream, ...) \
+  hipemu::launch((grid), (block), (shmem), [&]() { kern(__VA_ARGS__); })
+
+hipError_t hipMalloc(void** p, size_t n);
+hipError_t hipFree(void* p);
+hipError_t hipHostMalloc(void** p, size_t n, unsigned flags);
+hipError_t hipHostFree(void* p);
+hipError_t hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind k, hipStream_t s);
+hipError_t hipMemcpy(void* dst, const void* src, size_t n, hipMemcpyKind k);
+hipError_t hipMemcpy2DAsync(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
+                            size_t height, hipMemcpyKind k, hipStream_t s);
+hipError_t hipMemsetAsync(void* dst, int v, size_t n, hipStream_t s);
+hipError_t hipStreamSynchronize(hipStream_t s);
+hipError_t hipDeviceSynchronize();
+hipError_t hipGetLastError();
+hipError_t hipGetDevice(int* d);
+hipError_t hipSetDevice(int d);
+hipError_t hipFuncSetAttribute(const void* f, hipFuncAttribute a, int v);
+template <typename T>
+hipError_t hipMalloc(T** p, size_t n) {
+  return hipMalloc((void**)p, n);
+}
+template <typename T>
+hipError_t hipHostMalloc(T** p, size_t n, unsigned flags) {
+  return hipHostMalloc((void**)p, n, flags);
+}

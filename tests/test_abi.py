@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI: the library loads, exports exactly what
+include/ttice.h declares, the ctypes struct matches the C layout, and
+argument validation that happens before any device call."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ttice.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ttice_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2211_12487_amd import ttice
+    return ttice.lib()
+
+
+def test_library_exports_every_declared_symbol(L):
+    from paper_2211_12487_amd import ttice
+    decl = declared_functions()
+    assert decl == sorted(ttice.EXPORTS)
+    for name in decl:
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", ttice.library_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = sorted(set(re.findall(r" T (\w+)", out)))
+    assert exported == decl
+
+
+def test_update_info_layout_matches_c():
+    from paper_2211_12487_amd.ttice import UpdateInfo
+    prog = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "ttice.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(struct ttice_update_info),
+         offsetof(struct ttice_update_info, norm_y2), offsetof(struct ttice_update_info, ranks),
+         offsetof(struct ttice_update_info, r_new), offsetof(struct ttice_update_info, tail2),
+         offsetof(struct ttice_update_info, margin), offsetof(struct ttice_update_info, achieved2));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as td:
+        c = os.path.join(td, "t.c")
+        exe = os.path.join(td, "t")
+        open(c, "w").write(prog)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    py = [ctypes.sizeof(UpdateInfo), UpdateInfo.norm_y2.offset, UpdateInfo.ranks.offset,
+          UpdateInfo.r_new.offset, UpdateInfo.tail2.offset, UpdateInfo.margin.offset,
+          UpdateInfo.achieved2.offset]
+    assert vals == py
+
+
+def test_header_compiles_as_c_and_cpp():
+    with tempfile.TemporaryDirectory() as td:
+        for ext, comp in ((".c", "gcc"), (".cpp", "g++")):
+            f = os.path.join(td, "h" + ext)
+            open(f, "w").write('#include "ttice.h"\nint main(void){return TTICE_OK;}\n')
+            subprocess.run([comp, "-Wall", "-Werror", "-I", os.path.dirname(HEADER), f, "-o",
+                            os.path.join(td, "h" + ext + ".out")], check=True)
+
+
+def test_argument_validation_without_device(L):
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_int64 * 3)(4, 5, 6)
+    # invalid arguments are rejected before any device call
+    assert L.ttice_create(0, dims, 0.1, ctypes.byref(h)) == -1
+    assert L.ttice_create(17, dims, 0.1, ctypes.byref(h)) == -1
+    assert L.ttice_create(3, dims, 0.0, ctypes.byref(h)) == -1
+    assert L.ttice_create(3, dims, 1.0, ctypes.byref(h)) == -1
+    bad = (ctypes.c_int64 * 3)(4, 0, 6)
+    assert L.ttice_create(3, bad, 0.1, ctypes.byref(h)) == -1
+    huge = (ctypes.c_int64 * 3)(1 << 12, 1 << 12, 1 << 8)
+    assert L.ttice_create(3, huge, 0.1, ctypes.byref(h)) == -1
+    assert L.ttice_create(3, dims, 0.1, None) == -1
+    # null state
+    r = (ctypes.c_int64 * 5)()
+    assert L.ttice_ranks(None, r, None) == -4
+    assert L.ttice_update(None, None, 0, 0, None) == -4
+    assert L.ttice_reconstruct(None, 0, 0, None, 0) == -4
+    assert L.ttice_set_option(None, 1, None) == -4
+    assert L.ttice_get_core(None, 0, None, None, None) == -4
+    L.ttice_destroy(None)
+    assert L.ttice_strerror(0) == b"ok"
+    assert L.ttice_strerror(-2) == b"out of memory"

@@ -1,0 +1,240 @@
+"""GPU <-> oracle parity of the HIP TT-ICE path, through the C ABI.
+
+Every case feeds the same seeded arrays to libttice.so and to the FP64 CPU
+oracle.  Bars: equal TT-ranks on every increment whose rank decisions clear
+the oracle's margin floor, reconstructions within 1e-10 relative (FP64
+path), achieved error <= eps per increment, orthonormal cores to 1e-12."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import TTICE as Oracle
+from paper_2211_12487_amd import synth
+
+from gpu_helpers import (MARGIN_FP64, compare_stream, full_reconstruction_error, log, orthogonality,
+                         to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12487_amd import ttice
+    ttice.lib()
+    yield
+
+
+def make(dims, eps, **kw):
+    from paper_2211_12487_amd.ttice import TTICE
+    return TTICE(dims, eps, **kw)
+
+
+def sep(n, dims, batch, seed, terms=4, noise=1e-3, dtype=np.float64):
+    return list(synth.smooth_separable_stream(n, dims, terms, noise, batch, seed, dtype=dtype))
+
+
+def test_separable16_full_stream_fp64():
+    """16x16x3 tensors, one per increment, 100 increments, eps = 0.05."""
+    log("case separable16 x100, FP64 input")
+    dims, eps = (16, 16, 3), 0.05
+    g, o = make(dims, eps), Oracle(dims, eps)
+    infos, ok = compare_stream(g, o, sep(100, dims, 1, 0, terms=5), 1e-10, MARGIN_FP64, label="sep16")
+    assert ok
+    for gi, oi in infos:
+        assert gi["achieved2"] <= eps ** 2 * gi["normY2"] * (1 + 1e-9)
+        assert gi["achieved2"] == pytest.approx(oi["achieved2"], rel=1e-6, abs=1e-20)
+    full_reconstruction_error(g, o, 1e-10)
+    assert orthogonality(g) <= 1e-12
+    assert g.ranks() == o.ranks + [1]
+
+
+@pytest.mark.parametrize("in_dtype", [np.float64, np.float32])
+def test_ragged_shapes_varying_batches(in_dtype):
+    """Sizes off the 64-wide tiles (37 x 29 x 5), batch sizes 1..7."""
+    log(f"case ragged 37x29x5 dtype={in_dtype.__name__}")
+    dims, eps = (37, 29, 5), 0.02
+    rng = np.random.default_rng(3)
+    sizes = [int(x) for x in rng.integers(1, 8, 12)]
+    gen = synth.smooth_separable_stream(sum(sizes), dims, 6, 1e-3, 1, 4, dtype=in_dtype)
+    flat = list(gen)
+    batches, k = [], 0
+    for s in sizes:
+        batches.append(np.concatenate(flat[k:k + s]))
+        k += s
+    g, o = make(dims, eps), Oracle(dims, eps)
+    _, ok = compare_stream(g, o, batches, 1e-10 if in_dtype == np.float64 else 1e-9, MARGIN_FP64,
+                           label="ragged")
+    assert ok
+    assert orthogonality(g) <= 1e-12
+
+
+def test_order4_batches():
+    log("case order-4 9x7x11x3, batches of 4")
+    dims, eps = (9, 7, 11, 3), 0.03
+    g, o = make(dims, eps), Oracle(dims, eps)
+    _, ok = compare_stream(g, o, sep(40, dims, 4, 5, terms=5), 1e-10, MARGIN_FP64, label="order4")
+    assert ok
+    full_reconstruction_error(g, o, 1e-10)
+    assert orthogonality(g) <= 1e-12
+
+
+def test_order1_and_order2():
+    log("case order-1 (70,) and order-2 (40, 90)")
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((70, 5))
+    for dims, eps, mk in [((70,), 0.05, lambda b: (A @ rng.standard_normal((5, b))).T + 1e-3 * rng.standard_normal((b, 70))),
+                          ((40, 90), 0.05, None)]:
+        g, o = make(dims, eps), Oracle(dims, eps)
+        if mk is None:
+            batches = sep(30, dims, 6, 7, terms=4)
+        else:
+            batches = [mk(b) for b in (50, 3, 20, 1, 9)]
+        _, ok = compare_stream(g, o, batches, 1e-10, MARGIN_FP64, label=f"order{len(dims)}")
+        assert ok
+        assert orthogonality(g) <= 1e-12
+
+
+def test_video_prefix_fp32_input():
+    """Video-shaped 240x320x3 FP32 frames, batches of 32 (the benchmark's
+    shapes): 240x240 left Gram at core 1, 96x96 right Gram at core 2."""
+    log("case video240 prefix: 3 increments x 32 frames")
+    dims, eps = (240, 320, 3), 0.1
+    g, o = make(dims, eps), Oracle(dims, eps)
+    batches = list(synth.video_stream(96, 32, seed=1))
+    _, ok = compare_stream(g, o, batches, 1e-10, MARGIN_FP64, label="video")
+    assert ok
+    assert orthogonality(g) <= 1e-12
+
+
+def test_lowrank_stream_discovers_tt_ranks():
+    """Exactly low-rank stream (App. B shapes, TT-ranks [1,2,3,5,1]); eps is
+    1e-6 because the GPU path takes singular values from a Gram matrix."""
+    dims = (10, 15, 20)
+    g = make(dims, 1e-6)
+    for k, Y in enumerate(synth.tt_lowrank_stream(dims, (2, 3, 5), 12, 1, seed=7), start=1):
+        g.update(to_dev(Y))
+        assert g.ranks()[1:-1] == [2, 3, min(k, 5)], (k, g.ranks())
+
+
+@pytest.mark.parametrize("batch", [4, 9])
+def test_star_against_oracle(batch):
+    """Algorithm 2 (TT-ICE*): skip decisions, subselection, eps_upd, ranks and
+    reconstructions against the oracle."""
+    log(f"case TT-ICE* batch {batch}")
+    dims, eps = (12, 10, 6), 0.05
+    g = make(dims, eps, algo="star")
+    o = Oracle(dims, eps, algo="star")
+    n_skip = 0
+    rng = np.random.default_rng(8)
+    batches = [Y + 1e-3 * rng.standard_normal(Y.shape)
+               for Y in synth.tt_lowrank_stream(dims, (3, 4, 4), 10 * batch, batch, seed=8)]
+    for k, Y in enumerate(batches):
+        gi = g.update(to_dev(Y))
+        oi = o.update(Y)
+        assert gi["skipped"] == oi["skipped"], k
+        n_skip += gi["skipped"]
+        assert gi["used"] == oi["used"], k
+        if not oi["skipped"]:
+            assert gi["eps_upd"] == pytest.approx(oi["eps_upd"], rel=1e-9)
+        assert gi["ranks"][1:-1] == oi["ranks"][1:-1], (k, gi["ranks"], oi["ranks"])
+    full_reconstruction_error(g, o, 1e-10)
+    assert orthogonality(g) <= 1e-12
+    assert n_skip > 0
+    log(f"  skipped {n_skip} increments")
+
+
+def test_star_equals_plain_when_every_frame_exceeds():
+    dims, eps = (8, 6, 5), 0.02
+    a, b = make(dims, eps), make(dims, eps, algo="star")
+    for Y in sep(12, dims, 3, 6, terms=6):
+        ia = a.update(to_dev(Y))
+        ib = b.update(to_dev(Y))
+        assert not ib["skipped"]
+        assert ib["eps_upd"] == pytest.approx(eps, rel=1e-12)
+        assert ia["ranks"] == ib["ranks"]
+    ra, rb = a.reconstruct().cpu().numpy(), b.reconstruct().cpu().numpy()
+    assert np.abs(ra - rb).max() <= 1e-10 * np.abs(ra).max()
+
+
+def test_project_matches_oracle():
+    dims, eps = (12, 10, 6), 0.05
+    g, o = make(dims, eps), Oracle(dims, eps)
+    for Y in sep(8, dims, 2, 9):
+        g.update(to_dev(Y))
+        o.update(Y)
+    Ynew = sep(5, dims, 5, 99)[0]
+    coef, err2, y2 = g.project(to_dev(Ynew))
+    ocoef, otil = o.project(Ynew)
+    np.testing.assert_allclose(coef.cpu().numpy(), ocoef, rtol=0, atol=1e-10 * np.abs(ocoef).max())
+    brute = np.array([np.sum((Ynew[b] - otil[b]) ** 2) for b in range(5)])
+    np.testing.assert_allclose(err2.cpu().numpy(), brute, rtol=1e-8)
+    np.testing.assert_allclose(y2.cpu().numpy(), np.sum(Ynew ** 2, axis=(1, 2, 3)), rtol=1e-12)
+
+
+def test_degenerate_inputs_and_errors():
+    from paper_2211_12487_amd.ttice import TTICEError
+    dims, eps = (4, 3, 5), 0.1
+    g = make(dims, eps)
+    # empty batch: no-op
+    info = g.update(torch.zeros((0,) + dims, dtype=torch.float64, device="cuda"))
+    assert info["n_total"] == 0 and g.ranks() == [1, 0, 0, 0, 1]
+    # all-zero batch: appended as zero coefficients, no rank growth
+    g.update(torch.zeros((2,) + dims, dtype=torch.float64, device="cuda"))
+    assert g.ranks() == [1, 0, 0, 0, 1] and g.n_total == 2
+    assert float(g.reconstruct().abs().max()) == 0.0
+    Y = sep(3, dims, 3, 10)[0]
+    g.update(to_dev(Y))
+    r_before, n_before = g.ranks(), g.n_total
+    rec_before = g.reconstruct().cpu()
+    # non-finite batch -> EINVAL, state unchanged
+    bad = to_dev(Y.copy())
+    bad[1, 2, 1, 3] = float("nan")
+    with pytest.raises(TTICEError) as ei:
+        g.update(bad)
+    assert ei.value.code == -1
+    bad[1, 2, 1, 3] = float("inf")
+    with pytest.raises(TTICEError):
+        g.update(bad)
+    assert g.ranks() == r_before and g.n_total == n_before
+    assert torch.equal(g.reconstruct().cpu(), rec_before)
+    # reconstruct out of range
+    with pytest.raises(TTICEError):
+        g.reconstruct(n_before - 1, 2)
+    with pytest.raises(TTICEError):
+        g.reconstruct(-1, 1)
+    # single tensor without the batch axis
+    g.update(to_dev(Y[0]))
+    assert g.n_total == n_before + 1
+
+
+def test_video_full_stream_properties():
+    """The benchmark's workload at full size (2048 frames of 240x320x3 in
+    batches of 32, eps = 0.1): every increment within eps (Theorem 1 / Cor. 1,
+    checked on the device against the input), cores orthonormal, and the
+    first two increments against the oracle."""
+    dims, eps = (240, 320, 3), 0.1
+    g = make(dims, eps)
+    o = Oracle(dims, eps)
+    worst = 0.0
+    for k, Y in enumerate(synth.video_stream(2048, 32, seed=0)):
+        Yd = to_dev(Y)
+        gi = g.update(Yd)
+        rec = g.reconstruct(g.n_total - 32, 32)
+        err = float(torch.linalg.vector_norm(rec - Yd.double())) / math.sqrt(gi["normY2"])
+        worst = max(worst, err)
+        assert err <= eps, (k, err)
+        assert err ** 2 * gi["normY2"] == pytest.approx(gi["achieved2"], rel=1e-6)
+        if k < 2:
+            oi = o.update(Y)
+            assert gi["ranks"] == oi["ranks"]
+            ro = o.reconstruct(o.n_total - 32, 32)
+            assert np.linalg.norm(rec.cpu().numpy() - ro) <= 1e-10 * np.linalg.norm(ro)
+        if k % 16 == 0:
+            log(f"  video increment {k}: ranks {gi['ranks']} err {err:.4f}")
+    assert orthogonality(g) <= 1e-12
+    log(f"  worst increment error {worst:.4f}")
