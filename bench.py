@@ -1,0 +1,141 @@
+"""Benchmark: TT-ICE stream compression throughput on one MI355X.
+
+Workload (the video-shaped stream): 2048 FP32 frames of 240x320x3 arriving
+in increments of 32, eps = 0.1 (fixed rank-8 separable background, four
+moving Gaussian blobs, N(0, 1e-2) noise; seeded).  One step = the whole
+stream compressed from empty cores (64 ttice_update calls), with every
+increment already resident in HBM.  value = tensors/s = 2048 * steps /
+(summed wall time of the steps).
+
+Both arms run at the same eps and must reach the same TT-ranks: the chosen
+precision (--prec, default fp32 projections) and the plain FP64 path.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = dict(name="video240", dims=(240, 320, 3), eps=0.1, frames=2048, batch=32, seed=0)
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--frames", type=int, default=WORKLOAD["frames"])
+    ap.add_argument("--cpu-increments", type=int, default=6,
+                    help="increments of the stream the CPU oracle baseline compresses")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-arm", action="store_true")
+    return ap.parse_args()
+
+
+def gen_stream(frames):
+    from paper_2211_12487_amd import synth
+    w = WORKLOAD
+    return np.concatenate(list(synth.video_stream(frames, w["batch"], seed=w["seed"])))
+
+
+def run_stream(Yd, prec, batch, eps, dims, lat=None):
+    from paper_2211_12487_amd.ttice import TTICE
+    import torch
+    g = TTICE(dims, eps, prec=prec)
+    info = None
+    for k in range(0, Yd.shape[0], batch):
+        t0 = time.perf_counter()
+        info = g.update(Yd[k:k + batch])
+        if lat is not None:
+            lat.append(time.perf_counter() - t0)
+    ranks = g.ranks()
+    g.close()
+    return ranks, info
+
+
+def time_arm(Yd, prec, steps, warmup):
+    import torch
+    w = WORKLOAD
+    for _ in range(warmup):
+        run_stream(Yd, prec, w["batch"], w["eps"], w["dims"])
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ranks = None
+    for _ in range(steps):
+        ranks, _ = run_stream(Yd, prec, w["batch"], w["eps"], w["dims"], lat)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    total = t1 - t0
+    return dict(seconds=total, tensors_per_s=Yd.shape[0] * steps / total, ranks=ranks,
+                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3))
+
+
+def cpu_baseline(Y, n_inc):
+    """The FP64 NumPy oracle on the first n_inc increments of the same stream."""
+    from oracle import TTICE as Oracle
+    w = WORKLOAD
+    o = Oracle(w["dims"], w["eps"])
+    t0 = time.perf_counter()
+    for k in range(n_inc):
+        o.update(Y[k * w["batch"]:(k + 1) * w["batch"]])
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    return dict(value=n_inc * w["batch"] / dt, unit="tensors/s", cores=cores, kind="oracle",
+                sample=f"first {n_inc} increments ({n_inc * w['batch']} frames) of the stream, "
+                       f"NumPy FP64 + LAPACK, BLAS threads up to {cores}", seconds=dt)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps(dict(error="this benchmark runs on one GPU only; multi-GPU sharding is "
+                                    "design-only (see DESIGN.md)", n_gpus=a.gpus)))
+        sys.exit(2)
+    import torch
+    from paper_2211_12487_amd import ttice
+    ttice.lib()
+    w = WORKLOAD
+    print(f"generating {a.frames} frames", file=sys.stderr, flush=True)
+    Y = gen_stream(a.frames)
+    Yd = torch.from_numpy(Y).cuda()
+    torch.cuda.synchronize()
+    print("timing chosen arm", file=sys.stderr, flush=True)
+    chosen = time_arm(Yd, a.prec, a.steps, a.warmup)
+    fp64 = None
+    if not a.no_fp64_arm and a.prec != "fp64":
+        print("timing fp64 arm", file=sys.stderr, flush=True)
+        fp64 = time_arm(Yd, "fp64", a.steps, a.warmup)
+        assert fp64["ranks"] == chosen["ranks"], (fp64["ranks"], chosen["ranks"])
+    cpu = None
+    if not a.no_cpu_baseline:
+        print("timing cpu oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(Y, a.cpu_increments)
+    ms_per_step = chosen["seconds"] / a.steps * 1e3
+    out = dict(
+        metric="tensors/s at fixed eps (chosen precision vs plain FP64), % HBM roofline, p99 update latency",
+        value=chosen["tensors_per_s"], unit="tensors/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+        ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype={"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[a.prec], data="synthetic",
+        config=dict(workload=f"{w['name']}: {a.frames} frames 240x320x3 fp32, increments of {w['batch']}, "
+                             f"eps={w['eps']}, TT-ICE (Algorithm 1) from empty cores",
+                    frames=a.frames, batch=w["batch"], eps=w["eps"], prec=a.prec),
+        final_ranks=chosen["ranks"], p50_update_ms=chosen["p50_ms"], p99_update_ms=chosen["p99_ms"],
+        fp64_arm=(dict(value=fp64["tensors_per_s"], p50_update_ms=fp64["p50_ms"], p99_update_ms=fp64["p99_ms"])
+                  if fp64 else None),
+        roofline=None,
+        cpu_baseline=cpu,
+    )
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

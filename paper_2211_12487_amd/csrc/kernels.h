@@ -54,15 +54,25 @@ inline View unfolding(int64_t cols, int64_t fs, const int32_t* fidx = nullptr) {
   return v;
 }
 
+// Scratch the product may use to split a long K-sum across workgroups.
+struct GemmWs {
+  double* p = nullptr;
+  int64_t len = 0;  // doubles
+};
+
 // D = alpha * A * B + beta * E over an M x N output, K-sum split into
 // ceil(K / kchunk) slices along grid z (slice z writes D + z*dz).  A is FP64.
 // Optional outputs: colpart[mb*N + n] = sum over the rows of output tile mb of
 // D(m, n)^2 (FP64), bnorm[n] = sum_k B(k, n)^2 (only with one K slice).
-// Any of E / D / colpart / bnorm may be null.
+// Any of E / D / colpart / bnorm may be null.  When one K slice is asked
+// for (kchunk >= K), the output has few tiles and K is long, the product is
+// split over K into partial sums in ws (if given and large enough) and
+// finished by a second kernel that applies alpha, beta*E and colpart; the
+// result does not depend on the split (fixed summation order per split).
 template <typename TB, typename TE, typename TD>
 hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk, double alpha,
                 const double* A, View va, const TB* B, View vb, double beta, const TE* E, View ve,
-                TD* D, View vd, int64_t dz, double* colpart, double* bnorm);
+                TD* D, View vd, int64_t dz, double* colpart, double* bnorm, GemmWs ws = GemmWs());
 
 inline int32_t gemm_row_blocks(int32_t M) { return M > 0 ? (M + 63) / 64 : 1; }
 
@@ -78,13 +88,17 @@ hipError_t accumulate(hipStream_t st, double* acc, const double* x, int64_t n);
 // (slice stride m*m), mirrored to be exactly symmetric.
 hipError_t gram_reduce(hipStream_t st, const double* part, int32_t S, int32_t m, double* G);
 
-// Symmetric eigendecomposition G = V diag(w) V^T by cyclic two-sided Jacobi
-// (round-robin parallel ordering).  G (m x m, row-major, ld = m) is
-// overwritten; V (m x m row-major, column t = eigenvector t); w (m), unsorted.
-// scratch: >= 8*m doubles.  Returns the number of sweeps in *h_sweeps
-// (device int written to dsweeps).
-hipError_t sym_eig(hipStream_t st, int32_t m, double* G, double* V, double* w, int32_t* dsweeps);
-int32_t sym_eig_lds_max();
+// Eigenvalues of the symmetric m x m matrix A (row-major, ld = m): A is
+// reduced in place to tridiagonal form T = Q^T A Q (d, e; reflectors kept in
+// A's rows and tau) and w receives all eigenvalues in decreasing order
+// (Sturm bisection).  vp: 2m doubles of scratch (m > sym_tri_lds_max()).
+hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* vp,
+                       double* w);
+// Eigenvectors of A for its r largest eigenvalues lam[0..r) (from
+// sym_eigvals, decreasing): X (m x r, row-major).  ws: 8m + m*r doubles.
+hipError_t sym_eigvecs(hipStream_t st, int32_t m, int32_t r, const double* d, const double* e,
+                       const double* lam, const double* A, const double* tau, double* ws, double* X);
+int32_t sym_tri_lds_max();
 
 // Rank selection for SVD(R, eps) from the eigenvalues w (m) of the residual's
 // Gram matrix: order[t] = index of the t-th largest eigenvalue, lam[t] its

@@ -7,6 +7,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace ttice {
 
 namespace {
@@ -24,6 +26,49 @@ __device__ __forceinline__ int64_t col_off(const View& v, int32_t j) {
   const uint32_t w = (uint32_t)j - f * (uint32_t)v.cpf;
   const int64_t ff = v.cfidx ? (int64_t)v.cfidx[f] : (int64_t)f;
   return ff * v.cfs + (int64_t)w * v.cs;
+}
+
+// Shared epilogue of the tiled products: D(m,n) = alpha*acc + beta*E(m,n),
+// and per-column sums of D^2 over the tile's rows into colpart.
+template <typename TE, typename TD>
+__device__ __forceinline__ void gemm_epilogue(double (&acc)[4][4], int32_t M, int32_t N, int32_t m0, int32_t n0,
+                                              double alpha, double beta, const TE* __restrict__ E, const View& ve,
+                                              TD* __restrict__ D, const View& vd, double* __restrict__ colpart,
+                                              double* red) {
+  const int t = threadIdx.x;
+  const int tx = t & 15, ty = t >> 4;
+  double csq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int32_t m = m0 + ty + 16 * i;
+    if (m >= M) continue;
+    const int64_t ero = E ? row_off(ve, m) : 0;
+    const int64_t dro = D ? row_off(vd, m) : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int32_t n = n0 + tx + 16 * j;
+      if (n >= N) continue;
+      double v = alpha * acc[i][j];
+      if (E) v = fma(beta, (double)E[ero + col_off(ve, n)], v);
+      if (D) D[dro + col_off(vd, n)] = (TD)v;
+      csq[j] = fma(v, v, csq[j]);
+    }
+  }
+  if (colpart != nullptr) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      red[t] = csq[j];
+      __syncthreads();
+      if (ty == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int y = 0; y < 16; ++y) s += red[y * 16 + tx];
+        const int32_t n = n0 + tx + 16 * j;
+        if (n < N) colpart[(int64_t)blockIdx.y * N + n] = s;
+      }
+      __syncthreads();
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -99,39 +144,35 @@ __global__ __launch_bounds__(256) void k_gemm(int32_t M, int32_t N, int32_t K, i
     __syncthreads();
   }
 
-  double csq[4] = {0.0, 0.0, 0.0, 0.0};
   TD* Dz = D ? D + dz * (int64_t)blockIdx.z : nullptr;
+  gemm_epilogue<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, Dz, vd, colpart, red);
+}
+
+// Second pass of a K-split product: sum the S partial products (fixed
+// order), then the same epilogue as k_gemm.
+template <typename TE, typename TD>
+__global__ __launch_bounds__(256) void k_splitk_finish(int32_t M, int32_t N, int32_t S,
+                                                        const double* __restrict__ part, double alpha,
+                                                        double beta, const TE* __restrict__ E, View ve,
+                                                        TD* __restrict__ D, View vd,
+                                                        double* __restrict__ colpart) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  const int tx = t & 15, ty = t >> 4;
+  const int32_t m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int64_t MN = (int64_t)M * N;
+  double acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int32_t m = m0 + ty + 16 * i;
-    if (m >= M) continue;
-    const int64_t ero = E ? row_off(ve, m) : 0;
-    const int64_t dro = Dz ? row_off(vd, m) : 0;
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int32_t n = n0 + tx + 16 * j;
-      if (n >= N) continue;
-      double v = alpha * acc[i][j];
-      if (E) v = fma(beta, (double)E[ero + col_off(ve, n)], v);
-      if (Dz) Dz[dro + col_off(vd, n)] = (TD)v;
-      csq[j] = fma(v, v, csq[j]);
+      const int32_t m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
+      double s = 0.0;
+      if (m < M && n < N)
+        for (int32_t z = 0; z < S; ++z) s += part[z * MN + (int64_t)m * N + n];
+      acc[i][j] = s;
     }
-  }
-  if (colpart != nullptr) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      red[t] = csq[j];
-      __syncthreads();
-      if (ty == 0) {
-        double s = 0.0;
-#pragma unroll
-        for (int y = 0; y < 16; ++y) s += red[y * 16 + tx];
-        const int32_t n = n0 + tx + 16 * j;
-        if (n < N) colpart[(int64_t)blockIdx.y * N + n] = s;
-      }
-      __syncthreads();
-    }
-  }
+  gemm_epilogue<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, D, vd, colpart, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -198,230 +239,6 @@ __global__ void k_gram_reduce(const double* __restrict__ part, int32_t S, int32_
   double s = 0.0;
   for (int32_t z = 0; z < S; ++z) s += part[z * mm + src];
   G[idx] = s;
-}
-
-// ---------------------------------------------------------------------------
-// Cyclic two-sided Jacobi (Golub & Van Loan, symmetric Schur 2x2 rotations)
-// with the round-robin ("circle") parallel ordering: at step t the pairs are
-// (t mod (n-1), n-1) and ((t+k) mod (n-1), (t-k) mod (n-1)), k = 1..n/2-1,
-// so every index pair is visited once per sweep and the n/2 rotations of a
-// step act on disjoint index pairs.  For disjoint pairs the two-sided update
-// G <- J^T G J factorises over 2x2 blocks (pair a rows, pair b cols):
-// block_ab <- J_a^T block_ab J_b, so each block is updated independently.
-// The matrix lives either in LDS (Gs/Vs with row stride ldl) or in global
-// memory; the same device routine serves both.
-// ---------------------------------------------------------------------------
-constexpr int kJacobiThreads = 1024;
-constexpr int kJacobiLdsMax = 96;
-constexpr int kMaxSweeps = 40;
-
-constexpr int kJacobiGlobalHalf = 2048;  // pairs per step of the global-memory path (m <= 4096)
-
-template <int HALF>
-struct JacobiShared {
-  int32_t p[HALF];
-  int32_t q[HALF];
-  double c[HALF];
-  double s[HALF];
-  double tn[HALF];
-  int32_t rot[HALF];
-  int32_t any;
-  double red[kJacobiThreads / 64];
-};
-
-__device__ double block_sum_1024(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < kJacobiThreads / 64; ++i) s += red[i];
-  __syncthreads();
-  if (threadIdx.x == 0) red[0] = s;
-  __syncthreads();
-  s = red[0];
-  __syncthreads();
-  return s;
-}
-
-__device__ __forceinline__ void pair_of(int32_t t, int32_t k, int32_t n, int32_t& p, int32_t& q) {
-  const int32_t n1 = n - 1;
-  if (k == 0) {
-    p = t % n1;
-    q = n1;
-  } else {
-    p = (t + k) % n1;
-    q = (t - k + n1) % n1;
-  }
-  if (p > q) {
-    const int32_t x = p;
-    p = q;
-    q = x;
-  }
-}
-
-// G, V: n x n (n even) with row stride ld; indices >= m are padding.
-template <bool kLds, int HALF>
-__device__ void jacobi_run(int32_t m, int32_t n, double* G, double* V, int64_t ld,
-                           JacobiShared<HALF>& sh, int32_t* dsweeps) {
-  const int t = threadIdx.x;
-  const int32_t half = n / 2;
-  // Frobenius norm for the absolute threshold
-  double fs = 0.0;
-  for (int64_t e = t; e < (int64_t)m * m; e += kJacobiThreads) {
-    const int32_t i = (int32_t)(e / m), j = (int32_t)(e % m);
-    const double g = G[(int64_t)i * ld + j];
-    fs = fma(g, g, fs);
-  }
-  const double normF = sqrt(block_sum_1024(fs, sh.red));
-  const double u = 2.220446049250313e-16;
-  const double tol_abs = u * normF / (double)(n > 1 ? n : 1);
-  __syncthreads();
-
-  int32_t sweep = 0;
-  for (; sweep < kMaxSweeps; ++sweep) {
-    if (t == 0) sh.any = 0;
-    __syncthreads();
-    for (int32_t step = 0; step < n - 1; ++step) {
-      for (int32_t k = t; k < half; k += kJacobiThreads) {
-        int32_t p, q;
-        pair_of(step, k, n, p, q);
-        sh.p[k] = p;
-        sh.q[k] = q;
-        int32_t rot = 0;
-        double cs = 1.0, sn = 0.0, tn = 0.0;
-        if (q < m) {
-          const double a = G[(int64_t)p * ld + p];
-          const double b = G[(int64_t)q * ld + q];
-          const double c = G[(int64_t)p * ld + q];
-          const double thr = fmax(u * sqrt(fabs(a) * fabs(b)), tol_abs);
-          if (fabs(c) > thr) {
-            const double tau = (b - a) / (2.0 * c);
-            const double tt = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                                           : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-            cs = 1.0 / sqrt(1.0 + tt * tt);
-            sn = tt * cs;
-            tn = tt;
-            rot = 1;
-          }
-        }
-        sh.c[k] = cs;
-        sh.s[k] = sn;
-        sh.tn[k] = tn;
-        sh.rot[k] = rot;
-        if (rot) sh.any = 1;
-      }
-      __syncthreads();
-      // 2x2 block updates for ka <= kb (mirror kb < ka)
-      const int32_t nblk = half * half;
-      for (int32_t task = t; task < nblk; task += kJacobiThreads) {
-        const int32_t ka = task / half, kb = task - ka * half;
-        if (kb < ka) continue;
-        const int32_t ra = sh.rot[ka], rb = sh.rot[kb];
-        if (!ra && !rb) continue;
-        const int32_t pa = sh.p[ka], qa = sh.q[ka], pb = sh.p[kb], qb = sh.q[kb];
-        if (ka == kb) {
-          const double c = G[(int64_t)pa * ld + qa];
-          const double tt = sh.tn[ka];
-          G[(int64_t)pa * ld + pa] -= tt * c;
-          G[(int64_t)qa * ld + qa] += tt * c;
-          G[(int64_t)pa * ld + qa] = 0.0;
-          G[(int64_t)qa * ld + pa] = 0.0;
-          continue;
-        }
-        const double ca = sh.c[ka], sa = sh.s[ka], cb = sh.c[kb], sb = sh.s[kb];
-        const double g11 = G[(int64_t)pa * ld + pb], g12 = G[(int64_t)pa * ld + qb];
-        const double g21 = G[(int64_t)qa * ld + pb], g22 = G[(int64_t)qa * ld + qb];
-        const double h11 = ca * g11 - sa * g21, h12 = ca * g12 - sa * g22;
-        const double h21 = sa * g11 + ca * g21, h22 = sa * g12 + ca * g22;
-        const double n11 = cb * h11 - sb * h12, n12 = sb * h11 + cb * h12;
-        const double n21 = cb * h21 - sb * h22, n22 = sb * h21 + cb * h22;
-        G[(int64_t)pa * ld + pb] = n11;
-        G[(int64_t)pa * ld + qb] = n12;
-        G[(int64_t)qa * ld + pb] = n21;
-        G[(int64_t)qa * ld + qb] = n22;
-        G[(int64_t)pb * ld + pa] = n11;
-        G[(int64_t)qb * ld + pa] = n12;
-        G[(int64_t)pb * ld + qa] = n21;
-        G[(int64_t)qb * ld + qa] = n22;
-      }
-      // V <- V J
-      const int32_t nv = m * half;
-      for (int32_t task = t; task < nv; task += kJacobiThreads) {
-        const int32_t i = task / half, k = task - i * half;
-        if (!sh.rot[k]) continue;
-        const int32_t p = sh.p[k], q = sh.q[k];
-        const double cs = sh.c[k], sn = sh.s[k];
-        const double v1 = V[(int64_t)i * ld + p], v2 = V[(int64_t)i * ld + q];
-        V[(int64_t)i * ld + p] = cs * v1 - sn * v2;
-        V[(int64_t)i * ld + q] = sn * v1 + cs * v2;
-      }
-      if (!kLds) __threadfence_block();
-      __syncthreads();
-    }
-    const int32_t any = sh.any;
-    __syncthreads();
-    if (!any) break;
-  }
-  if (t == 0 && dsweeps) *dsweeps = sweep;
-}
-
-__global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(int32_t m, double* __restrict__ G,
-                                                               double* __restrict__ V,
-                                                               double* __restrict__ w,
-                                                               int32_t* dsweeps) {
-  HIP_DYNAMIC_SHARED(double, lds);
-  __shared__ JacobiShared<kJacobiLdsMax / 2> sh;
-  const int32_t n = m + (m & 1);
-  const int64_t ld = n + 1;
-  double* Gs = lds;
-  double* Vs = lds + (int64_t)n * ld;
-  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += kJacobiThreads) {
-    const int32_t i = (int32_t)(e / n), j = (int32_t)(e % n);
-    Gs[i * ld + j] = (i < m && j < m) ? G[(int64_t)i * m + j] : 0.0;
-    Vs[i * ld + j] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  jacobi_run<true, kJacobiLdsMax / 2>(m, n, Gs, Vs, ld, sh, dsweeps);
-  __syncthreads();
-  for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += kJacobiThreads) {
-    const int32_t i = (int32_t)(e / m), j = (int32_t)(e % m);
-    V[e] = Vs[i * ld + j];
-  }
-  for (int32_t i = threadIdx.x; i < m; i += kJacobiThreads) w[i] = Gs[i * ld + i];
-}
-
-// Global-memory variant: G and V are n x n buffers (n = m rounded up to
-// even), ld = n; the caller provides them padded.
-__global__ __launch_bounds__(kJacobiThreads) void k_jacobi_global(int32_t m, double* __restrict__ G,
-                                                                  double* __restrict__ V,
-                                                                  double* __restrict__ w,
-                                                                  int32_t* dsweeps) {
-  __shared__ JacobiShared<kJacobiGlobalHalf> sh;
-  const int32_t n = m + (m & 1);
-  jacobi_run<false, kJacobiGlobalHalf>(m, n, G, V, n, sh, dsweeps);
-  __syncthreads();
-  for (int32_t i = threadIdx.x; i < m; i += kJacobiThreads) w[i] = G[(int64_t)i * n + i];
-}
-
-// repack G (m x m, ld m) into an n x n padded buffer with V = I (in place is
-// not possible; src and dst differ)
-__global__ void k_pad_square(int32_t m, int32_t n, const double* __restrict__ src,
-                             double* __restrict__ G, double* __restrict__ V) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)n * n) return;
-  const int32_t i = (int32_t)(e / n), j = (int32_t)(e % n);
-  G[e] = (i < m && j < m) ? src[(int64_t)i * m + j] : 0.0;
-  V[e] = (i == j) ? 1.0 : 0.0;
-}
-
-__global__ void k_unpad_square(int32_t m, int32_t n, const double* __restrict__ V,
-                               double* __restrict__ dst) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)m * m) return;
-  const int32_t i = (int32_t)(e / m), j = (int32_t)(e % m);
-  dst[e] = V[(int64_t)i * n + j];
 }
 
 // ---------------------------------------------------------------------------
@@ -582,11 +399,31 @@ inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs
 template <typename TB, typename TE, typename TD>
 hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk, double alpha,
                 const double* A, View va, const TB* B, View vb, double beta, const TE* E, View ve,
-                TD* D, View vd, int64_t dz, double* colpart, double* bnorm) {
+                TD* D, View vd, int64_t dz, double* colpart, double* bnorm, GemmWs ws) {
   if (N <= 0) return hipSuccess;
+  const int32_t gx = (N + 63) / 64, gy = gemm_row_blocks(M);
+  const int64_t tiles = (int64_t)gx * gy;
+  if ((kchunk <= 0 || kchunk >= K) && ws.p && !bnorm && M > 0 && K >= 512 && tiles < 96) {
+    int64_t S = std::min<int64_t>((K + 255) / 256, std::max<int64_t>(2, 192 / tiles));
+    const int64_t MN = (int64_t)M * N;
+    S = std::min<int64_t>(S, ws.len / std::max<int64_t>(MN, 1));
+    if (S >= 2) {
+      int64_t chunk = (K + S - 1) / S;
+      chunk = ((chunk + 15) / 16) * 16;
+      S = (K + chunk - 1) / chunk;
+      hipLaunchKernelGGL((k_gemm<TB, double, double>), dim3(gx, gy, (unsigned)S), dim3(256), 0, st, M, N, K,
+                         (int32_t)chunk, 1.0, A, va, B, vb, 0.0, (const double*)nullptr, View(), ws.p,
+                         row_major(N), MN, (double*)nullptr, (double*)nullptr);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_splitk_finish<TE, TD>), dim3(gx, gy), dim3(256), 0, st, M, N, (int32_t)S, ws.p,
+                         alpha, beta, E, ve, D, vd, colpart);
+      return hipGetLastError();
+    }
+  }
   if (kchunk <= 0) kchunk = K > 0 ? K : 1;
   const int32_t S = K > 0 ? (K + kchunk - 1) / kchunk : 1;
-  dim3 grid((unsigned)((N + 63) / 64), (unsigned)gemm_row_blocks(M), (unsigned)S);
+  dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)S);
   hipLaunchKernelGGL((k_gemm<TB, TE, TD>), grid, dim3(256), 0, st, M, N, K, kchunk, alpha, A, va, B,
                      vb, beta, E, ve, D, vd, dz, colpart, bnorm);
   return hipGetLastError();
@@ -595,7 +432,7 @@ hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk,
 #define TTICE_GEMM_INST(TB, TE, TD)                                                                  \
   template hipError_t gemm<TB, TE, TD>(hipStream_t, int32_t, int32_t, int32_t, int32_t, double,      \
                                        const double*, View, const TB*, View, double, const TE*, View, \
-                                       TD*, View, int64_t, double*, double*);
+                                       TD*, View, int64_t, double*, double*, GemmWs);
 TTICE_GEMM_INST(double, double, double)
 TTICE_GEMM_INST(float, double, double)
 TTICE_GEMM_INST(double, float, double)
@@ -627,37 +464,6 @@ hipError_t gram_reduce(hipStream_t st, const double* part, int32_t S, int32_t m,
   const int64_t mm = (int64_t)m * m;
   if (mm == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks(mm, 256)), dim3(256), 0, st, part, S, m, G);
-  return hipGetLastError();
-}
-
-int32_t sym_eig_lds_max() { return kJacobiLdsMax; }
-
-// Work buffers for the global-memory path live right after G and V: the
-// caller allocates G and V with room for n*n doubles each (n = m + (m & 1))
-// plus an extra n*n each for the padded copies.
-hipError_t sym_eig(hipStream_t st, int32_t m, double* G, double* V, double* w, int32_t* dsweeps) {
-  if (m <= 0) return hipSuccess;
-  if (m <= kJacobiLdsMax) {
-    const int32_t n = m + (m & 1);
-    const size_t lds = (size_t)2 * n * (n + 1) * sizeof(double);
-    static bool attr_set = false;
-    if (!attr_set) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_lds,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)((size_t)2 * 96 * 97 * sizeof(double)));
-      if (e != hipSuccess) return e;
-      attr_set = true;
-    }
-    hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(kJacobiThreads), lds, st, m, G, V, w, dsweeps);
-    return hipGetLastError();
-  }
-  const int32_t n = m + (m & 1);
-  double* Gp = G + (int64_t)n * n;  // padded copies (caller-provided room)
-  double* Vp = V + (int64_t)n * n;
-  hipLaunchKernelGGL(k_pad_square, dim3(nblocks((int64_t)n * n, 256)), dim3(256), 0, st, m, n, G, Gp,
-                     Vp);
-  hipLaunchKernelGGL(k_jacobi_global, dim3(1), dim3(kJacobiThreads), 0, st, m, Gp, Vp, w, dsweeps);
-  hipLaunchKernelGGL(k_unpad_square, dim3(nblocks((int64_t)m * m, 256)), dim3(256), 0, st, m, n, Vp, V);
   return hipGetLastError();
 }
 

@@ -106,8 +106,8 @@ struct ttice_state {
   int64_t n_total = 0;
 
   // workspace
-  DevBuf z[2], rbuf, colpart, bnorm, fres, fy2, e2acc, scal, gpart, gram, V, w, order, lam, tail,
-      selres, W, W2, T, S, dlist, coefscratch, sweeps;
+  DevBuf z[2], rbuf, colpart, bnorm, fres, fy2, e2acc, scal, gpart, gram, tri, order, lam, tail, W, W2, T,
+      S, dlist, eigws, splitk;
   double* hs = nullptr;  // pinned host scalars (64 doubles)
 
   ~ttice_state();
@@ -118,6 +118,8 @@ struct ttice_state {
     return c;
   }
   int grow_core(Core& c, int64_t need_rows, int64_t need_cols, int64_t keep_rows, int64_t keep_cols);
+  // scratch for K-split products (allocated once per state)
+  GemmWs gws() { return GemmWs{as<double>(splitk), (int64_t)(splitk.bytes / sizeof(double))}; }
   int sync_scalars(int n);
   template <typename TIn>
   int core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, double tol_in, int64_t* rk_pend,
@@ -135,9 +137,8 @@ ttice_state::~ttice_state() {
   for (int i = 0; i < TTICE_MAX_D; ++i)
     if (U[i].p) (void)hipFree(U[i].p);
   if (Gt.p) (void)hipFree(Gt.p);
-  DevBuf* bufs[] = {&z[0], &z[1], &rbuf, &colpart, &bnorm, &fres, &fy2, &e2acc, &scal, &gpart,
-                    &gram, &V, &w, &order, &lam, &tail, &selres, &W, &W2, &T, &S, &dlist,
-                    &coefscratch, &sweeps};
+  DevBuf* bufs[] = {&z[0], &z[1], &rbuf, &colpart, &bnorm, &fres, &fy2, &e2acc, &scal, &gpart, &gram,
+                    &tri, &order, &lam, &tail, &W, &W2, &T, &S, &dlist, &eigws, &splitk};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (hs) (void)hipHostFree(hs);
@@ -250,11 +251,11 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
     if (zin_is_input) {
       CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
                                  vUt, (const TIn*)zin, vz, 0.0, (const TIn*)nullptr, View(), out, vout,
-                                 0, nullptr, bn)));
+                                 0, nullptr, bn, gws())));
     } else {
       CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0,
                                        Ui.p, vUt, (const double*)zin, vz, 0.0, (const double*)nullptr,
-                                       View(), out, vout, 0, nullptr, bn)));
+                                       View(), out, vout, 0, nullptr, bn, gws())));
     }
 
     const double occupancy = rows > 0 ? (double)r / (double)rows : 1.0;
@@ -281,11 +282,11 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       if (zin_is_input) {
         CK((gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r, (int32_t)std::max<int64_t>(r, 1),
                                       -1.0, Ui.p, vU, out, vout, 1.0, (const TIn*)zin, vz, rout, vr, 0,
-                                      as<double>(colpart), nullptr)));
+                                      as<double>(colpart), nullptr, gws())));
       } else {
         CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
                                          (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, vU, out, vout, 1.0,
-                                         (const double*)zin, vz, rout, vr, 0, as<double>(colpart), nullptr)));
+                                         (const double*)zin, vz, rout, vr, 0, as<double>(colpart), nullptr, gws())));
       }
       CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
       CK(total_sum(st, as<double>(fres), N, as<double>(scal)));
@@ -307,11 +308,11 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
           CK((zin_is_input
                   ? gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
                                               (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, vU, out, vout, 1.0,
-                                              (const TIn*)zin, vz, as<double>(rbuf), vr, 0, nullptr, nullptr)
+                                              (const TIn*)zin, vz, as<double>(rbuf), vr, 0, nullptr, nullptr, gws())
                   : gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
                                                  (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, vU, out, vout,
                                                  1.0, (const double*)zin, vz, as<double>(rbuf), vr, 0, nullptr,
-                                                 nullptr)));
+                                                 nullptr, gws())));
         }
         // Truncated SVD of R_cat = [R(1) ... R(N)] (eq:svdfirst) via the
         // eigendecomposition of its Gram matrix: left (rows x rows) when
@@ -323,35 +324,27 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         const View vRt = transposed(vr);      // Ncol x rows
         const int32_t kchunk = gram_kchunk((int32_t)m, K);
         const int64_t Sg = (K + kchunk - 1) / kchunk;
-        const int64_t npad = m + (m & 1);
         CKS(ensure(gpart, (size_t)Sg * m * m * sizeof(double)));
-        CKS(ensure(gram, (size_t)2 * npad * npad * sizeof(double)));
-        CKS(ensure(V, (size_t)2 * npad * npad * sizeof(double)));
-        CKS(ensure(w, (size_t)m * sizeof(double)));
+        CKS(ensure(gram, (size_t)m * m * sizeof(double)));
+        CKS(ensure(tri, (size_t)6 * m * sizeof(double)));  // d, e, tau, 2m scratch, w
         CKS(ensure(order, (size_t)m * sizeof(int32_t)));
         CKS(ensure(lam, (size_t)m * sizeof(double)));
         CKS(ensure(tail, (size_t)(m + 1) * sizeof(double)));
-        CKS(ensure(sweeps, 16));
+        double* dd = as<double>(tri);
+        double* ee = dd + m;
+        double* tauv = dd + 2 * m;
+        double* vp = dd + 3 * m;
+        double* wv = dd + 5 * m;
         CK((gemm<double, double, double>(st, (int32_t)m, (int32_t)m, (int32_t)K, kchunk, 1.0, as<double>(rbuf),
                                          left ? vR : vRt, as<double>(rbuf), left ? vRt : vR, 0.0,
                                          (const double*)nullptr, View(), as<double>(gpart), row_major(m),
                                          m * m, nullptr, nullptr)));
         CK(gram_reduce(st, as<double>(gpart), (int32_t)Sg, (int32_t)m, as<double>(gram)));
-        CK(sym_eig(st, (int32_t)m, as<double>(gram), as<double>(V), as<double>(w), as<int32_t>(sweeps)));
+        CK(sym_eigvals(st, (int32_t)m, as<double>(gram), dd, ee, tauv, vp, wv));
         const int64_t cap = rows - r;
-        CK(select_rank(st, (int32_t)m, as<double>(w), tol2, cap, as<int32_t>(order), as<double>(lam),
+        CK(select_rank(st, (int32_t)m, wv, tol2, cap, as<int32_t>(order), as<double>(lam),
                        as<double>(tail), as<double>(scal)));
         CKS(sync_scalars(4));
-#ifdef TTICE_EMU_DEBUG
-        {
-          std::vector<double> hw(m);
-          hipMemcpy(hw.data(), w.p, m * 8, hipMemcpyDeviceToHost);
-          fprintf(stderr, "level %d rows %ld Ncol %ld left %d m %ld tol2 %g rR %g w:", i, (long)rows, (long)Ncol, (int)left, (long)m, tol2, hs[0]);
-          for (int64_t q = 0; q < m && q < 20; ++q) fprintf(stderr, " %g", hw[q]);
-          std::vector<double> hg(m * m);
-          fprintf(stderr, "\n");
-        }
-#endif
         if (hs[3] != 0.0) return TTICE_EDEVICE;
         rR = (int64_t)hs[0];
         tail2 = hs[1];
@@ -359,20 +352,23 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         if (rR > 0) {
           CKS(ensure(W, (size_t)rows * rR * sizeof(double)));
           CKS(ensure(W2, (size_t)rows * rR * sizeof(double)));
+          CKS(ensure(eigws, (size_t)(8 * m + m * rR) * sizeof(double)));
           double* Wp = as<double>(W);
           double* W2p = as<double>(W2);
           const View vW = row_major(rR);
           if (left) {
-            CK(gather_columns(st, (int32_t)rows, (int32_t)rR, as<double>(V), (int32_t)m, as<int32_t>(order),
-                              as<double>(lam), false, Wp));
+            // eigenvectors of R R^T for the r_R largest eigenvalues
+            CK(sym_eigvecs(st, (int32_t)m, (int32_t)rR, dd, ee, wv, as<double>(gram), tauv, as<double>(eigws), Wp));
           } else {
-            // U_R = R V_r Sigma_r^{-1}
+            // U_R = R V_r Sigma_r^{-1} with V_r the eigenvectors of R^T R
             CKS(ensure(T, (size_t)Ncol * rR * sizeof(double)));
-            CK(gather_columns(st, (int32_t)Ncol, (int32_t)rR, as<double>(V), (int32_t)m, as<int32_t>(order),
+            CK(sym_eigvecs(st, (int32_t)m, (int32_t)rR, dd, ee, wv, as<double>(gram), tauv, as<double>(eigws),
+                           as<double>(W2)));
+            CK(gather_columns(st, (int32_t)Ncol, (int32_t)rR, as<double>(W2), (int32_t)rR, as<int32_t>(order),
                               as<double>(lam), true, as<double>(T)));
             CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)rR, (int32_t)Ncol, (int32_t)Ncol, 1.0,
                                              as<double>(rbuf), vR, as<double>(T), vW, 0.0,
-                                             (const double*)nullptr, View(), Wp, vW, 0, nullptr, nullptr)));
+                                             (const double*)nullptr, View(), Wp, vW, 0, nullptr, nullptr, gws())));
           }
           // Re-orthogonalise against U (two classical Gram-Schmidt passes)
           if (r > 0) {
@@ -380,10 +376,10 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
             for (int pass = 0; pass < 2; ++pass) {
               CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)rR, (int32_t)rows, (int32_t)rows, 1.0,
                                                Ui.p, vUt, Wp, vW, 0.0, (const double*)nullptr, View(),
-                                               as<double>(T), vW, 0, nullptr, nullptr)));
+                                               as<double>(T), vW, 0, nullptr, nullptr, gws())));
               CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)rR, (int32_t)r, (int32_t)r, -1.0,
                                                Ui.p, vU, as<double>(T), vW, 1.0, Wp, vW, Wp, vW, 0, nullptr,
-                                               nullptr)));
+                                               nullptr, gws())));
             }
           }
           // ... and among themselves: two Newton-Schulz steps towards the
@@ -392,10 +388,10 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
           for (int pass = 0; pass < 2; ++pass) {
             CK((gemm<double, double, double>(st, (int32_t)rR, (int32_t)rR, (int32_t)rows, (int32_t)rows, 1.0, Wp,
                                              transposed(vW), Wp, vW, 0.0, (const double*)nullptr, View(),
-                                             as<double>(S), vW, 0, nullptr, nullptr)));
+                                             as<double>(S), vW, 0, nullptr, nullptr, gws())));
             CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)rR, (int32_t)rR, (int32_t)rR, -0.5, Wp,
                                              vW, as<double>(S), vW, 1.5, Wp, vW, W2p, vW, 0, nullptr,
-                                             nullptr)));
+                                             nullptr, gws())));
             std::swap(Wp, W2p);
           }
           CK(sign_fix(st, (int32_t)rows, (int32_t)rR, Wp, rR));
@@ -429,12 +425,12 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
           if (zin_is_input) {
             CK((gemm<TIn, TIn, double>(st, (int32_t)rR, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0,
                                        Ui.p + r, vUt2, (const TIn*)zin, vz, 0.0, (const TIn*)nullptr, View(),
-                                       out + r * cols, vout2, 0, nullptr, nullptr)));
+                                       out + r * cols, vout2, 0, nullptr, nullptr, gws())));
           } else {
             CK((gemm<double, double, double>(st, (int32_t)rR, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0,
                                              Ui.p + r, vUt2, (const double*)zin, vz, 0.0,
                                              (const double*)nullptr, View(), out + r * cols, vout2, 0,
-                                             nullptr, nullptr)));
+                                             nullptr, nullptr, gws())));
           }
           rk_pend[i + 1] = r + rR;
         }
@@ -482,11 +478,11 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
     if (zin_is_input)
       CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
                                  transposed(row_major(Ui.ld)), (const TIn*)zin, vz, 0.0, (const TIn*)nullptr,
-                                 View(), out, vout, 0, nullptr, bn)));
+                                 View(), out, vout, 0, nullptr, bn, gws())));
     else
       CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
                                        transposed(row_major(Ui.ld)), (const double*)zin, vz, 0.0,
-                                       (const double*)nullptr, View(), out, vout, 0, nullptr, bn)));
+                                       (const double*)nullptr, View(), out, vout, 0, nullptr, bn, gws())));
     if (bn) CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, y2_out));
     if (err2_out) {
       const int32_t MB = gemm_row_blocks((int32_t)rows);
@@ -496,12 +492,12 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
         CK((gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
                                       (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out, vout,
                                       1.0, (const TIn*)zin, vz, (double*)nullptr, View(), 0,
-                                      as<double>(colpart), nullptr)));
+                                      as<double>(colpart), nullptr, gws())));
       else
         CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
                                          (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out,
                                          vout, 1.0, (const double*)zin, vz, (double*)nullptr, View(), 0,
-                                         as<double>(colpart), nullptr)));
+                                         as<double>(colpart), nullptr, gws())));
       CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
       CK(accumulate(st, err2_out, as<double>(fres), N));
     }
@@ -522,6 +518,7 @@ int ttice_state::update_impl(const TIn* batch, int64_t N, ttice_update_info* inf
   CKS(ensure(z[0], (size_t)N * P * sizeof(double)));
   CKS(ensure(z[1], (size_t)N * P * sizeof(double)));
   CKS(ensure(scal, 64 * sizeof(double)));
+  CKS(ensure(splitk, ((size_t)1 << 20) * sizeof(double)));
   CKS(grow_core(Gt, n_total + N, std::max<int64_t>(rk[d], 1), n_total, rk[d]));
 
   int64_t rkp[TTICE_MAX_D + 1];
@@ -604,6 +601,7 @@ int ttice_state::reconstruct_impl(int64_t first, int64_t count, TD* out) {
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(count, ((int64_t)1 << 26) / P));
   CKS(ensure(z[0], (size_t)chunk * P * sizeof(double)));
   CKS(ensure(z[1], (size_t)chunk * P * sizeof(double)));
+  CKS(ensure(splitk, ((size_t)1 << 20) * sizeof(double)));
   for (int64_t f0 = 0; f0 < count; f0 += chunk) {
     const int64_t cnt = std::min(chunk, count - f0);
     // level d-1 input: the last-core rows of the chosen tensors
@@ -620,13 +618,13 @@ int ttice_state::reconstruct_impl(int64_t first, int64_t count, TD* out) {
         TD* o = out + f0 * P;
         CK((gemm<double, double, TD>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r, (int32_t)std::max<int64_t>(r, 1),
                                      1.0, U[i].p, row_major(U[i].ld), xin, vx, 0.0, (const double*)nullptr,
-                                     View(), o, unfolding(cols, P), 0, nullptr, nullptr)));
+                                     View(), o, unfolding(cols, P), 0, nullptr, nullptr, gws())));
       } else {
         double* o = as<double>(z[i % 2]);
         CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
                                          (int32_t)std::max<int64_t>(r, 1), 1.0, U[i].p, row_major(U[i].ld), xin,
                                          vx, 0.0, (const double*)nullptr, View(), o, unfolding(cols, P), 0,
-                                         nullptr, nullptr)));
+                                         nullptr, nullptr, gws())));
         xin = o;
         // next level reads per frame (r_i x cols_{i-1}) = (rk[i]) x (dims[i]*cols)
         vx = unfolding(dims[i] * cols, P);
@@ -766,6 +764,7 @@ int ttice_project(ttice_state* st, const void* batch, int64_t n, int32_t dtype, 
   int rc = ensure(st->z[0], (size_t)n * st->P * sizeof(double));
   if (rc == TTICE_OK) rc = ensure(st->z[1], (size_t)n * st->P * sizeof(double));
   if (rc == TTICE_OK) rc = ensure(st->scal, 64 * sizeof(double));
+  if (rc == TTICE_OK) rc = ensure(st->splitk, ((size_t)1 << 20) * sizeof(double));
   int nonfinite = 0;
   if (rc == TTICE_OK) {
     const int64_t rd = std::max<int64_t>(st->rk[st->d], 1);

@@ -21,10 +21,11 @@ long long g_fail_alloc_after = -1;
 
 namespace {
 constexpr size_t kStack = 256 * 1024;
+enum State { RUN = 0, AT_BLOCK = 1, AT_WAVE = 2, DONE = 3 };
 struct Fiber {
   ucontext_t ctx;
   char* stack = nullptr;
-  bool done = false;
+  int state = RUN;
 };
 ucontext_t sched_ctx;
 std::vector<Fiber> fibers;
@@ -55,7 +56,7 @@ void fiber_entry() {
   __sanitizer_finish_switch_fiber(nullptr, &sched_bottom, &sched_size);
 #endif
   (*g_body)();
-  fibers[cur].done = true;
+  fibers[cur].state = DONE;
   to_scheduler(true);
 }
 
@@ -71,17 +72,82 @@ void resume(unsigned t) {
   __sanitizer_finish_switch_fiber(sched_fake, nullptr, nullptr);
 #endif
 }
+
+void wave_barrier() {
+  fibers[cur].state = AT_WAVE;
+  to_scheduler(false);
+}
+
+// Run every fiber of the block to completion, releasing block barriers when
+// every live thread waits at one and wave barriers when every live lane of
+// that wave waits at one.
+void run_block(unsigned nt) {
+  for (;;) {
+    bool progressed = false;
+    for (unsigned t = 0; t < nt; ++t)
+      if (fibers[t].state == RUN) {
+        resume(t);
+        progressed = true;
+      }
+    if (progressed) continue;
+    unsigned live = 0, at_block = 0;
+    for (unsigned t = 0; t < nt; ++t) {
+      if (fibers[t].state != DONE) ++live;
+      if (fibers[t].state == AT_BLOCK) ++at_block;
+    }
+    if (live == 0) return;
+    bool released = false;
+    for (unsigned w0 = 0; w0 < nt; w0 += 64) {
+      const unsigned w1 = std::min(nt, w0 + 64);
+      unsigned lv = 0, aw = 0;
+      for (unsigned t = w0; t < w1; ++t) {
+        if (fibers[t].state != DONE) ++lv;
+        if (fibers[t].state == AT_WAVE) ++aw;
+      }
+      if (aw > 0 && aw == lv) {
+        for (unsigned t = w0; t < w1; ++t)
+          if (fibers[t].state == AT_WAVE) fibers[t].state = RUN;
+        released = true;
+      }
+    }
+    if (released) continue;
+    if (at_block == live) {
+      if (live != nt) {
+        fprintf(stderr, "hipemu: __syncthreads reached by %u threads while %u exited\n", live, nt - live);
+        abort();
+      }
+      for (unsigned t = 0; t < nt; ++t) fibers[t].state = RUN;
+      continue;
+    }
+    fprintf(stderr, "hipemu: deadlock (%u live, %u at a block barrier, the rest at wave barriers)\n", live,
+            at_block);
+    abort();
+  }
+}
 }  // namespace
 
-void barrier() { to_scheduler(false); }
+void barrier() {
+  fibers[cur].state = AT_BLOCK;
+  to_scheduler(false);
+}
 
 double shfl_down(double v, int off) {
   const unsigned tid = cur;
   shfl_buf[tid] = v;
-  barrier();
+  wave_barrier();
   const unsigned lane = tid & 63u;
   const double r = (lane + (unsigned)off < 64u && tid + (unsigned)off < nthreads) ? shfl_buf[tid + off] : v;
-  barrier();
+  wave_barrier();
+  return r;
+}
+
+double shfl_xor(double v, int mask) {
+  const unsigned tid = cur;
+  shfl_buf[tid] = v;
+  wave_barrier();
+  const unsigned src = (tid & ~63u) | ((tid & 63u) ^ (unsigned)mask);
+  const double r = src < nthreads ? shfl_buf[src] : v;
+  wave_barrier();
   return r;
 }
 
@@ -107,22 +173,10 @@ void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& bo
           fibers[t].ctx.uc_stack.ss_sp = fibers[t].stack;
           fibers[t].ctx.uc_stack.ss_size = kStack;
           fibers[t].ctx.uc_link = nullptr;
-          fibers[t].done = false;
+          fibers[t].state = RUN;
           makecontext(&fibers[t].ctx, fiber_entry, 0);
         }
-        for (;;) {
-          unsigned alive = 0, finished = 0;
-          for (unsigned t = 0; t < nt; ++t) {
-            if (fibers[t].done) continue;
-            resume(t);
-            if (fibers[t].done) ++finished; else ++alive;
-          }
-          if (alive == 0) break;
-          if (finished != 0) {
-            fprintf(stderr, "hipemu: %u threads exited while %u wait at a barrier\n", finished, alive);
-            abort();
-          }
-        }
+        run_block(nt);
       }
 }
 

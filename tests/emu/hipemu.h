@@ -3,8 +3,8 @@
 // Never part of the product: the shipped library is built by hipcc for
 // gfx950.  Each block runs as blockDim host threads; __syncthreads is a
 // barrier over them; blocks run one after another; "device" memory is host
-// memory.  Wave operations (__shfl_down) assume 64-lane waves and are only
-// valid where the whole block calls them together (as the kernels do).
+// memory.  Wave operations (__shfl_down/__shfl_xor) assume 64-lane waves
+// and wave-uniform control flow: every live lane of the wave reaches them.
 #pragma once
 
 #include <stdint.h>
@@ -50,6 +50,7 @@ extern thread_local dim3 tl_threadIdx, tl_blockIdx;
 extern dim3 g_blockDim, g_gridDim;
 void barrier();
 double shfl_down(double v, int off);
+double shfl_xor(double v, int mask);
 void* dyn_lds();
 void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body);
 extern long long g_fail_alloc_after;  // failure injection: fail the k-th allocation (-1: never)
@@ -64,6 +65,11 @@ inline void __syncthreads() { hipemu::barrier(); }
 inline void __threadfence_block() {}
 inline void __threadfence() {}
 inline double __shfl_down(double v, int off, int = 64) { return hipemu::shfl_down(v, off); }
+inline double __shfl_xor(double v, int mask, int = 64) { return hipemu::shfl_xor(v, mask); }
+using std::copysign;
+using std::sin;
+using std::fmin;
+using std::fmax;
 
 using std::fma;
 using std::fabs;
