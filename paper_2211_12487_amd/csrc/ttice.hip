@@ -352,7 +352,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         if (rR > 0) {
           CKS(ensure(W, (size_t)rows * rR * sizeof(double)));
           CKS(ensure(W2, (size_t)rows * rR * sizeof(double)));
-          CKS(ensure(eigws, (size_t)(8 * m + m * rR) * sizeof(double)));
+          CKS(ensure(eigws, (size_t)7 * m * rR * sizeof(double)));
           double* Wp = as<double>(W);
           double* W2p = as<double>(W2);
           const View vW = row_major(rR);

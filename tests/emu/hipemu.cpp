@@ -151,6 +151,18 @@ double shfl_xor(double v, int mask) {
   return r;
 }
 
+unsigned long long ballot(int pred) {
+  const unsigned tid = cur;
+  shfl_buf[tid] = pred ? 1.0 : 0.0;
+  wave_barrier();
+  const unsigned w0 = tid & ~63u;
+  unsigned long long mask = 0;
+  for (unsigned l = 0; l < 64 && w0 + l < nthreads; ++l)
+    if (fibers[w0 + l].state != DONE && shfl_buf[w0 + l] != 0.0) mask |= 1ull << l;
+  wave_barrier();
+  return mask;
+}
+
 void* dyn_lds() { return dyn.data(); }
 
 void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body) {

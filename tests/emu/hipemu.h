@@ -51,6 +51,7 @@ extern dim3 g_blockDim, g_gridDim;
 void barrier();
 double shfl_down(double v, int off);
 double shfl_xor(double v, int mask);
+unsigned long long ballot(int pred);
 void* dyn_lds();
 void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body);
 extern long long g_fail_alloc_after;  // failure injection: fail the k-th allocation (-1: never)
@@ -66,6 +67,8 @@ inline void __threadfence_block() {}
 inline void __threadfence() {}
 inline double __shfl_down(double v, int off, int = 64) { return hipemu::shfl_down(v, off); }
 inline double __shfl_xor(double v, int mask, int = 64) { return hipemu::shfl_xor(v, mask); }
+inline unsigned long long __ballot(int pred) { return hipemu::ballot(pred); }
+inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 using std::copysign;
 using std::sin;
 using std::fmin;
