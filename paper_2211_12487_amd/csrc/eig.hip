@@ -1,10 +1,16 @@
 // Symmetric eigensolver for the truncated SVD of the residual (eq:svdfirst):
 // the Gram matrix G = R R^T (or R^T R) is reduced to tridiagonal form by
 // Householder reflections (one workgroup), all eigenvalues are found by
-// Sturm-sequence bisection (one thread per eigenvalue, returned in
+// Sturm-sequence multisection (one wave per eigenvalue, returned in
 // decreasing order), and only the eigenvectors that TT-ICE keeps are formed
 // by inverse iteration on the tridiagonal matrix followed by the
 // back-transformation with the stored reflectors.
+//
+// Everything here is latency-bound (one workgroup, long dependent chains),
+// so the working sets live in LDS wherever they fit: the trailing block of
+// the reduction once it is at most kTriLdsMax wide, the tridiagonal matrix
+// in the Sturm counts, the per-vector LU factors of inverse iteration and
+// chunks of reflectors in the back-transformation.
 #include "kernels.h"
 
 #include <math.h>
@@ -13,13 +19,14 @@ namespace ttice {
 namespace {
 
 constexpr int kTriThreads = 512;
-constexpr int kTriLdsMax = 124;  // (m x (m+1)) FP64 + vectors fit in 160 KB of LDS
 constexpr int kWaves = kTriThreads / 64;
+constexpr int kTriLdsMax = 124;      // trailing blocks up to this size are reduced in LDS
+constexpr int kEigMax = 4096;        // largest Gram matrix the solver accepts
+constexpr int kLdsDoubles = 19200;   // 150 KB of dynamic LDS per workgroup
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;  // valid in lane 0
-}
+// Wave-wide sum (DPP reduction of the device library; every lane gets it).
+extern "C" __device__ double __ockl_wfred_add_f64(double);
+__device__ __forceinline__ double wave_sum(double v) { return __ockl_wfred_add_f64(v); }
 
 // Sum over the block; every thread gets the result.  red: >= kWaves doubles.
 __device__ double block_sum(double v, double* red) {
@@ -30,49 +37,93 @@ __device__ double block_sum(double v, double* red) {
   __syncthreads();
   double s = 0.0;
   for (int i = 0; i < kWaves; ++i) s += red[i];
+  __syncthreads();
   return s;
 }
 
-// Householder tridiagonalisation (dsytd2 order) of the symmetric m x m
-// matrix A (row-major, row stride ld, full storage).  On exit d[0..m),
-// e[0..m-1) hold the tridiagonal matrix T = Q^T A Q, Q = H_0 ... H_{m-3},
-// H_k = I - tau[k] v_k v_k^T acting on indices k+1..m-1, and row k of A
-// holds v_k in columns k+1..m-1 (v_k[0] = 1).
+// sum_{i = i0, i0+G, ... < L} col[i*ld] * v[i], with eight independent
+// loads in flight (the loop is latency-bound, not bandwidth-bound).
+template <int G>
+__device__ __forceinline__ double col_dot(const double* col, int64_t ld, const double* v, int32_t i0, int32_t L) {
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int32_t i = i0;
+  for (; i + 7 * G < L; i += 8 * G) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = col[(int64_t)(i + u * G) * ld];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = fma(a[u], v[i + u * G], acc[u]);
+  }
+  for (; i < L; i += G) acc[0] = fma(col[(int64_t)i * ld], v[i], acc[0]);
+  return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+// col[i*ld] -= v_i w_j + w_i v_j for i = i0, i0+G, ... < L, where
+// w_i = p_i - gam v_i; eight rows per batch.
+template <int G>
+__device__ __forceinline__ void col_update(double* col, int64_t ld, const double* v, const double* p, double gam,
+                                           double vj, double wj, int32_t i0, int32_t L) {
+  int32_t i = i0;
+  for (; i + 7 * G < L; i += 8 * G) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = col[(int64_t)(i + u * G) * ld];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double vi = v[i + u * G];
+      a[u] = a[u] - vi * wj - (p[i + u * G] - gam * vi) * vj;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) col[(int64_t)(i + u * G) * ld] = a[u];
+  }
+  for (; i < L; i += G) {
+    const double vi = v[i];
+    col[(int64_t)i * ld] = col[(int64_t)i * ld] - vi * wj - (p[i] - gam * vi) * vj;
+  }
+}
+
+// Householder reflections k = 0 .. kend-1 (dsytd2 order) of the symmetric
+// n x n block A (row-major, row stride ld, full storage): d[k], e[k] of the
+// tridiagonal matrix, tau[k], and v_k stored in row k, columns k+1..n-1
+// (v_k[0] = 1).  H_k = I - tau_k v_k v_k^T acts on indices k+1..n-1.
 //
-// Three barriers per reflection: every thread derives (beta, tau) from the
-// shared x[0] and ||x[1:]||^2; wave w forms p_i = tau (A v)_i for rows
-// i = w, w + waves, ... (lanes across the row) and a partial p.v; the
-// rank-2 update A -= v w^T + w v^T (w = p - (tau/2)(p.v) v) is applied row
-// by row, and the wave that updates the first row of the trailing block also
-// stores the next reflection's x and ||x[1:]||^2.  vbuf: 4m doubles (two
-// alternating x vectors, the normalised v, and p), in LDS.
-template <bool kLds>
-__device__ void tridiag_run(int32_t m, double* A, int64_t ld, double* vbuf, double* red, double* sc,
-                            double* d, double* e, double* tau) {
+// Threads form G groups of NC = 512/G: in the matrix-vector product
+// p = tau A v, thread (g, c) sums rows i = g (mod G) of columns c, c+NC, ...
+// (no shuffles; G partial sums per column in LDS); the rank-2 update
+// A -= v w^T + w v^T with w = p - (tau/2)(p.v) v uses the same layout, and
+// group 0 (which updates row 0 of the trailing block) also stores the next
+// reflection's x and ||x[1:]||^2.  Four barriers per reflection.
+// vbuf: 4n doubles (+ G*n when G > 1), in LDS.  red2: kWaves doubles.
+template <int G, bool kLds>
+__device__ void tri_steps(int32_t n, double* A, int64_t ld, int32_t kend, double* vbuf, double* red,
+                          double* red2, double* d, double* e, double* tau) {
+  constexpr int NC = kTriThreads / G;
+  constexpr int W0 = NC / 64;  // waves in group 0
   const int t = threadIdx.x;
   const int lane = t & 63, wid = t >> 6;
-  double* va = vbuf;          // x of the current reflection (read only in the step)
-  double* vb = vbuf + m;      // x of the next reflection
-  double* vn = vbuf + 2 * m;  // v = [1, x[1:] / (x[0] - beta)]
-  double* p = vbuf + 3 * m;
-  // sc[k & 1] holds ||x[1:]||^2 of reflection k (written during step k-1)
-  if (m >= 3) {
-    // x of the first reflection: row 0, columns 1..m-1
+  const int g = t / NC, c0 = t % NC;
+  double* va = vbuf;          // x of the current reflection (read only during the step)
+  double* vb = vbuf + n;      // x of the next reflection
+  double* vn = vbuf + 2 * n;  // v = [1, x[1:] / (x[0] - beta)]
+  double* p = vbuf + 3 * n;
+  double* part = vbuf + 4 * n;  // G x n partial sums (G > 1)
+  if (kend <= 0) return;
+  {
     double s = 0.0;
-    for (int32_t i = t; i < m - 1; i += kTriThreads) {
+    for (int32_t i = t; i < n - 1; i += kTriThreads) {
       const double x = A[1 + i];
       va[i] = x;
       if (i > 0) s = fma(x, x, s);
     }
     s = block_sum(s, red);
-    if (t == 0) sc[0] = s;
+    if (t < kWaves) red2[t] = (t == 0) ? s : 0.0;
     __syncthreads();
   }
-  for (int32_t k = 0; k + 2 < m; ++k) {
-    const int32_t L = m - k - 1;
+  for (int32_t k = 0; k < kend; ++k) {
+    const int32_t L = n - k - 1;
     double* row = A + (int64_t)k * ld + (k + 1);
-    const double sigma = sc[k & 1];
-    double* snext = sc + ((k + 1) & 1);
+    double sigma = 0.0;
+    for (int w = 0; w < W0; ++w) sigma += red2[w];
     const double alpha = va[0];
     double beta, tk, scale;
     if (sigma == 0.0) {
@@ -94,115 +145,148 @@ __device__ void tridiag_run(int32_t m, double* A, int64_t ld, double* vbuf, doub
       vn[i] = vi;
       row[i] = vi;  // v_k kept for the back-transformation
     }
-    __syncthreads();  // (1) v complete
+    __syncthreads();  // (1) v complete; every thread has read red2 and va[0]
     double* sub = A + (int64_t)(k + 1) * ld + (k + 1);
+    double sn = 0.0;
     if (tk != 0.0) {
       double pvw = 0.0;
-      for (int32_t i = wid; i < L; i += kWaves) {
-        const double* ri = sub + (int64_t)i * ld;
-        double acc = 0.0;
-        for (int32_t j = lane; j < L; j += 64) acc = fma(ri[j], vn[j], acc);
-        acc = wave_sum(acc);
-        if (lane == 0) {
-          p[i] = tk * acc;
-          pvw = fma(tk * acc, vn[i], pvw);
+      if (G == 1) {
+        for (int32_t j = c0; j < L; j += NC) {
+          const double pj = tk * col_dot<1>(sub + j, ld, vn, 0, L);
+          p[j] = pj;
+          pvw = fma(pj, vn[j], pvw);
         }
-      }
-      if (lane == 0) red[wid] = pvw;
-      __syncthreads();  // (2) p and the partial p.v complete
-      double pv = 0.0;
-      for (int i = 0; i < kWaves; ++i) pv += red[i];
-      const double gam = 0.5 * tk * pv;
-      for (int32_t i = wid; i < L; i += kWaves) {
-        double* ri = sub + (int64_t)i * ld;
-        const double vi = vn[i], wi = p[i] - gam * vi;
-        double sn = 0.0;
-        for (int32_t j = lane; j < L; j += 64) {
-          const double a = ri[j] - vi * (p[j] - gam * vn[j]) - wi * vn[j];
-          ri[j] = a;
-          if (i == 0 && j >= 1) {
-            vb[j - 1] = a;
-            if (j >= 2) sn = fma(a, a, sn);
+        __syncthreads();  // (2)
+      } else {
+        for (int32_t j = c0; j < L; j += NC) part[g * n + j] = col_dot<G>(sub + j, ld, vn, g, L);
+        __syncthreads();  // (2) partial sums complete
+        if (g == 0)
+          for (int32_t j = c0; j < L; j += NC) {
+            double acc = 0.0;
+            for (int gg = 0; gg < G; ++gg) acc += part[gg * n + j];
+            const double pj = tk * acc;
+            p[j] = pj;
+            pvw = fma(pj, vn[j], pvw);
           }
+      }
+      if (g == 0) {
+        pvw = wave_sum(pvw);
+        if (lane == 0) red[wid] = pvw;
+      }
+      __syncthreads();  // (3) p and the partial p.v complete
+      double pv = 0.0;
+      for (int w = 0; w < W0; ++w) pv += red[w];
+      const double gam = 0.5 * tk * pv;
+      for (int32_t j = c0; j < L; j += NC) {
+        const double vj = vn[j], wj = p[j] - gam * vj;
+        if (g == 0 && j >= 1) {  // row 0 of the block: also the next reflection's x
+          const double nv = sub[j] - vn[0] * wj - (p[0] - gam * vn[0]) * vj;
+          sub[j] = nv;
+          vb[j - 1] = nv;
+          if (j >= 2) sn = fma(nv, nv, sn);
         }
-        if (i == 0) {
-          sn = wave_sum(sn);
-          if (lane == 0) *snext = sn;
-        }
+        col_update<G>(sub + j, ld, vn, p, gam, vj, wj, (g == 0 && j >= 1) ? G : g, L);
       }
     } else {
-      // no reflection: the next x is row k+1 as it stands
-      if (wid == 0) {
-        double sn = 0.0;
-        for (int32_t j = lane; j < L; j += 64)
+      __syncthreads();  // keep the barrier count uniform
+      __syncthreads();
+      if (g == 0)
+        for (int32_t j = c0; j < L; j += NC)
           if (j >= 1) {
             const double a = sub[j];
             vb[j - 1] = a;
             if (j >= 2) sn = fma(a, a, sn);
           }
-        sn = wave_sum(sn);
-        if (lane == 0) *snext = sn;
-      }
+    }
+    if (g == 0) {
+      sn = wave_sum(sn);
+      if (lane == 0) red2[wid] = sn;
     }
     if (!kLds) __threadfence_block();
-    __syncthreads();  // (3) update, next x and its norm complete
+    __syncthreads();  // (4) update, next x and its norm complete
     double* tmp = va;
     va = vb;
     vb = tmp;
   }
-  if (t == 0) {
-    if (m >= 2) {
-      d[m - 2] = A[(int64_t)(m - 2) * ld + (m - 2)];
-      e[m - 2] = A[(int64_t)(m - 2) * ld + (m - 1)];
-      tau[m - 2] = 0.0;
+}
+
+// The last 2x2 block of the tridiagonal matrix once all reflections are done.
+__device__ void tri_tail(int32_t n, const double* A, int64_t ld, double* d, double* e, double* tau) {
+  if (threadIdx.x == 0) {
+    if (n >= 2) {
+      d[n - 2] = A[(int64_t)(n - 2) * ld + (n - 2)];
+      e[n - 2] = A[(int64_t)(n - 2) * ld + (n - 1)];
+      tau[n - 2] = 0.0;
     }
-    d[m - 1] = A[(int64_t)(m - 1) * ld + (m - 1)];
-    tau[m - 1] = 0.0;
+    d[n - 1] = A[(int64_t)(n - 1) * ld + (n - 1)];
+    tau[n - 1] = 0.0;
   }
-  __syncthreads();
 }
 
-__global__ __launch_bounds__(kTriThreads) void k_tridiag_lds(int32_t m, double* __restrict__ A,
-                                                             double* __restrict__ d, double* __restrict__ e,
-                                                             double* __restrict__ tau) {
+// Tridiagonalise A (m x m, row-major, ld = m) in place.  Reflections whose
+// trailing block is wider than kTriLdsMax run on A in global memory (one
+// thread per column); the remaining block is then copied to LDS and reduced
+// there.  The reflectors end up in A's rows either way.
+__global__ __launch_bounds__(kTriThreads) void k_tridiag(int32_t m, double* __restrict__ A,
+                                                         double* __restrict__ d, double* __restrict__ e,
+                                                         double* __restrict__ tau) {
   HIP_DYNAMIC_SHARED(double, lds);
   __shared__ double red[kWaves];
-  __shared__ double sc[4];
-  const int64_t ld = m + 1;
+  __shared__ double red2[kWaves];
+  int32_t ksw = 0;
+  if (m > kTriLdsMax) {
+    ksw = m - kTriLdsMax;
+    tri_steps<1, false>(m, A, m, ksw, lds, red, red2, d, e, tau);
+  }
+  const int32_t n = m - ksw;
+  double* Ab = A + (int64_t)ksw * m + ksw;
+  const int64_t ld = n + 1;
   double* As = lds;
-  for (int32_t i = threadIdx.x >> 6; i < m; i += kWaves)
-    for (int32_t j = threadIdx.x & 63; j < m; j += 64) As[i * ld + j] = A[(int64_t)i * m + j];
+  for (int32_t i = threadIdx.x >> 6; i < n; i += kWaves)
+    for (int32_t j = threadIdx.x & 63; j < n; j += 64) As[i * ld + j] = Ab[(int64_t)i * m + j];
   __syncthreads();
-  tridiag_run<true>(m, As, ld, lds + (int64_t)m * ld, red, sc, d, e, tau);
-  // write the reflectors back (upper part of each row)
-  for (int32_t i = threadIdx.x >> 6; i < m; i += kWaves)
-    for (int32_t j = threadIdx.x & 63; j < m; j += 64) A[(int64_t)i * m + j] = As[i * ld + j];
+  tri_steps<4, true>(n, As, ld, n - 2, lds + (int64_t)n * ld, red, red2, d + ksw, e + ksw, tau + ksw);
+  tri_tail(n, As, ld, d + ksw, e + ksw, tau + ksw);
+  __syncthreads();
+  for (int32_t i = threadIdx.x >> 6; i < n; i += kWaves)
+    for (int32_t j = threadIdx.x & 63; j < n; j += 64) Ab[(int64_t)i * m + j] = As[i * ld + j];
 }
 
-__global__ __launch_bounds__(kTriThreads) void k_tridiag_global(int32_t m, double* __restrict__ A,
-                                                                double* __restrict__ d, double* __restrict__ e,
-                                                                double* __restrict__ tau) {
-  HIP_DYNAMIC_SHARED(double, lds);
-  __shared__ double red[kWaves];
-  __shared__ double sc[4];
-  tridiag_run<false>(m, A, m, lds, red, sc, d, e, tau);
+size_t tridiag_lds_bytes(int32_t m) {
+  const int32_t n = m < kTriLdsMax ? m : kTriLdsMax;
+  const size_t a = (size_t)n * (n + 1) + 8 * (size_t)n;  // block + vectors + 4 partial rows
+  const size_t b = m > kTriLdsMax ? 4 * (size_t)m : 0;   // global phase vectors
+  return (a > b ? a : b) * sizeof(double);
+}
+
+// 1/q to full double accuracy from the hardware reciprocal estimate and
+// one Newton step (the Sturm recurrence only needs q's sign and magnitude).
+__device__ __forceinline__ double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
 }
 
 // w[j] = j-th largest eigenvalue of T, j < m, by multisection on the Sturm
-// count: 16 lanes per eigenvalue each count the eigenvalues below one of 16
-// interior points of the current interval, and the interval shrinks 17-fold
-// per round (14 rounds take the Gershgorin interval below rounding level).
-constexpr int kSect = 16;
-constexpr int kBisectRounds = 14;
+// count (LDL^T pivots of T - x I, tiny pivots replaced by -pivmin): the 64
+// lanes of a wave each count the eigenvalues below one of 64 interior points
+// of the eigenvalue's current interval, so it shrinks 65-fold per round; 9
+// rounds take the Gershgorin interval below rounding level.
+constexpr int kSect = 64;
+constexpr int kBisectRounds = 9;
 
 __global__ __launch_bounds__(256) void k_bisect(int32_t m, const double* __restrict__ d,
                                                 const double* __restrict__ e, double* __restrict__ w) {
+  HIP_DYNAMIC_SHARED(double, lds);
   __shared__ double rlo[4], rhi[4], remax[4];
+  double* dS = lds;
+  double* e2S = lds + m;  // e2S[i] = e[i-1]^2, e2S[0] = 0
   const int t = threadIdx.x;
-  // Gershgorin interval of T (block reduction)
   double lo = 1e300, hi = -1e300, emax = 0.0;
   for (int32_t i = t; i < m; i += 256) {
     const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < m ? fabs(e[i]) : 0.0);
+    dS[i] = d[i];
+    e2S[i] = i > 0 ? e[i - 1] * e[i - 1] : 0.0;
     lo = fmin(lo, d[i] - r);
     hi = fmax(hi, d[i] + r);
     if (i + 1 < m) emax = fmax(emax, e[i] * e[i]);
@@ -228,43 +312,34 @@ __global__ __launch_bounds__(256) void k_bisect(int32_t m, const double* __restr
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax);
 
   const int32_t j = (int32_t)blockIdx.x * (256 / kSect) + t / kSect;  // eigenvalue index (descending)
-  const int32_t l = t % kSect;                                        // lane within the group
-  const bool valid = j < m;
+  const int32_t l = t % kSect;
+  if (j >= m) return;  // whole waves leave together
   const int32_t target = m - 1 - j;  // the target-th smallest (0-based)
-  const int gshift = (t & 63) / kSect * kSect;
   for (int round = 0; round < kBisectRounds; ++round) {
     const double h = (hi - lo) / (double)(kSect + 1);
     const double x = lo + h * (double)(l + 1);
     int32_t c = 0;
-    if (valid) {
-      double q = d[0] - x;
+    double q = 1.0;
+    for (int32_t i = 0; i < m; ++i) {
+      q = (dS[i] - x) - e2S[i] * recip(q);
       if (fabs(q) < pivmin) q = -pivmin;
       c += q < 0.0;
-      for (int32_t i = 1; i < m; ++i) {
-        const double ei = e[i - 1];
-        q = (d[i] - x) - (ei * ei) / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        c += q < 0.0;
-      }
     }
-    // lanes whose point has at most `target` eigenvalues below it; the count
-    // is monotone in x, so they are the group's first k lanes
-    const unsigned long long bal = __ballot(valid && c <= target);
-    const int k = __popcll((bal >> gshift) & ((1ull << kSect) - 1ull));
+    // the lanes whose point has at most `target` eigenvalues below it are
+    // the wave's first k lanes (the count is monotone in x)
+    const int k = __popcll(__ballot(c <= target));
     const double nlo = (k == 0) ? lo : lo + h * (double)k;
     const double nhi = (k == kSect) ? hi : lo + h * (double)(k + 1);
     lo = nlo;
     hi = nhi;
   }
-  if (valid && l == 0) w[j] = 0.5 * (lo + hi);
+  if (l == 0) w[j] = 0.5 * (lo + hi);
 }
 
-// Inverse iteration for eigenvalue lc of T (d, e) in per-vector scratch:
-// LU with partial pivoting of T - lc I (LAPACK gttrf order) into
-// DL/DD/DU/DU2/piv, then `iters` solves from the start vector in y, each
-// rescaled by its largest entry.  Serial (one thread).
-__device__ void tri_factor(int32_t m, const double* __restrict__ d, const double* __restrict__ e, double lc,
-                           double pert, double* DL, double* DD, double* DU, double* DU2, int32_t* piv) {
+// LU with partial pivoting of T - lc I (tridiagonal, LAPACK gttrf order)
+// into DL/DD/DU/DU2/piv; zero or tiny pivots become +-pert.  Serial.
+__device__ void tri_factor(int32_t m, const double* d, const double* e, double lc, double pert, double* DL,
+                           double* DD, double* DU, double* DU2, int32_t* piv) {
   for (int32_t i = 0; i < m; ++i) {
     DD[i] = d[i] - lc;
     if (i + 1 < m) {
@@ -295,10 +370,14 @@ __device__ void tri_factor(int32_t m, const double* __restrict__ d, const double
       piv[i] = i + 1;
     }
   }
-  for (int32_t i = 0; i < m; ++i)
+  for (int32_t i = 0; i < m; ++i) {
     if (fabs(DD[i]) < pert) DD[i] = DD[i] < 0.0 ? -pert : pert;
+    DD[i] = 1.0 / DD[i];  // stored as reciprocals for the solves
+  }
 }
 
+// y <- (T - lc I)^{-1} y from the factors (DD holds reciprocal pivots),
+// rescaled by its largest entry.
 __device__ void tri_solve(int32_t m, const double* DL, const double* DD, const double* DU, const double* DU2,
                           const int32_t* piv, double* y) {
   for (int32_t i = 0; i + 1 < m; ++i) {
@@ -310,34 +389,62 @@ __device__ void tri_solve(int32_t m, const double* DL, const double* DD, const d
       y[i + 1] = tmp;
     }
   }
-  y[m - 1] /= DD[m - 1];
-  if (m >= 2) y[m - 2] = (y[m - 2] - DU[m - 2] * y[m - 1]) / DD[m - 2];
-  for (int32_t i = m - 3; i >= 0; --i) y[i] = (y[i] - DU[i] * y[i + 1] - DU2[i] * y[i + 2]) / DD[i];
+  y[m - 1] *= DD[m - 1];
+  if (m >= 2) y[m - 2] = (y[m - 2] - DU[m - 2] * y[m - 1]) * DD[m - 2];
+  for (int32_t i = m - 3; i >= 0; --i) y[i] = (y[i] - DU[i] * y[i + 1] - DU2[i] * y[i + 2]) * DD[i];
   double mx = 0.0;
   for (int32_t i = 0; i < m; ++i) mx = fmax(mx, fabs(y[i]));
   const double s = mx > 0.0 ? 1.0 / mx : 1.0;
   for (int32_t i = 0; i < m; ++i) y[i] *= s;
 }
 
+__device__ __forceinline__ int64_t refl_offset(int32_t m, int32_t klo, int32_t k) {
+  // sum_{j=klo}^{k-1} (m - j - 1)
+  const int64_t q = k - klo;
+  return q * (m - 1 - klo) - (q * (q - 1)) / 2;
+}
+
 // Eigenvectors of T for the r largest eigenvalues lam[0..r) (decreasing) by
-// inverse iteration, then back-transformed x = Q y with the reflectors kept
-// in A's rows.  Vectors are computed concurrently, one thread each; vectors
-// whose eigenvalue lies within 1e-3 ||T|| of the previous one (a cluster) are
-// then recomputed in order with modified Gram-Schmidt against the earlier
-// members of their cluster at every iteration.  Output X (m x r, row-major).
-// One workgroup; ws: 6*m*r + m*r doubles.
+// inverse iteration, back-transformed x = Q y with the reflectors kept in A's
+// rows.  Every vector starts on its own thread (LU + three solves from a
+// fixed start vector); vectors whose eigenvalue lies within 1e-3 ||T|| of the
+// previous one (a cluster) are then recomputed in order with modified
+// Gram-Schmidt against the earlier members of their cluster at every
+// iteration.  The back-transformation applies the reflectors in chunks
+// staged through LDS, one wave per column.  Output X (m x r, row-major).
+// kLdsWork: the per-vector factors and Y live in LDS (else in ws, 7*m*r
+// doubles).
+template <bool kLdsWork>
 __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t r, const double* __restrict__ d,
                                                              const double* __restrict__ e,
                                                              const double* __restrict__ lam,
                                                              const double* __restrict__ A,
                                                              const double* __restrict__ tau,
                                                              double* __restrict__ ws, double* __restrict__ X) {
+  HIP_DYNAMIC_SHARED(double, lds);
   __shared__ double red[kWaves];
   const int t = threadIdx.x;
-  double* Y = ws + (int64_t)6 * m * r;  // column c at Y + c*m
+  double* dS = lds;
+  double* eS = lds + m;
+  double *Y, *scr, *refl;
+  int64_t refl_cap;
+  if (kLdsWork) {
+    Y = lds + 2 * m;
+    scr = Y + (int64_t)m * r;
+    refl = scr + (int64_t)6 * m * r;
+    refl_cap = kLdsDoubles - (2 * (int64_t)m + 7 * (int64_t)m * r);
+  } else {
+    Y = ws;
+    scr = ws + (int64_t)m * r;
+    refl = lds + 2 * m;
+    refl_cap = kLdsDoubles - 2 * (int64_t)m;
+  }
   double tn = 0.0;
-  for (int32_t i = t; i < m; i += kTriThreads)
+  for (int32_t i = t; i < m; i += kTriThreads) {
+    dS[i] = d[i];
+    eS[i] = (i + 1 < m) ? e[i] : 0.0;
     tn = fmax(tn, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < m ? fabs(e[i]) : 0.0));
+  }
   for (int off = 32; off > 0; off >>= 1) tn = fmax(tn, __shfl_down(tn, off, 64));
   if ((t & 63) == 0) red[t >> 6] = tn;
   __syncthreads();
@@ -350,12 +457,16 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
 
   // phase 1: every vector on its own thread
   for (int32_t c = t; c < r; c += kTriThreads) {
-    double* base = ws + (int64_t)6 * m * c;
+    double* base = scr + (int64_t)6 * m * c;
     double *DL = base, *DD = base + m, *DU = base + 2 * m, *DU2 = base + 3 * m;
     int32_t* piv = (int32_t*)(base + 4 * m);
     double* y = base + 5 * m;
-    tri_factor(m, d, e, lam[c], pert, DL, DD, DU, DU2, piv);
-    for (int32_t i = 0; i < m; ++i) y[i] = 1.0 + 0.5 * sin(0.7 * i + 1.3 * c + 0.1);
+    tri_factor(m, dS, eS, lam[c], pert, DL, DD, DU, DU2, piv);
+    // fixed, non-degenerate start vector (golden-ratio sequence in [0.5, 1.5))
+    for (int32_t i = 0; i < m; ++i) {
+      const double z = 0.6180339887498949 * (i + 1) + 0.7548776662466927 * (c + 1);
+      y[i] = 0.5 + (z - floor(z));
+    }
     for (int it = 0; it < 3; ++it) tri_solve(m, DL, DD, DU, DU2, piv, y);
     double nn = 0.0;
     for (int32_t i = 0; i < m; ++i) nn = fma(y[i], y[i], nn);
@@ -363,11 +474,10 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
     for (int32_t i = 0; i < m; ++i) Y[(int64_t)c * m + i] = y[i] * inv;
   }
   __syncthreads();
-  // phase 2: clustered vectors, in order, orthogonalised against their
-  // predecessors in the cluster
+  // phase 2: clustered vectors, in order
   for (int32_t c = 1; c < r; ++c) {
     if (!(fabs(lam[c - 1] - lam[c]) <= ortol)) continue;
-    double* base = ws + (int64_t)6 * m * c;
+    double* base = scr + (int64_t)6 * m * c;
     double *DL = base, *DD = base + m, *DU = base + 2 * m, *DU2 = base + 3 * m;
     int32_t* piv = (int32_t*)(base + 4 * m);
     double* y = Y + (int64_t)c * m;
@@ -390,58 +500,82 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
       __syncthreads();
     }
   }
-  // back-transformation x = H_0 H_1 ... H_{m-3} y, one wave per column
-  for (int32_t k = m - 3; k >= 0; --k) {
-    const double tk = tau[k];
-    if (tk == 0.0) continue;
-    const double* vk = A + (int64_t)k * m + (k + 1);  // v_k, length m-k-1, vk[0] = 1
-    const int32_t L = m - k - 1;
-    for (int32_t c = t >> 6; c < r; c += kWaves) {
-      double* yc = Y + (int64_t)c * m + (k + 1);
-      double acc = 0.0;
-      for (int32_t i = t & 63; i < L; i += 64) acc = fma(vk[i], yc[i], acc);
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-      const double f = tk * acc;
-      for (int32_t i = t & 63; i < L; i += 64) yc[i] -= f * vk[i];
+  // back-transformation x = H_0 H_1 ... H_{m-3} y, reflectors klo..khi
+  // staged in LDS per chunk
+  int32_t khi = m - 3;
+  while (khi >= 0) {
+    int32_t klo = khi;
+    int64_t used = m - khi - 1;
+    while (klo > 0 && used + (m - klo) <= refl_cap) {
+      --klo;
+      used += m - klo - 1;
+    }
+    for (int32_t k = klo; k <= khi; ++k) {
+      const int64_t off = refl_offset(m, klo, k);
+      const int32_t L = m - k - 1;
+      for (int32_t i = t; i < L; i += kTriThreads) refl[off + i] = A[(int64_t)k * m + k + 1 + i];
     }
     __syncthreads();
+    for (int32_t k = khi; k >= klo; --k) {
+      const double tk = tau[k];
+      if (tk == 0.0) continue;
+      const double* vk = refl + refl_offset(m, klo, k);
+      const int32_t L = m - k - 1;
+      for (int32_t c = t >> 6; c < r; c += kWaves) {
+        double* yc = Y + (int64_t)c * m + (k + 1);
+        double acc = 0.0;
+        for (int32_t i = t & 63; i < L; i += 64) acc = fma(vk[i], yc[i], acc);
+        const double f = tk * wave_sum(acc);
+        for (int32_t i = t & 63; i < L; i += 64) yc[i] -= f * vk[i];
+      }
+      __syncthreads();
+    }
+    khi = klo - 1;
   }
   for (int32_t i = t >> 6; i < m; i += kWaves)
     for (int32_t c = t & 63; c < r; c += 64) X[(int64_t)i * r + c] = Y[(int64_t)c * m + i];
 }
 
+hipError_t set_lds_attr(const void* f) {
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsDoubles * sizeof(double)));
+}
+
 }  // namespace
 
-int32_t sym_tri_lds_max() { return kTriLdsMax; }
+int32_t sym_eig_max() { return kEigMax; }
 
-hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* vp,
-                       double* w) {
+hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* w) {
   if (m <= 0) return hipSuccess;
-  if (m <= kTriLdsMax) {
-    const size_t lds = ((size_t)m * (m + 1) + 4 * (size_t)m) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-      hipError_t er = hipFuncSetAttribute((const void*)k_tridiag_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          (int)(((size_t)kTriLdsMax * (kTriLdsMax + 1) + 4 * kTriLdsMax) *
-                                                sizeof(double)));
-      if (er != hipSuccess) return er;
-      attr = true;
-    }
-    hipLaunchKernelGGL(k_tridiag_lds, dim3(1), dim3(kTriThreads), lds, st, m, A, d, e, tau);
-  } else {
-    hipLaunchKernelGGL(k_tridiag_global, dim3(1), dim3(kTriThreads), (size_t)4 * m * sizeof(double), st, m, A,
-                       d, e, tau);
+  if (m > kEigMax) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t er = set_lds_attr((const void*)k_tridiag);
+    if (er == hipSuccess) er = set_lds_attr((const void*)k_bisect);
+    if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_eigvecs<true>);
+    if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_eigvecs<false>);
+    if (er != hipSuccess) return er;
+    attr = true;
   }
+  hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kTriThreads), tridiag_lds_bytes(m), st, m, A, d, e, tau);
   hipError_t er = hipGetLastError();
   if (er != hipSuccess) return er;
-  hipLaunchKernelGGL(k_bisect, dim3((m + (256 / kSect) - 1) / (256 / kSect)), dim3(256), 0, st, m, d, e, w);
+  hipLaunchKernelGGL(k_bisect, dim3((m + (256 / kSect) - 1) / (256 / kSect)), dim3(256),
+                     (size_t)2 * m * sizeof(double), st, m, d, e, w);
   return hipGetLastError();
 }
 
 hipError_t sym_eigvecs(hipStream_t st, int32_t m, int32_t r, const double* d, const double* e,
                        const double* lam, const double* A, const double* tau, double* ws, double* X) {
   if (m <= 0 || r <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tri_eigvecs, dim3(1), dim3(kTriThreads), 0, st, m, r, d, e, lam, A, tau, ws, X);
+  const int64_t base_lds = 2 * (int64_t)m + 7 * (int64_t)m * r;
+  // all work in LDS when that leaves room for at least one reflector
+  if (base_lds + m <= kLdsDoubles) {
+    hipLaunchKernelGGL(k_tri_eigvecs<true>, dim3(1), dim3(kTriThreads), (size_t)kLdsDoubles * sizeof(double),
+                       st, m, r, d, e, lam, A, tau, ws, X);
+  } else {
+    hipLaunchKernelGGL(k_tri_eigvecs<false>, dim3(1), dim3(kTriThreads), (size_t)kLdsDoubles * sizeof(double),
+                       st, m, r, d, e, lam, A, tau, ws, X);
+  }
   return hipGetLastError();
 }
 

@@ -54,6 +54,30 @@ inline View unfolding(int64_t cols, int64_t fs, const int32_t* fidx = nullptr) {
   return v;
 }
 
+__device__ __forceinline__ int64_t row_off(const View& v, int32_t i) {
+  if (v.rpf == kUnframed) return (int64_t)i * v.rs;
+  const uint32_t f = (uint32_t)i / (uint32_t)v.rpf;
+  const uint32_t w = (uint32_t)i - f * (uint32_t)v.rpf;
+  return (int64_t)f * v.rfs + (int64_t)w * v.rs;
+}
+
+__device__ __forceinline__ int64_t col_off(const View& v, int32_t j) {
+  if (v.cpf == kUnframed) return (int64_t)j * v.cs;
+  const uint32_t f = (uint32_t)j / (uint32_t)v.cpf;
+  const uint32_t w = (uint32_t)j - f * (uint32_t)v.cpf;
+  const int64_t ff = v.cfidx ? (int64_t)v.cfidx[f] : (int64_t)f;
+  return ff * v.cfs + (int64_t)w * v.cs;
+}
+
+// Fused one-pass projection of narrow cores (r <= 64, U staged in LDS):
+// for every column j of Z (rows x Ncol view), C(:, j) = U^T z_j (view vc),
+// znorm2[j] = ||z_j||^2 and rho2[j] = ||z_j||^2 - ||C(:, j)||^2 (FP64).
+// Any output may be null.
+bool proj_fits(int32_t rows, int32_t r);
+template <typename TIn, typename TOut>
+hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
+                        const double* U, int64_t ldu, TOut* C, View vc, double* znorm2, double* rho2);
+
 // Scratch the product may use to split a long K-sum across workgroups.
 struct GemmWs {
   double* p = nullptr;
@@ -88,17 +112,16 @@ hipError_t accumulate(hipStream_t st, double* acc, const double* x, int64_t n);
 // (slice stride m*m), mirrored to be exactly symmetric.
 hipError_t gram_reduce(hipStream_t st, const double* part, int32_t S, int32_t m, double* G);
 
-// Eigenvalues of the symmetric m x m matrix A (row-major, ld = m): A is
-// reduced in place to tridiagonal form T = Q^T A Q (d, e; reflectors kept in
-// A's rows and tau) and w receives all eigenvalues in decreasing order
-// (Sturm bisection).  vp: 2m doubles of scratch (m > sym_tri_lds_max()).
-hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* vp,
-                       double* w);
+// Eigenvalues of the symmetric m x m matrix A (row-major, ld = m, m <=
+// sym_eig_max()): A is reduced in place to tridiagonal form T = Q^T A Q (d, e;
+// reflectors kept in A's rows and tau; d, e, tau: m doubles each) and w
+// receives all eigenvalues in decreasing order.
+hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* w);
 // Eigenvectors of A for its r largest eigenvalues lam[0..r) (from
 // sym_eigvals, decreasing): X (m x r, row-major).  ws: 7*m*r doubles.
 hipError_t sym_eigvecs(hipStream_t st, int32_t m, int32_t r, const double* d, const double* e,
                        const double* lam, const double* A, const double* tau, double* ws, double* X);
-int32_t sym_tri_lds_max();
+int32_t sym_eig_max();
 
 // Rank selection for SVD(R, eps) from the eigenvalues w (m) of the residual's
 // Gram matrix: order[t] = index of the t-th largest eigenvalue, lam[t] its

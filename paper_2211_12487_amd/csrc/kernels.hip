@@ -13,21 +13,6 @@ namespace ttice {
 
 namespace {
 
-__device__ __forceinline__ int64_t row_off(const View& v, int32_t i) {
-  if (v.rpf == kUnframed) return (int64_t)i * v.rs;
-  const uint32_t f = (uint32_t)i / (uint32_t)v.rpf;
-  const uint32_t w = (uint32_t)i - f * (uint32_t)v.rpf;
-  return (int64_t)f * v.rfs + (int64_t)w * v.rs;
-}
-
-__device__ __forceinline__ int64_t col_off(const View& v, int32_t j) {
-  if (v.cpf == kUnframed) return (int64_t)j * v.cs;
-  const uint32_t f = (uint32_t)j / (uint32_t)v.cpf;
-  const uint32_t w = (uint32_t)j - f * (uint32_t)v.cpf;
-  const int64_t ff = v.cfidx ? (int64_t)v.cfidx[f] : (int64_t)f;
-  return ff * v.cfs + (int64_t)w * v.cs;
-}
-
 // Shared epilogue of the tiled products: D(m,n) = alpha*acc + beta*E(m,n),
 // and per-column sums of D^2 over the tile's rows into colpart.
 template <typename TE, typename TD>

@@ -242,27 +242,61 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
     const View vUt = transposed(row_major(Ui.ld));
     const View vU = row_major(Ui.ld);
 
-    // C = U^T Z (eq:first_resid / eq:project_further, projection part)
-    double* bn = nullptr;
-    if (i == 0) {
-      CKS(ensure(bnorm, (size_t)Ncol * sizeof(double)));
-      bn = as<double>(bnorm);
-    }
-    if (zin_is_input) {
-      CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
-                                 vUt, (const TIn*)zin, vz, 0.0, (const TIn*)nullptr, View(), out, vout,
-                                 0, nullptr, bn, gws())));
-    } else {
-      CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0,
-                                       Ui.p, vUt, (const double*)zin, vz, 0.0, (const double*)nullptr,
-                                       View(), out, vout, 0, nullptr, bn, gws())));
-    }
-
     const double occupancy = rows > 0 ? (double)r / (double)rows : 1.0;
     const bool occ_skip = use_occ && occupancy >= tau;
     int64_t rR = 0;
     double rho2 = std::numeric_limits<double>::quiet_NaN(), tail2 = 0.0;
     double margin = std::numeric_limits<double>::infinity();
+
+    // C = U^T Z (eq:first_resid / eq:project_further, projection part) and
+    // the per-column energies of Z (level 1) and of the residual
+    double* bn = nullptr;
+    if (i == 0) {
+      CKS(ensure(bnorm, (size_t)Ncol * sizeof(double)));
+      bn = as<double>(bnorm);
+    }
+    const bool fused = proj_fits((int32_t)rows, (int32_t)r);
+    const int32_t MB = fused ? 1 : gemm_row_blocks((int32_t)rows);
+    CKS(ensure(colpart, (size_t)MB * Ncol * sizeof(double)));
+    CKS(ensure(fres, (size_t)N * sizeof(double)));
+    CKS(ensure(rbuf, (size_t)std::max<int64_t>(1, rows * Ncol) * sizeof(double)));
+    const View vr = unfolding(cols, rows * cols);
+    const bool small = rows * Ncol <= ((int64_t)1 << 22);
+    bool have_R = false;
+    double* cp = occ_skip ? nullptr : as<double>(colpart);
+    if (fused) {
+      // one pass: ||(I - U U^T) z||^2 = ||z||^2 - ||U^T z||^2 (orthonormal U)
+      if (zin_is_input)
+        CK((proj_columns<TIn, double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p,
+                                      Ui.ld, out, vout, bn, cp)));
+      else
+        CK((proj_columns<double, double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz,
+                                         Ui.p, Ui.ld, out, vout, bn, cp)));
+    } else {
+      if (zin_is_input) {
+        CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
+                                   vUt, (const TIn*)zin, vz, 0.0, (const TIn*)nullptr, View(), out, vout,
+                                   0, nullptr, bn, gws())));
+      } else {
+        CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0,
+                                         Ui.p, vUt, (const double*)zin, vz, 0.0, (const double*)nullptr,
+                                         View(), out, vout, 0, nullptr, bn, gws())));
+      }
+      if (!occ_skip) {
+        // R = Z - U C with per-column energies (eq:first_resid, eq:ithresidual)
+        double* rout = small ? as<double>(rbuf) : nullptr;
+        have_R = small;
+        if (zin_is_input) {
+          CK((gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r, (int32_t)std::max<int64_t>(r, 1),
+                                        -1.0, Ui.p, vU, out, vout, 1.0, (const TIn*)zin, vz, rout, vr, 0, cp,
+                                        nullptr, gws())));
+        } else {
+          CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
+                                           (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, vU, out, vout, 1.0,
+                                           (const double*)zin, vz, rout, vr, 0, cp, nullptr, gws())));
+        }
+      }
+    }
 
     if (i == 0 && tol2 < 0) {
       CKS(ensure(fy2, (size_t)N * sizeof(double)));
@@ -271,23 +305,6 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
     }
 
     if (!occ_skip) {
-      // R = Z - U C with per-column energies (eq:first_resid, eq:ithresidual)
-      const int32_t MB = gemm_row_blocks((int32_t)rows);
-      CKS(ensure(colpart, (size_t)MB * Ncol * sizeof(double)));
-      CKS(ensure(fres, (size_t)N * sizeof(double)));
-      const bool small = rows * Ncol <= ((int64_t)1 << 22);
-      CKS(ensure(rbuf, (size_t)std::max<int64_t>(1, rows * Ncol) * sizeof(double)));
-      const View vr = unfolding(cols, rows * cols);
-      double* rout = small ? as<double>(rbuf) : nullptr;
-      if (zin_is_input) {
-        CK((gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r, (int32_t)std::max<int64_t>(r, 1),
-                                      -1.0, Ui.p, vU, out, vout, 1.0, (const TIn*)zin, vz, rout, vr, 0,
-                                      as<double>(colpart), nullptr, gws())));
-      } else {
-        CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
-                                         (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, vU, out, vout, 1.0,
-                                         (const double*)zin, vz, rout, vr, 0, as<double>(colpart), nullptr, gws())));
-      }
       CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
       CK(total_sum(st, as<double>(fres), N, as<double>(scal)));
       CKS(sync_scalars(4));
@@ -301,10 +318,11 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       }
       rho2 = hs[0];
       if (hs[1] != 0.0 || !isfinite(rho2)) return TTICE_EINVAL;
+      rho2 = std::max(rho2, 0.0);
       tail2 = rho2;
 
       if (rho2 > tol2) {
-        if (!small) {
+        if (!have_R) {
           CK((zin_is_input
                   ? gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
                                               (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, vU, out, vout, 1.0,
@@ -326,21 +344,21 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         const int64_t Sg = (K + kchunk - 1) / kchunk;
         CKS(ensure(gpart, (size_t)Sg * m * m * sizeof(double)));
         CKS(ensure(gram, (size_t)m * m * sizeof(double)));
-        CKS(ensure(tri, (size_t)6 * m * sizeof(double)));  // d, e, tau, 2m scratch, w
+        CKS(ensure(tri, (size_t)4 * m * sizeof(double)));  // d, e, tau, w
         CKS(ensure(order, (size_t)m * sizeof(int32_t)));
         CKS(ensure(lam, (size_t)m * sizeof(double)));
         CKS(ensure(tail, (size_t)(m + 1) * sizeof(double)));
         double* dd = as<double>(tri);
         double* ee = dd + m;
         double* tauv = dd + 2 * m;
-        double* vp = dd + 3 * m;
-        double* wv = dd + 5 * m;
+        double* wv = dd + 3 * m;
         CK((gemm<double, double, double>(st, (int32_t)m, (int32_t)m, (int32_t)K, kchunk, 1.0, as<double>(rbuf),
                                          left ? vR : vRt, as<double>(rbuf), left ? vRt : vR, 0.0,
                                          (const double*)nullptr, View(), as<double>(gpart), row_major(m),
                                          m * m, nullptr, nullptr)));
         CK(gram_reduce(st, as<double>(gpart), (int32_t)Sg, (int32_t)m, as<double>(gram)));
-        CK(sym_eigvals(st, (int32_t)m, as<double>(gram), dd, ee, tauv, vp, wv));
+        if (m > sym_eig_max()) return TTICE_EINVAL;  // documented size limit of the residual's SVD
+        CK(sym_eigvals(st, (int32_t)m, as<double>(gram), dd, ee, tauv, wv));
         const int64_t cap = rows - r;
         CK(select_rank(st, (int32_t)m, wv, tol2, cap, as<int32_t>(order), as<double>(lam),
                        as<double>(tail), as<double>(scal)));
@@ -475,30 +493,45 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
       CKS(ensure(bnorm, (size_t)Ncol * sizeof(double)));
       bn = as<double>(bnorm);
     }
-    if (zin_is_input)
-      CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
-                                 transposed(row_major(Ui.ld)), (const TIn*)zin, vz, 0.0, (const TIn*)nullptr,
-                                 View(), out, vout, 0, nullptr, bn, gws())));
-    else
-      CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
-                                       transposed(row_major(Ui.ld)), (const double*)zin, vz, 0.0,
-                                       (const double*)nullptr, View(), out, vout, 0, nullptr, bn, gws())));
-    if (bn) CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, y2_out));
+    const bool fused = proj_fits((int32_t)rows, (int32_t)r);
+    const int32_t MB = fused ? 1 : gemm_row_blocks((int32_t)rows);
+    double* cp = nullptr;
     if (err2_out) {
-      const int32_t MB = gemm_row_blocks((int32_t)rows);
       CKS(ensure(colpart, (size_t)MB * Ncol * sizeof(double)));
       CKS(ensure(fres, (size_t)N * sizeof(double)));
+      cp = as<double>(colpart);
+    }
+    if (fused) {
       if (zin_is_input)
-        CK((gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
-                                      (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out, vout,
-                                      1.0, (const TIn*)zin, vz, (double*)nullptr, View(), 0,
-                                      as<double>(colpart), nullptr, gws())));
+        CK((proj_columns<TIn, double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p,
+                                      Ui.ld, out, vout, bn, cp)));
       else
-        CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
-                                         (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out,
-                                         vout, 1.0, (const double*)zin, vz, (double*)nullptr, View(), 0,
-                                         as<double>(colpart), nullptr, gws())));
-      CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
+        CK((proj_columns<double, double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz,
+                                         Ui.p, Ui.ld, out, vout, bn, cp)));
+    } else {
+      if (zin_is_input)
+        CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
+                                   transposed(row_major(Ui.ld)), (const TIn*)zin, vz, 0.0, (const TIn*)nullptr,
+                                   View(), out, vout, 0, nullptr, bn, gws())));
+      else
+        CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
+                                         transposed(row_major(Ui.ld)), (const double*)zin, vz, 0.0,
+                                         (const double*)nullptr, View(), out, vout, 0, nullptr, bn, gws())));
+      if (err2_out) {
+        if (zin_is_input)
+          CK((gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
+                                        (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out, vout,
+                                        1.0, (const TIn*)zin, vz, (double*)nullptr, View(), 0, cp, nullptr, gws())));
+        else
+          CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
+                                           (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out,
+                                           vout, 1.0, (const double*)zin, vz, (double*)nullptr, View(), 0, cp, nullptr,
+                                           gws())));
+      }
+    }
+    if (bn) CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, y2_out));
+    if (err2_out) {
+      CK(frame_sums(st, cp, MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
       CK(accumulate(st, err2_out, as<double>(fres), N));
     }
     zin = out;

@@ -9,8 +9,8 @@
 
 extern "C" int hipemu_sym_eig(int m, const double* A_in, double* w, int r, double* X) {
   std::vector<double> A(A_in, A_in + (size_t)m * m);
-  std::vector<double> d(m), e(m), tau(m), vp(2 * m), ws((size_t)7 * m * (r > 0 ? r : 1));
-  if (ttice::sym_eigvals(nullptr, m, A.data(), d.data(), e.data(), tau.data(), vp.data(), w) != hipSuccess) return -1;
+  std::vector<double> d(m), e(m), tau(m), ws((size_t)7 * m * (r > 0 ? r : 1));
+  if (ttice::sym_eigvals(nullptr, m, A.data(), d.data(), e.data(), tau.data(), w) != hipSuccess) return -1;
   if (r > 0 && ttice::sym_eigvecs(nullptr, m, r, d.data(), e.data(), w, A.data(), tau.data(), ws.data(), X) !=
                    hipSuccess)
     return -2;
@@ -20,6 +20,6 @@ extern "C" int hipemu_sym_eig(int m, const double* A_in, double* w, int r, doubl
 // Tridiagonal form only (d, e) of a host matrix.
 extern "C" int hipemu_tridiag(int m, const double* A_in, double* d, double* e) {
   std::vector<double> A(A_in, A_in + (size_t)m * m);
-  std::vector<double> tau(m), vp(2 * m), w(m);
-  return ttice::sym_eigvals(nullptr, m, A.data(), d, e, tau.data(), vp.data(), w.data()) == hipSuccess ? 0 : -1;
+  std::vector<double> tau(m), w(m);
+  return ttice::sym_eigvals(nullptr, m, A.data(), d, e, tau.data(), w.data()) == hipSuccess ? 0 : -1;
 }

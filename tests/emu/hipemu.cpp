@@ -163,6 +163,18 @@ unsigned long long ballot(int pred) {
   return mask;
 }
 
+double wave_reduce_add(double v) {
+  const unsigned tid = cur;
+  shfl_buf[tid] = v;
+  wave_barrier();
+  const unsigned w0 = tid & ~63u;
+  double s = 0.0;
+  for (unsigned l = 0; l < 64 && w0 + l < nthreads; ++l)
+    if (fibers[w0 + l].state != DONE) s += shfl_buf[w0 + l];
+  wave_barrier();
+  return s;
+}
+
 void* dyn_lds() { return dyn.data(); }
 
 void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body) {
@@ -248,3 +260,5 @@ extern "C" void hipemu_fail_alloc_after(long long k) {
   hipemu::g_fail_alloc_after = k;
   g_allocs = 0;
 }
+
+extern "C" double __ockl_wfred_add_f64(double v) { return hipemu::wave_reduce_add(v); }

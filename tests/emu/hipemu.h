@@ -52,6 +52,7 @@ void barrier();
 double shfl_down(double v, int off);
 double shfl_xor(double v, int mask);
 unsigned long long ballot(int pred);
+double wave_reduce_add(double v);
 void* dyn_lds();
 void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body);
 extern long long g_fail_alloc_after;  // failure injection: fail the k-th allocation (-1: never)
@@ -69,6 +70,9 @@ inline double __shfl_down(double v, int off, int = 64) { return hipemu::shfl_dow
 inline double __shfl_xor(double v, int mask, int = 64) { return hipemu::shfl_xor(v, mask); }
 inline unsigned long long __ballot(int pred) { return hipemu::ballot(pred); }
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
+extern "C" double __ockl_wfred_add_f64(double v);
+inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
+using std::floor;
 using std::copysign;
 using std::sin;
 using std::fmin;
