@@ -65,9 +65,29 @@ enum ttice_option {
   TTICE_OPT_TAU = 4,       /* double, occupancy threshold of Algorithm 2,
                               eq:coreoccupancy (default 1.0: skip only full
                               cores, which cannot gain a direction)            */
-  TTICE_OPT_STREAM = 5     /* hipStream_t passed as (const void*)&stream; all
+  TTICE_OPT_STREAM = 5,    /* hipStream_t passed as (const void*)&stream; all
                               device work of later calls runs on it (default:
                               the null stream)                                 */
+  TTICE_OPT_PROFILE = 6    /* int32_t: 1 = time the kernels listed in enum
+                              ttice_kernel with HIP events on the library's
+                              stream (setting it resets the counters); 0 = off */
+};
+
+/* Kernels whose launches TTICE_OPT_PROFILE times. */
+enum ttice_kernel {
+  TTICE_KERNEL_PROJ_L1 = 0 /* fused projection of level 1: one pass over each
+                              increment giving U_1^T Y, ||Y(b)||^2 and the
+                              residual energy (eq:first_resid)               */
+};
+
+/* Accumulated timing of one kernel since profiling was enabled.  bytes is
+ * the algorithmic HBM traffic of the launches: the increment read once
+ * (n * prod(dims) * sizeof(element)) plus the coefficients written
+ * (r_1 * n * n_2...n_d FP64). */
+struct ttice_kernel_stats {
+  int64_t launches;
+  double total_ms;
+  double bytes;
 };
 
 #define TTICE_MAX_D 16
@@ -128,6 +148,10 @@ int ttice_reconstruct(ttice_state* st, int64_t first, int64_t count, void* out,
  * (device, [n] FP64).  Errors as ttice_update. */
 int ttice_project(ttice_state* st, const void* batch, int64_t n, int32_t dtype,
                   double* coef, double* err2, double* y2);
+
+/* Read the profile of kernel `kernel` (enum ttice_kernel) into *out (host).
+ * Errors: ESTATE, EINVAL (unknown kernel or null out). */
+int ttice_get_kernel_stats(const ttice_state* st, int32_t kernel, struct ttice_kernel_stats* out);
 
 /* ranks: host array of d+2 entries (r_0 = 1, r_1..r_d, r_{d+1} = 1);
  * n_total: host pointer (may be NULL).  Errors: ESTATE, EINVAL. */

@@ -69,14 +69,18 @@ __device__ __forceinline__ int64_t col_off(const View& v, int32_t j) {
   return ff * v.cfs + (int64_t)w * v.cs;
 }
 
-// Fused one-pass projection of narrow cores (r <= 64, U staged in LDS):
-// for every column j of Z (rows x Ncol view), C(:, j) = U^T z_j (view vc),
-// znorm2[j] = ||z_j||^2 and rho2[j] = ||z_j||^2 - ||C(:, j)||^2 (FP64).
-// Any output may be null.
+// Fused one-pass projection of narrow cores (r <= 64, FP64 matrix cores):
+// for every column j of Z (rows x Ncol view, rows unframed), C(:, j) =
+// U^T z_j (view vc, rows unframed), znorm2[j] = ||z_j||^2 and rho2[j] =
+// ||z_j||^2 - ||C(:, j)||^2 (FP64).  Any output may be null.  U is read
+// kProjTail doubles wide from the start of each of its rows, so its
+// allocation must extend at least kProjTail doubles past row (rows - 1)'s
+// start (the values there are never used).
+constexpr int kProjTail = 64;
 bool proj_fits(int32_t rows, int32_t r);
-template <typename TIn, typename TOut>
+template <typename TIn>
 hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
-                        const double* U, int64_t ldu, TOut* C, View vc, double* znorm2, double* rho2);
+                        const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2);
 
 // Scratch the product may use to split a long K-sum across workgroups.
 struct GemmWs {

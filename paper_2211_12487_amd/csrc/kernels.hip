@@ -23,18 +23,28 @@ __device__ __forceinline__ void gemm_epilogue(double (&acc)[4][4], int32_t M, in
   const int t = threadIdx.x;
   const int tx = t & 15, ty = t >> 4;
   double csq[4] = {0.0, 0.0, 0.0, 0.0};
+  // E is read from clamped in-bounds positions first (all loads in flight),
+  // then masked; M > 0 and E != null are uniform.
+  double ev[4][4];
+  if (E && M > 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t ero = row_off(ve, min(m0 + ty + 16 * i, M - 1));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ev[i][j] = (double)E[ero + col_off(ve, min(n0 + tx + 16 * j, N - 1))];
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int32_t m = m0 + ty + 16 * i;
     if (m >= M) continue;
-    const int64_t ero = E ? row_off(ve, m) : 0;
     const int64_t dro = D ? row_off(vd, m) : 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int32_t n = n0 + tx + 16 * j;
       if (n >= N) continue;
       double v = alpha * acc[i][j];
-      if (E) v = fma(beta, (double)E[ero + col_off(ve, n)], v);
+      if (E) v = fma(beta, ev[i][j], v);
       if (D) D[dro + col_off(vd, n)] = (TD)v;
       csq[j] = fma(v, v, csq[j]);
     }
@@ -78,12 +88,16 @@ __global__ __launch_bounds__(256) void k_gemm(int32_t M, int32_t N, int32_t K, i
   const int32_t kb = (int32_t)blockIdx.z * kchunk;
   const int32_t ke = min(K, kb + kchunk);
 
+  // Tile loads always read a clamped, in-bounds element and mask it
+  // afterwards, so the compiler keeps them in flight together (a guarded load
+  // becomes a branch with a wait).  M > 0 is uniform over the block.
   const int32_t bn = n0 + ln;
   const bool bvalid = bn < N;
-  const int64_t bco = bvalid ? col_off(vb, bn) : 0;
+  const int64_t bco = col_off(vb, min(bn, N - 1));
   const int32_t am = m0 + ln;
   const bool avalid = am < M;
-  const int64_t aro = avalid ? row_off(va, am) : 0;
+  const bool aload = M > 0;
+  const int64_t aro = aload ? row_off(va, min(am, M - 1)) : 0;
 
   double acc[4][4];
 #pragma unroll
@@ -93,18 +107,22 @@ __global__ __launch_bounds__(256) void k_gemm(int32_t M, int32_t N, int32_t K, i
   double bsq = 0.0;
 
   for (int32_t k0 = kb; k0 < ke; k0 += 16) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t kc = min(k0 + lk + 4 * u, ke - 1);
+      av[u] = aload ? A[aro + col_off(va, kc)] : 0.0;
+      bv[u] = (double)B[row_off(vb, kc) + bco];
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int kk = lk + 4 * u;
-      const int32_t k = k0 + kk;
-      double av = 0.0, bv = 0.0;
-      if (k < ke) {
-        if (avalid) av = A[aro + col_off(va, k)];
-        if (bvalid) bv = (double)B[row_off(vb, k) + bco];
-      }
-      As[kk][ln] = av;
-      Bs[kk][ln] = bv;
-      bsq = fma(bv, bv, bsq);
+      const bool kin = k0 + kk < ke;
+      const double a = (kin && avalid) ? av[u] : 0.0;
+      const double b = (kin && bvalid) ? bv[u] : 0.0;
+      As[kk][ln] = a;
+      Bs[kk][ln] = b;
+      bsq = fma(b, b, bsq);
     }
     __syncthreads();
 #pragma unroll

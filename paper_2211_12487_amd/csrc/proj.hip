@@ -10,127 +10,246 @@
 // FP64 the cancellation costs ~1e-13 relative at the tolerances used, so the
 // residual itself is only formed when a core is actually updated).
 //
-// Layout: a block owns 64 consecutive columns (one per lane) and splits the
-// rows over its 4 waves; U (rows x r, FP64) is staged in LDS and read as
-// wave-wide broadcasts; each lane keeps RMAX FP64 accumulators; the 4 row
-// partials are combined through LDS in a fixed order.  Loads of Z are
-// coalesced along the columns of a frame (a frame boundary inside a wave's
-// 64 columns only splits its load into two runs).
+// The product runs on the FP64 matrix cores (v_mfma_f64_16x16x4f64: a
+// 16 x 4 tile of U^T times a 4 x 16 tile of Z per instruction).  Layout:
+//  * a block owns 16*VEC consecutive columns; lane (kq = lane / 16,
+//    n = lane % 16) holds VEC consecutive columns 16*VEC*blk + VEC*n + g of
+//    row 4*q + kq of every row quad q, loaded as one VEC-wide vector (one
+//    load instruction moves 4 rows x 16*VEC columns), and column slot g
+//    feeds MFMA group g;
+//  * the A operand of quad q is U[4q + kq, 16t + n] (one FP64 per lane per
+//    16-wide tile t of U's columns; U is small and cache resident);
+//  * the W waves of a block split the row quads, and their FP64 partial
+//    tiles are summed by a fixed-order tree through LDS (deterministic);
+//  * output element i of a D tile on lane (kq, n) is row 16t + 4i + kq.
+// VEC > 1 needs the columns of a frame, the row and frame strides and the
+// base pointers of Z and C to be VEC-aligned (checked on the host).
 #include "kernels.h"
 
 namespace ttice {
 namespace {
 
-constexpr int kProjWaves = 4;
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int kChunkQuads = 8;  // row quads whose loads are issued together
 
-template <typename TIn, typename TOut, int RMAX>
-__global__ __launch_bounds__(64 * kProjWaves) void k_proj_col(int32_t rows, int32_t r, int32_t Ncol, View vz,
-                                                              const TIn* __restrict__ Z, const double* __restrict__ U,
-                                                              int64_t ldu, TOut* __restrict__ C, View vc,
-                                                              double* __restrict__ znorm2,
-                                                              double* __restrict__ rho2) {
-  HIP_DYNAMIC_SHARED(double, lds);
-  double* Us = lds;                               // rows x RMAX (zero-padded)
-  double* part = lds + (int64_t)rows * RMAX;      // kProjWaves x (RMAX + 1) x 64
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int64_t q = threadIdx.x; q < (int64_t)rows * RMAX; q += 64 * kProjWaves) {
-    const int32_t i = (int32_t)(q / RMAX), k = (int32_t)(q % RMAX);
-    Us[q] = k < r ? U[(int64_t)i * ldu + k] : 0.0;
+template <typename T, int VEC>
+struct Vec;
+template <typename T>
+struct Vec<T, 1> {
+  T v[1];
+  __device__ static Vec load(const T* p) { return Vec{{p[0]}}; }
+};
+template <typename T>
+struct Vec<T, 2> {
+  T v[2];
+  __device__ static Vec load(const T* p) {
+    Vec r;
+    __builtin_memcpy(&r.v[0], __builtin_assume_aligned(p, 2 * sizeof(T)), 2 * sizeof(T));
+    return r;
   }
-  __syncthreads();
-  const int32_t j = (int32_t)blockIdx.x * 64 + lane;
-  const bool valid = j < Ncol;
-  const TIn* zc = Z + (valid ? col_off(vz, j) : 0);
-  // rows of this wave: [i0, i1)
-  const int32_t per = (rows + kProjWaves - 1) / kProjWaves;
-  const int32_t i0 = wid * per, i1 = min(rows, i0 + per);
-  double acc[RMAX];
-#pragma unroll
-  for (int k = 0; k < RMAX; ++k) acc[k] = 0.0;
-  double zz = 0.0;
-  if (valid) {
-    int32_t i = i0;
-    for (; i + 4 <= i1; i += 4) {
-      double z[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) z[u] = (double)zc[row_off(vz, i + u)];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        zz = fma(z[u], z[u], zz);
-        const double* ui = Us + (int64_t)(i + u) * RMAX;
-#pragma unroll
-        for (int k = 0; k < RMAX; ++k) acc[k] = fma(ui[k], z[u], acc[k]);
-      }
-    }
-    for (; i < i1; ++i) {
-      const double z = (double)zc[row_off(vz, i)];
-      zz = fma(z, z, zz);
-      const double* ui = Us + (int64_t)i * RMAX;
-#pragma unroll
-      for (int k = 0; k < RMAX; ++k) acc[k] = fma(ui[k], z, acc[k]);
-    }
+};
+template <typename T>
+struct Vec<T, 4> {
+  T v[4];
+  __device__ static Vec load(const T* p) {
+    Vec r;
+    __builtin_memcpy(&r.v[0], __builtin_assume_aligned(p, 4 * sizeof(T)), 4 * sizeof(T));
+    return r;
   }
-  // combine the row partials of the 4 waves (fixed order)
-  double* pw = part + (int64_t)wid * (RMAX + 1) * 64;
-#pragma unroll
-  for (int k = 0; k < RMAX; ++k) pw[k * 64 + lane] = acc[k];
-  pw[RMAX * 64 + lane] = zz;
-  __syncthreads();
-  if (wid == 0 && valid) {
-    double cc = 0.0;
-    const int64_t co = col_off(vc, j);
-    for (int k = 0; k < r; ++k) {
-      double s = 0.0;
-#pragma unroll
-      for (int w = 0; w < kProjWaves; ++w) s += part[(int64_t)w * (RMAX + 1) * 64 + k * 64 + lane];
-      if (C) C[row_off(vc, k) + co] = (TOut)s;
-      cc = fma(s, s, cc);
-    }
-    double zs = 0.0;
-#pragma unroll
-    for (int w = 0; w < kProjWaves; ++w) zs += part[(int64_t)w * (RMAX + 1) * 64 + RMAX * 64 + lane];
-    if (znorm2) znorm2[j] = zs;
-    if (rho2) rho2[j] = zs - cc;
+};
+
+template <int VEC>
+__device__ __forceinline__ void store_vec(double* p, const double* v) {
+  if constexpr (VEC == 1) {
+    p[0] = v[0];
+  } else {
+    __builtin_memcpy(__builtin_assume_aligned(p, VEC * sizeof(double)), v, VEC * sizeof(double));
   }
 }
 
-template <typename TIn, typename TOut, int RMAX>
+template <typename TIn, int VEC, int RT, int W>
+__global__ __launch_bounds__(64 * W) void k_proj_mfma(int32_t rows, int32_t r, int32_t Ncol, View vz,
+                                                      const TIn* __restrict__ Z, const double* __restrict__ U,
+                                                      int64_t ldu, double* __restrict__ C, View vc,
+                                                      double* __restrict__ znorm2, double* __restrict__ rho2) {
+  constexpr int NV = RT * VEC * 4 + VEC;  // doubles per lane: D tiles + ||z||^2 partials
+  HIP_DYNAMIC_SHARED(double, red);        // (W / 2) x NV x 64
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int kq = lane >> 4, n = lane & 15;
+  const int32_t j = (int32_t)blockIdx.x * (16 * VEC) + VEC * n;  // first of this lane's VEC columns
+  const bool valid = j < Ncol;
+  // lanes past the last column read column 0 and are never stored
+  const int64_t coff = valid ? col_off(vz, j) : 0;
+  const int64_t rs = vz.rs;
+  const int32_t nq = (rows + 3) >> 2;
+  const int32_t per = (nq + W - 1) / W;
+  const int32_t q0 = wid * per, q1 = min(nq, q0 + per);
+
+  d4 acc[RT][VEC];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int g = 0; g < VEC; ++g) acc[t][g] = d4{0.0, 0.0, 0.0, 0.0};
+  double zz[VEC];
+#pragma unroll
+  for (int g = 0; g < VEC; ++g) zz[g] = 0.0;
+
+  for (int32_t qb = q0; qb < q1; qb += kChunkQuads) {
+    // all loads of the chunk first (rows clamped in bounds, masked below)
+    Vec<TIn, VEC> zr[kChunkQuads];
+    double ur[kChunkQuads][RT];
+#pragma unroll
+    for (int u = 0; u < kChunkQuads; ++u) {
+      const int32_t i = min((qb + u) * 4 + kq, rows - 1);
+      zr[u] = Vec<TIn, VEC>::load(Z + (int64_t)i * rs + coff);
+#pragma unroll
+      for (int t = 0; t < RT; ++t) ur[u][t] = U[(int64_t)i * ldu + 16 * t + n];
+    }
+#pragma unroll
+    for (int u = 0; u < kChunkQuads; ++u) {
+      const bool live = qb + u < q1 && (qb + u) * 4 + kq < rows;
+#pragma unroll
+      for (int g = 0; g < VEC; ++g) {
+        const double z = live ? (double)zr[u].v[g] : 0.0;
+        zz[g] = fma(z, z, zz[g]);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) acc[t][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(ur[u][t], z, acc[t][g], 0, 0, 0);
+      }
+    }
+  }
+
+  // fixed-order tree over the waves' row partials
+#pragma unroll
+  for (int h = W / 2; h >= 1; h /= 2) {
+    if (wid >= h && wid < 2 * h) {
+      double* o = red + (int64_t)(wid - h) * NV * 64 + lane;
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int g = 0; g < VEC; ++g)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) o[((t * VEC + g) * 4 + i) * 64] = acc[t][g][i];
+#pragma unroll
+      for (int g = 0; g < VEC; ++g) o[(RT * VEC * 4 + g) * 64] = zz[g];
+    }
+    __syncthreads();
+    if (wid < h) {
+      const double* o = red + (int64_t)wid * NV * 64 + lane;
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int g = 0; g < VEC; ++g)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[t][g][i] += o[((t * VEC + g) * 4 + i) * 64];
+#pragma unroll
+      for (int g = 0; g < VEC; ++g) zz[g] += o[(RT * VEC * 4 + g) * 64];
+    }
+    __syncthreads();
+  }
+  if (wid != 0) return;
+
+  double cc[VEC];
+#pragma unroll
+  for (int g = 0; g < VEC; ++g) cc[g] = 0.0;
+  const int64_t co = valid ? col_off(vc, j) : 0;
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = 16 * t + 4 * i + kq;
+      if (m < r) {
+        double v[VEC];
+#pragma unroll
+        for (int g = 0; g < VEC; ++g) {
+          v[g] = acc[t][g][i];
+          cc[g] = fma(v[g], v[g], cc[g]);
+        }
+        if (C && valid) store_vec<VEC>(C + row_off(vc, m) + co, v);
+      }
+    }
+  // sum over the four row phases kq (lanes n, n + 16, n + 32, n + 48)
+#pragma unroll
+  for (int g = 0; g < VEC; ++g) {
+    cc[g] += __shfl_xor(cc[g], 16);
+    cc[g] += __shfl_xor(cc[g], 32);
+    zz[g] += __shfl_xor(zz[g], 16);
+    zz[g] += __shfl_xor(zz[g], 32);
+  }
+  if (kq == 0 && valid) {
+    if (znorm2) store_vec<VEC>(znorm2 + j, zz);
+    if (rho2) {
+      double e[VEC];
+#pragma unroll
+      for (int g = 0; g < VEC; ++g) e[g] = zz[g] - cc[g];
+      store_vec<VEC>(rho2 + j, e);
+    }
+  }
+}
+
+template <int W, int NV>
+constexpr size_t red_bytes() {
+  return (size_t)(W / 2) * NV * 64 * sizeof(double);
+}
+
+template <typename TIn, int VEC, int RT>
 hipError_t launch_proj(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
-                       const double* U, int64_t ldu, TOut* C, View vc, double* znorm2, double* rho2) {
-  const size_t lds = ((size_t)rows * RMAX + (size_t)kProjWaves * (RMAX + 1) * 64) * sizeof(double);
+                       const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2) {
+  constexpr int W = RT == 4 ? 4 : 8;
+  constexpr size_t lds = red_bytes<W, RT * VEC * 4 + VEC>();
+  static_assert(lds <= 80 * 1024, "reduction buffer");
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_proj_col<TIn, TOut, RMAX>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    hipError_t e = hipFuncSetAttribute((const void*)k_proj_mfma<TIn, VEC, RT, W>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((k_proj_col<TIn, TOut, RMAX>), dim3((unsigned)((Ncol + 63) / 64)), dim3(64 * kProjWaves), lds,
-                     st, rows, r, Ncol, vz, Z, U, ldu, C, vc, znorm2, rho2);
+  const int32_t cols_per_block = 16 * VEC;
+  hipLaunchKernelGGL((k_proj_mfma<TIn, VEC, RT, W>), dim3((unsigned)((Ncol + cols_per_block - 1) / cols_per_block)),
+                     dim3(64 * W), lds, st, rows, r, Ncol, vz, Z, U, ldu, C, vc, znorm2, rho2);
   return hipGetLastError();
+}
+
+template <typename TIn, int VEC>
+hipError_t launch_rt(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
+                     const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2) {
+  if (r <= 16) return launch_proj<TIn, VEC, 1>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
+  if (r <= 32) return launch_proj<TIn, VEC, 2>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
+  return launch_proj<TIn, VEC, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
+}
+
+// Widest VEC such that every lane's VEC columns are consecutive in memory
+// and VEC-aligned, for Z (elements of TIn) and C.
+bool aligned_cols(const View& v, const void* base, size_t esize, int vec) {
+  if (v.cs != 1 || (v.rs % vec) != 0) return false;
+  if (v.cpf != kUnframed && ((v.cpf % vec) != 0 || (v.cfs % vec) != 0)) return false;
+  return ((uintptr_t)base % (vec * esize)) == 0;
 }
 
 }  // namespace
 
-bool proj_fits(int32_t rows, int32_t r) {
-  if (r > 64 || rows <= 0) return false;
-  const int32_t R = r <= 8 ? 8 : (r <= 16 ? 16 : (r <= 32 ? 32 : 64));
-  return ((size_t)rows * R + (size_t)kProjWaves * (R + 1) * 64) * sizeof(double) <= 150 * 1024;
-}
+bool proj_fits(int32_t rows, int32_t r) { return r <= 64 && rows > 0; }
 
-template <typename TIn, typename TOut>
+template <typename TIn>
 hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
-                        const double* U, int64_t ldu, TOut* C, View vc, double* znorm2, double* rho2) {
+                        const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2) {
   if (Ncol <= 0) return hipSuccess;
-  if (r <= 8) return launch_proj<TIn, TOut, 8>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
-  if (r <= 16) return launch_proj<TIn, TOut, 16>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
-  if (r <= 32) return launch_proj<TIn, TOut, 32>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
-  return launch_proj<TIn, TOut, 64>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
+  if (vz.rpf != kUnframed || vc.rpf != kUnframed || r > 64 || rows <= 0) return hipErrorInvalidValue;
+  // the widest instantiation reads 16 * 4 doubles of every row of U
+  static_assert(kProjTail >= 64, "core allocations must cover the widest row read");
+  for (int vec : {4, 2}) {
+    if ((Ncol % vec) == 0 && aligned_cols(vz, Z, sizeof(TIn), vec) && (!C || aligned_cols(vc, C, sizeof(double), vec))) {
+      if (vec == 4) return launch_rt<TIn, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
+      return launch_rt<TIn, 2>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
+    }
+  }
+  return launch_rt<TIn, 1>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
 }
 
-template hipError_t proj_columns<float, double>(hipStream_t, int32_t, int32_t, int32_t, const float*, View,
-                                                const double*, int64_t, double*, View, double*, double*);
-template hipError_t proj_columns<double, double>(hipStream_t, int32_t, int32_t, int32_t, const double*, View,
-                                                 const double*, int64_t, double*, View, double*, double*);
+template hipError_t proj_columns<float>(hipStream_t, int32_t, int32_t, int32_t, const float*, View, const double*,
+                                        int64_t, double*, View, double*, double*);
+template hipError_t proj_columns<double>(hipStream_t, int32_t, int32_t, int32_t, const double*, View, const double*,
+                                         int64_t, double*, View, double*, double*);
 
 }  // namespace ttice

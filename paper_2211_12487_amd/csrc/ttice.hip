@@ -37,6 +37,8 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// A core is allocated kProjTail doubles longer than cap_rows x ld, the
+// over-read the fused projection kernel does past its last row.
 struct Core {
   double* p = nullptr;
   int64_t cap_rows = 0;
@@ -110,6 +112,16 @@ struct ttice_state {
       S, dlist, eigws, splitk;
   double* hs = nullptr;  // pinned host scalars (64 doubles)
 
+  // kernel profiling (TTICE_OPT_PROFILE): event pairs recorded during one
+  // update and resolved when it has completed
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool;
+  int ev_used = 0;
+  std::vector<double> ev_bytes;
+  struct ttice_kernel_stats kstats[1] = {};
+  int prof_begin(hipEvent_t* a, hipEvent_t* b);
+  int prof_resolve();
+
   ~ttice_state();
 
   int64_t cols(int i) const {  // columns per tensor at level i
@@ -133,7 +145,34 @@ struct ttice_state {
   int reconstruct_impl(int64_t first, int64_t count, TD* out);
 };
 
+int ttice_state::prof_begin(hipEvent_t* a, hipEvent_t* b) {
+  while ((int)ev_pool.size() < ev_used + 2) {
+    hipEvent_t e;
+    CK(hipEventCreate(&e));
+    ev_pool.push_back(e);
+  }
+  *a = ev_pool[ev_used];
+  *b = ev_pool[ev_used + 1];
+  ev_used += 2;
+  return TTICE_OK;
+}
+
+int ttice_state::prof_resolve() {
+  for (int k = 0; k + 1 < ev_used; k += 2) {
+    float ms = 0.0f;
+    CK(hipEventSynchronize(ev_pool[k + 1]));
+    CK(hipEventElapsedTime(&ms, ev_pool[k], ev_pool[k + 1]));
+    kstats[0].launches += 1;
+    kstats[0].total_ms += ms;
+    kstats[0].bytes += ev_bytes[k / 2];
+  }
+  ev_used = 0;
+  ev_bytes.clear();
+  return TTICE_OK;
+}
+
 ttice_state::~ttice_state() {
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   for (int i = 0; i < TTICE_MAX_D; ++i)
     if (U[i].p) (void)hipFree(U[i].p);
   if (Gt.p) (void)hipFree(Gt.p);
@@ -156,7 +195,7 @@ int ttice_state::grow_core(Core& c, int64_t need_rows, int64_t need_cols, int64_
   nr = std::max<int64_t>(nr, 1);
   nl = std::max<int64_t>(nl, 1);
   double* p = nullptr;
-  hipError_t e = hipMalloc(&p, (size_t)nr * nl * sizeof(double));
+  hipError_t e = hipMalloc(&p, ((size_t)nr * nl + kProjTail) * sizeof(double));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return TTICE_ENOMEM;
@@ -188,6 +227,10 @@ int ttice_state::sync_scalars(int n) {
 }
 
 namespace {
+
+// The fused projection gives each column one lane: below this many columns
+// it cannot fill the device and the tiled products are used instead.
+constexpr int64_t kFusedMinCols = 8192;
 
 // Split the K-sum of a Gram product so the launch has a few hundred blocks.
 int32_t gram_kchunk(int32_t m, int64_t K) {
@@ -255,7 +298,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       CKS(ensure(bnorm, (size_t)Ncol * sizeof(double)));
       bn = as<double>(bnorm);
     }
-    const bool fused = proj_fits((int32_t)rows, (int32_t)r);
+    const bool fused = proj_fits((int32_t)rows, (int32_t)r) && Ncol >= kFusedMinCols;
     const int32_t MB = fused ? 1 : gemm_row_blocks((int32_t)rows);
     CKS(ensure(colpart, (size_t)MB * Ncol * sizeof(double)));
     CKS(ensure(fres, (size_t)N * sizeof(double)));
@@ -266,12 +309,20 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
     double* cp = occ_skip ? nullptr : as<double>(colpart);
     if (fused) {
       // one pass: ||(I - U U^T) z||^2 = ||z||^2 - ||U^T z||^2 (orthonormal U)
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      const bool timed = profile && i == 0;
+      if (timed) {
+        CKS(prof_begin(&e0, &e1));
+        ev_bytes.push_back((double)N * P * sizeof(TIn) + (double)r * Ncol * sizeof(double));
+        CK(hipEventRecord(e0, st));
+      }
       if (zin_is_input)
-        CK((proj_columns<TIn, double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p,
+        CK((proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p,
                                       Ui.ld, out, vout, bn, cp)));
       else
-        CK((proj_columns<double, double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz,
+        CK((proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz,
                                          Ui.p, Ui.ld, out, vout, bn, cp)));
+      if (timed) CK(hipEventRecord(e1, st));
     } else {
       if (zin_is_input) {
         CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
@@ -493,7 +544,7 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
       CKS(ensure(bnorm, (size_t)Ncol * sizeof(double)));
       bn = as<double>(bnorm);
     }
-    const bool fused = proj_fits((int32_t)rows, (int32_t)r);
+    const bool fused = proj_fits((int32_t)rows, (int32_t)r) && Ncol >= kFusedMinCols;
     const int32_t MB = fused ? 1 : gemm_row_blocks((int32_t)rows);
     double* cp = nullptr;
     if (err2_out) {
@@ -503,10 +554,10 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
     }
     if (fused) {
       if (zin_is_input)
-        CK((proj_columns<TIn, double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p,
+        CK((proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p,
                                       Ui.ld, out, vout, bn, cp)));
       else
-        CK((proj_columns<double, double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz,
+        CK((proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz,
                                          Ui.p, Ui.ld, out, vout, bn, cp)));
     } else {
       if (zin_is_input)
@@ -622,6 +673,7 @@ int ttice_state::update_impl(const TIn* batch, int64_t N, ttice_update_info* inf
     }
   }
   CK(hipStreamSynchronize(st));
+  if (profile) CKS(prof_resolve());
   // commit
   for (int i = 0; i <= d; ++i) rk[i] = rkp[i];
   n_total += N;
@@ -741,6 +793,12 @@ int ttice_set_option(ttice_state* st, int32_t key, const void* val) {
     case TTICE_OPT_STREAM:
       st->stream = *(const hipStream_t*)val;
       return TTICE_OK;
+    case TTICE_OPT_PROFILE:
+      st->profile = *(const int32_t*)val != 0;
+      memset(&st->kstats[0], 0, sizeof(st->kstats[0]));
+      st->ev_used = 0;
+      st->ev_bytes.clear();
+      return TTICE_OK;
     default:
       return TTICE_EINVAL;
   }
@@ -766,6 +824,8 @@ int ttice_update(ttice_state* st, const void* batch, int64_t n, int32_t dtype, t
     if (rc != TTICE_OK) {
       (void)hipStreamSynchronize(st->stream);
       (void)hipGetLastError();
+      st->ev_used = 0;
+      st->ev_bytes.clear();
     }
   }
   inf->n_total = st->n_total;
@@ -810,6 +870,13 @@ int ttice_project(ttice_state* st, const void* batch, int64_t n, int32_t dtype, 
   if (rc == TTICE_OK && nonfinite) rc = TTICE_EINVAL;
   if (rc != TTICE_OK) (void)hipGetLastError();
   return rc;
+}
+
+int ttice_get_kernel_stats(const ttice_state* st, int32_t kernel, struct ttice_kernel_stats* out) {
+  if (!st) return TTICE_ESTATE;
+  if (!out || kernel != TTICE_KERNEL_PROJ_L1) return TTICE_EINVAL;
+  *out = st->kstats[kernel];
+  return TTICE_OK;
 }
 
 int ttice_ranks(const ttice_state* st, int64_t* ranks, int64_t* n_total) {

@@ -22,7 +22,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 ALGO = {"plain": 0, "star": 1}
 SKIP = {"mean": 0, "batch": 1}
-OPT_PREC, OPT_ALGO, OPT_SKIP_RULE, OPT_TAU, OPT_STREAM = 1, 2, 3, 4, 5
+OPT_PREC, OPT_ALGO, OPT_SKIP_RULE, OPT_TAU, OPT_STREAM, OPT_PROFILE = 1, 2, 3, 4, 5, 6
+KERNEL_PROJ_L1 = 0
 F32, F64 = 0, 1
 
 EXPORTS = [
@@ -33,6 +34,7 @@ EXPORTS = [
     "ttice_project",
     "ttice_ranks",
     "ttice_get_core",
+    "ttice_get_kernel_stats",
     "ttice_destroy",
     "ttice_strerror",
 ]
@@ -67,6 +69,10 @@ class UpdateInfo(ctypes.Structure):
         )
 
 
+class KernelStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
 class TTICEError(RuntimeError):
     def __init__(self, code: int, what: str):
         super().__init__(f"{what}: {_strerror(code)} ({code})")
@@ -97,12 +103,13 @@ def lib():
     L.ttice_project.argtypes = [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp]
     L.ttice_ranks.argtypes = [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
     L.ttice_get_core.argtypes = [c_vp, c_i32, c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
+    L.ttice_get_kernel_stats.argtypes = [c_vp, c_i32, ctypes.POINTER(KernelStats)]
     L.ttice_destroy.argtypes = [c_vp]
     L.ttice_destroy.restype = None
     L.ttice_strerror.argtypes = [ctypes.c_int]
     L.ttice_strerror.restype = ctypes.c_char_p
     for name in ("ttice_create", "ttice_set_option", "ttice_update", "ttice_reconstruct",
-                 "ttice_project", "ttice_ranks", "ttice_get_core"):
+                 "ttice_project", "ttice_ranks", "ttice_get_core", "ttice_get_kernel_stats"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -212,6 +219,15 @@ class TTICE:
         if out.numel():
             _check(lib().ttice_get_core(self._h, i, ctypes.c_void_p(out.data_ptr()), None, None), "ttice_get_core")
         return out
+
+    def profile(self, on: bool = True) -> None:
+        """Time the profiled kernels with HIP events (resets the counters)."""
+        self.set_option(OPT_PROFILE, ctypes.c_int32(1 if on else 0))
+
+    def kernel_stats(self, kernel: int = KERNEL_PROJ_L1) -> dict:
+        ks = KernelStats()
+        _check(lib().ttice_get_kernel_stats(self._h, kernel, ctypes.byref(ks)), "ttice_get_kernel_stats")
+        return dict(launches=int(ks.launches), total_ms=float(ks.total_ms), bytes=float(ks.bytes))
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

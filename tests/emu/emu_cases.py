@@ -58,6 +58,12 @@ def case_ragged_f32():
     check_stream(EmuTTICE(L, dims, eps), Oracle(dims, eps), batches, rtol=1e-9, label="ragged")
 
 
+def case_wide_level():
+    """Level 1 wide enough (>= 8192 columns) for the fused one-pass projection."""
+    dims, eps = (12, 40, 50), 0.05
+    check_stream(EmuTTICE(L, dims, eps), Oracle(dims, eps), sep(15, dims, 5, 21, terms=4), label="wide")
+
+
 def case_order4():
     dims, eps = (9, 7, 11, 3), 0.03
     check_stream(EmuTTICE(L, dims, eps), Oracle(dims, eps), sep(12, dims, 4, 5, terms=5), label="order4")
@@ -208,6 +214,49 @@ def case_eigensolver():
     w, X = run(B @ B.T, 2)
     ev = np.linalg.eigvalsh(B @ B.T)[::-1]
     assert np.abs(w - ev).max() <= 1e-13 * ev[0]
+
+
+def case_proj_kernel():
+    """The fused column-projection kernel on its own, against NumPy FP64:
+    every vector width (4, 2, 1 columns per lane, and 1 for a misaligned
+    base), every U tile count (r <= 16, <= 32, <= 64), both input types,
+    ragged row quads and idle waves.  U is allocated with exactly the
+    documented over-read tail, so AddressSanitizer flags any read past it."""
+    import ctypes
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong
+    L.hipemu_proj.argtypes = [i32, i32, i32, i32, i64, i32, vp, vp, i64, vp, i64, vp, vp]
+    rng = np.random.default_rng(3)
+    tail = 64
+    for dt, code in ((np.float32, 0), (np.float64, 1)):
+        for cols, shift in ((8, 0), (6, 0), (3, 0), (8, 1)):
+            for rows, r in ((13, 5), (37, 20), (45, 40), (70, 16), (2, 0)):
+                N = 5
+                fs = rows * cols + 4
+                buf = rng.standard_normal(N * fs + shift).astype(dt)
+                Zb = buf[shift:]
+                Ufull = np.zeros(rows * max(r, 1) + tail)
+                Ufull[:rows * max(r, 1)] = rng.standard_normal(rows * max(r, 1)) / np.sqrt(rows)
+                Ufull[rows * max(r, 1):] = np.nan  # over-read values are never used
+                ldu = max(r, 1)
+                fs_c = max(r, 1) * cols
+                C = np.zeros(N * fs_c)
+                zn = np.zeros(N * cols)
+                rh = np.zeros(N * cols)
+                rc = L.hipemu_proj(rows, r, N, cols, fs, code, Zb.ctypes.data, Ufull.ctypes.data, ldu,
+                                   C.ctypes.data, fs_c, zn.ctypes.data, rh.ctypes.data)
+                assert rc == 0
+                U = Ufull[:rows * ldu].reshape(rows, ldu)[:, :r]
+                for b in range(N):
+                    Zf = Zb[b * fs: b * fs + rows * cols].astype(np.float64).reshape(rows, cols)
+                    Cref = U.T @ Zf
+                    z2 = (Zf * Zf).sum(axis=0)
+                    got = C[b * fs_c: b * fs_c + r * cols].reshape(r, cols)
+                    scale = np.sqrt(z2.max())
+                    if r:
+                        assert np.abs(got - Cref).max() <= 1e-13 * scale, (dt, cols, shift, rows, r)
+                    assert np.abs(zn[b * cols:(b + 1) * cols] - z2).max() <= 1e-13 * z2.max()
+                    res = z2 - (Cref * Cref).sum(axis=0)
+                    assert np.abs(rh[b * cols:(b + 1) * cols] - res).max() <= 1e-12 * z2.max()
 
 
 CASES = {k[5:]: v for k, v in globals().items() if k.startswith("case_")}

@@ -33,6 +33,7 @@ unsigned cur = 0;
 unsigned nthreads = 1;
 const std::function<void()>* g_body = nullptr;
 std::vector<double> shfl_buf;
+std::vector<double> mfma_buf;
 std::vector<unsigned char> dyn;
 #if EMU_ASAN
 void* sched_fake = nullptr;
@@ -175,6 +176,28 @@ double wave_reduce_add(double v) {
   return s;
 }
 
+d4 mfma_f64_16x16x4(double a, double b, d4 c) {
+  const unsigned tid = cur;
+  if (mfma_buf.size() < 2 * (size_t)nthreads) mfma_buf.assign(2 * (size_t)nthreads, 0.0);
+  mfma_buf[2 * tid] = a;
+  mfma_buf[2 * tid + 1] = b;
+  wave_barrier();
+  const unsigned w0 = tid & ~63u, l = tid & 63u;
+  if (w0 + 64 > nthreads) {
+    fprintf(stderr, "hipemu: MFMA in a partial wave\n");
+    abort();
+  }
+  d4 d = c;
+  for (int i = 0; i < 4; ++i) {
+    const unsigned m = l / 16 + 4 * i, n = l % 16;
+    double s = 0.0;
+    for (unsigned k = 0; k < 4; ++k) s += mfma_buf[2 * (w0 + m + 16 * k)] * mfma_buf[2 * (w0 + n + 16 * k) + 1];
+    d[i] += s;
+  }
+  wave_barrier();
+  return d;
+}
+
 void* dyn_lds() { return dyn.data(); }
 
 void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body) {
@@ -255,6 +278,25 @@ hipError_t hipGetDevice(int* d) {
 }
 hipError_t hipSetDevice(int) { return hipSuccess; }
 hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
+
+#include <chrono>
+hipError_t hipEventCreate(hipEvent_t* e) {
+  *e = new double(0.0);
+  return hipSuccess;
+}
+hipError_t hipEventDestroy(hipEvent_t e) {
+  delete (double*)e;
+  return hipSuccess;
+}
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t) {
+  *(double*)e = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  return hipSuccess;
+}
+hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
+  *ms = (float)(*(double*)b - *(double*)a);
+  return hipSuccess;
+}
 
 extern "C" void hipemu_fail_alloc_after(long long k) {
   hipemu::g_fail_alloc_after = k;

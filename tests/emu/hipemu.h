@@ -35,6 +35,7 @@ struct dim3 {
 
 typedef int hipError_t;
 typedef void* hipStream_t;
+typedef void* hipEvent_t;
 enum {
   hipSuccess = 0,
   hipErrorOutOfMemory = 2,
@@ -53,6 +54,8 @@ double shfl_down(double v, int off);
 double shfl_xor(double v, int mask);
 unsigned long long ballot(int pred);
 double wave_reduce_add(double v);
+typedef double d4 __attribute__((vector_size(4 * sizeof(double))));
+d4 mfma_f64_16x16x4(double a, double b, d4 c);
 void* dyn_lds();
 void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body);
 extern long long g_fail_alloc_after;  // failure injection: fail the k-th allocation (-1: never)
@@ -72,6 +75,16 @@ inline unsigned long long __ballot(int pred) { return hipemu::ballot(pred); }
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 extern "C" double __ockl_wfred_add_f64(double v);
 inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
+// only ever applied to wave-uniform values in the kernels
+inline int __builtin_amdgcn_readfirstlane(int x) { return x; }
+// clang's 4 x double vector type, as GCC's generic vector of the same size
+// (the kernels only use it for FP64 MFMA accumulators)
+#define ext_vector_type(n) vector_size((n) * sizeof(double))
+// FP64 16x16x4 matrix FMA over the 64 lanes of a wave: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[l / 16 + 4 i][l % 16]
+inline hipemu::d4 __builtin_amdgcn_mfma_f64_16x16x4f64(double a, double b, hipemu::d4 c, int, int, int) {
+  return hipemu::mfma_f64_16x16x4(a, b, c);
+}
 using std::floor;
 using std::copysign;
 using std::sin;
@@ -107,6 +120,11 @@ hipError_t hipGetLastError();
 hipError_t hipGetDevice(int* d);
 hipError_t hipSetDevice(int d);
 hipError_t hipFuncSetAttribute(const void* f, hipFuncAttribute a, int v);
+hipError_t hipEventCreate(hipEvent_t* e);
+hipError_t hipEventDestroy(hipEvent_t e);
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s = nullptr);
+hipError_t hipEventSynchronize(hipEvent_t e);
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
 template <typename T>
 hipError_t hipMalloc(T** p, size_t n) {
   return hipMalloc((void**)p, n);
