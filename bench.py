@@ -37,6 +37,9 @@ def parse():
                     help="increments of the stream the CPU oracle baseline compresses")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-arm", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, copy one increment device-to-device (a plain copy kernel of known "
+                         "size whose FETCH_SIZE / WRITE_SIZE counters calibrate the projection kernel's)")
     return ap.parse_args()
 
 
@@ -86,6 +89,26 @@ def time_arm(Yd, prec, steps, warmup):
                 kstats=kstats)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_proj_mfma_video240_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2211_12487_amd", "csrc", "proj.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the projection kernel from the committed
+    counter summary, or None when that summary is missing or was taken on
+    another revision of the kernel source."""
+    import hashlib
+    try:
+        fields = dict(line.split(":", 1) for line in open(TRAFFIC_FILE).read().splitlines()
+                      if ":" in line and not line.startswith("#"))
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if fields.get("kernel_source_sha256", "").strip() != src:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def roofline(kstats):
     """Level-1 fused projection kernel (U_1^T Y, ||Y(b)||^2 and the residual
     energy in one pass): algorithmic bytes per launch = the increment read
@@ -98,7 +121,7 @@ def roofline(kstats):
     bytes_per_launch = kstats["bytes"] / n
     achieved = bytes_per_launch / avg_s / 1e9
     return dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                traffic=None, kernel="k_proj_col (level-1 projection + residual energy)",
+                traffic=measured_traffic(), kernel="k_proj_mfma (level-1 projection + residual energy)",
                 launches=n, avg_us=avg_s * 1e6, bytes_per_launch=bytes_per_launch)
 
 
@@ -133,6 +156,14 @@ def main():
     torch.cuda.synchronize()
     print("timing chosen arm", file=sys.stderr, flush=True)
     chosen = time_arm(Yd, a.prec, a.steps, a.warmup)
+    if a.copy_calibration:
+        inc = Yd[:w["batch"]]
+        dst = torch.empty_like(inc)
+        for _ in range(3):
+            dst.copy_(inc)
+        torch.cuda.synchronize()
+        print(f"copy calibration: 3 device copies of {inc.numel() * inc.element_size()} bytes", file=sys.stderr,
+              flush=True)
     fp64 = None
     if not a.no_fp64_arm and a.prec != "fp64":
         print("timing fp64 arm", file=sys.stderr, flush=True)

@@ -69,8 +69,10 @@ enum ttice_option {
                               device work of later calls runs on it (default:
                               the null stream)                                 */
   TTICE_OPT_PROFILE = 6    /* int32_t: 1 = time the kernels listed in enum
-                              ttice_kernel with HIP events on the library's
-                              stream (setting it resets the counters); 0 = off */
+                              ttice_kernel with HIP events carried by their
+                              launches (start and end of the kernel itself, on
+                              the library's stream; setting it resets the
+                              counters); 0 = off                               */
 };
 
 /* Kernels whose launches TTICE_OPT_PROFILE times. */

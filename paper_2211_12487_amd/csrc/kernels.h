@@ -78,9 +78,12 @@ __device__ __forceinline__ int64_t col_off(const View& v, int32_t j) {
 // start (the values there are never used).
 constexpr int kProjTail = 64;
 bool proj_fits(int32_t rows, int32_t r);
+// With ev_start/ev_stop given, the launch carries them as its own start and
+// end timestamps (the dispatch packet's, so they time the kernel alone).
 template <typename TIn>
 hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
-                        const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2);
+                        const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
+                        hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // Scratch the product may use to split a long K-sum across workgroups.
 struct GemmWs {

@@ -24,6 +24,8 @@
 //  * output element i of a D tile on lane (kq, n) is row 16t + 4i + kq.
 // VEC > 1 needs the columns of a frame, the row and frame strides and the
 // base pointers of Z and C to be VEC-aligned (checked on the host).
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace ttice {
@@ -194,7 +196,8 @@ constexpr size_t red_bytes() {
 
 template <typename TIn, int VEC, int RT>
 hipError_t launch_proj(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
-                       const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2) {
+                       const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
+                       hipEvent_t ev0, hipEvent_t ev1) {
   constexpr int W = RT == 4 ? 4 : 8;
   constexpr size_t lds = red_bytes<W, RT * VEC * 4 + VEC>();
   static_assert(lds <= 80 * 1024, "reduction buffer");
@@ -206,17 +209,23 @@ hipError_t launch_proj(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, co
     attr = true;
   }
   const int32_t cols_per_block = 16 * VEC;
-  hipLaunchKernelGGL((k_proj_mfma<TIn, VEC, RT, W>), dim3((unsigned)((Ncol + cols_per_block - 1) / cols_per_block)),
-                     dim3(64 * W), lds, st, rows, r, Ncol, vz, Z, U, ldu, C, vc, znorm2, rho2);
+  const dim3 grid((unsigned)((Ncol + cols_per_block - 1) / cols_per_block));
+  if (ev0 || ev1)
+    hipExtLaunchKernelGGL((k_proj_mfma<TIn, VEC, RT, W>), grid, dim3(64 * W), (uint32_t)lds, st, ev0, ev1, 0u, rows,
+                          r, Ncol, vz, Z, U, ldu, C, vc, znorm2, rho2);
+  else
+    hipLaunchKernelGGL((k_proj_mfma<TIn, VEC, RT, W>), grid, dim3(64 * W), lds, st, rows, r, Ncol, vz, Z, U, ldu, C,
+                       vc, znorm2, rho2);
   return hipGetLastError();
 }
 
 template <typename TIn, int VEC>
 hipError_t launch_rt(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
-                     const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2) {
-  if (r <= 16) return launch_proj<TIn, VEC, 1>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
-  if (r <= 32) return launch_proj<TIn, VEC, 2>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
-  return launch_proj<TIn, VEC, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
+                     const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
+                     hipEvent_t ev0, hipEvent_t ev1) {
+  if (r <= 16) return launch_proj<TIn, VEC, 1>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  if (r <= 32) return launch_proj<TIn, VEC, 2>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  return launch_proj<TIn, VEC, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
 }
 
 // Widest VEC such that every lane's VEC columns are consecutive in memory
@@ -233,23 +242,24 @@ bool proj_fits(int32_t rows, int32_t r) { return r <= 64 && rows > 0; }
 
 template <typename TIn>
 hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
-                        const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2) {
+                        const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
+                        hipEvent_t ev0, hipEvent_t ev1) {
   if (Ncol <= 0) return hipSuccess;
   if (vz.rpf != kUnframed || vc.rpf != kUnframed || r > 64 || rows <= 0) return hipErrorInvalidValue;
   // the widest instantiation reads 16 * 4 doubles of every row of U
   static_assert(kProjTail >= 64, "core allocations must cover the widest row read");
   for (int vec : {4, 2}) {
     if ((Ncol % vec) == 0 && aligned_cols(vz, Z, sizeof(TIn), vec) && (!C || aligned_cols(vc, C, sizeof(double), vec))) {
-      if (vec == 4) return launch_rt<TIn, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
-      return launch_rt<TIn, 2>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
+      if (vec == 4) return launch_rt<TIn, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+      return launch_rt<TIn, 2>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
     }
   }
-  return launch_rt<TIn, 1>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2);
+  return launch_rt<TIn, 1>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
 }
 
 template hipError_t proj_columns<float>(hipStream_t, int32_t, int32_t, int32_t, const float*, View, const double*,
-                                        int64_t, double*, View, double*, double*);
+                                        int64_t, double*, View, double*, double*, hipEvent_t, hipEvent_t);
 template hipError_t proj_columns<double>(hipStream_t, int32_t, int32_t, int32_t, const double*, View, const double*,
-                                         int64_t, double*, View, double*, double*);
+                                         int64_t, double*, View, double*, double*, hipEvent_t, hipEvent_t);
 
 }  // namespace ttice

@@ -314,15 +314,13 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       if (timed) {
         CKS(prof_begin(&e0, &e1));
         ev_bytes.push_back((double)N * P * sizeof(TIn) + (double)r * Ncol * sizeof(double));
-        CK(hipEventRecord(e0, st));
       }
       if (zin_is_input)
-        CK((proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p,
-                                      Ui.ld, out, vout, bn, cp)));
+        CK((proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p, Ui.ld, out,
+                              vout, bn, cp, e0, e1)));
       else
-        CK((proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz,
-                                         Ui.p, Ui.ld, out, vout, bn, cp)));
-      if (timed) CK(hipEventRecord(e1, st));
+        CK((proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz, Ui.p, Ui.ld,
+                                 out, vout, bn, cp, e0, e1)));
     } else {
       if (zin_is_input) {
         CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
@@ -555,7 +553,7 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
     if (fused) {
       if (zin_is_input)
         CK((proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p,
-                                      Ui.ld, out, vout, bn, cp)));
+                              Ui.ld, out, vout, bn, cp)));
       else
         CK((proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz,
                                          Ui.p, Ui.ld, out, vout, bn, cp)));

@@ -104,6 +104,13 @@ inline long max(long a, long b) { return a > b ? a : b; }
 
 #define hipLaunchKernelGGL(kern, grid, block, shmem, stream, ...) \
   hipemu::launch((grid), (block), (shmem), [&]() { kern(__VA_ARGS__); })
+// launch bracketed by two events (recorded on the host clock here)
+#define hipExtLaunchKernelGGL(kern, grid, block, shmem, stream, ev0, ev1, flags, ...) \
+  do {                                                                                \
+    if (ev0) (void)hipEventRecord((ev0), (stream));                                  \
+    hipemu::launch((grid), (block), (shmem), [&]() { kern(__VA_ARGS__); });           \
+    if (ev1) (void)hipEventRecord((ev1), (stream));                                  \
+  } while (0)
 
 hipError_t hipMalloc(void** p, size_t n);
 hipError_t hipFree(void* p);
