@@ -66,6 +66,54 @@ __device__ __forceinline__ void gemm_epilogue(double (&acc)[4][4], int32_t M, in
   }
 }
 
+// One K tile of 16 of the product: thread (lk, ln) loads rows lk, lk+4,
+// lk+8, lk+12 of the tile (column ln of A^T and of B) from clamped in-bounds
+// positions ...
+template <typename TB>
+__device__ __forceinline__ void gemm_load(const double* __restrict__ A, const View& va, int64_t aro, bool aload,
+                                          const TB* __restrict__ B, const View& vb, int64_t bco, int32_t k0,
+                                          int32_t ke, int lk, double (&av)[4], double (&bv)[4]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int32_t kc = min(k0 + lk + 4 * u, ke - 1);
+    av[u] = aload ? A[aro + col_off(va, kc)] : 0.0;
+    bv[u] = (double)B[row_off(vb, kc) + bco];
+  }
+}
+// ... stores them masked into an LDS buffer (returns their B squares) ...
+__device__ __forceinline__ double gemm_store(int32_t k0, int32_t ke, int lk, int ln, bool avalid, bool bvalid,
+                                             const double (&av)[4], const double (&bv)[4], double (*As)[65],
+                                             double (*Bs)[65]) {
+  double bsq = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int kk = lk + 4 * u;
+    const bool kin = k0 + kk < ke;
+    const double a = (kin && avalid) ? av[u] : 0.0;
+    const double b = (kin && bvalid) ? bv[u] : 0.0;
+    As[kk][ln] = a;
+    Bs[kk][ln] = b;
+    bsq = fma(b, b, bsq);
+  }
+  return bsq;
+}
+// ... and multiplies a buffered tile into the 4 x 4 micro-tile.
+__device__ __forceinline__ void gemm_tile(const double (*As)[65], const double (*Bs)[65], int tx, int ty,
+                                          double (&acc)[4][4]) {
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    double a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Generic tiled product  D = alpha A B + beta E  (64 x 64 tiles, 256 threads,
 // 4 x 4 register micro-tiles strided by 16 to spread LDS banks, K staged in
@@ -78,8 +126,8 @@ __global__ __launch_bounds__(256) void k_gemm(int32_t M, int32_t N, int32_t K, i
                                                const TE* __restrict__ E, View ve, TD* __restrict__ D,
                                                View vd, int64_t dz, double* __restrict__ colpart,
                                                double* __restrict__ bnorm) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
+  __shared__ double As[2][16][65];
+  __shared__ double Bs[2][16][65];
   __shared__ double red[256];
   const int t = threadIdx.x;
   const int tx = t & 15, ty = t >> 4;
@@ -106,39 +154,20 @@ __global__ __launch_bounds__(256) void k_gemm(int32_t M, int32_t N, int32_t K, i
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
   double bsq = 0.0;
 
+  // K tiles of 16 go through two LDS buffers; the global loads of the next
+  // tile are in flight while the current one is multiplied (one barrier per
+  // tile).
+  double av[4], bv[4];
+  if (kb < ke) gemm_load(A, va, aro, aload, B, vb, bco, kb, ke, lk, av, bv);  // none when K == 0
+  int buf = 0;
   for (int32_t k0 = kb; k0 < ke; k0 += 16) {
-    double av[4], bv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int32_t kc = min(k0 + lk + 4 * u, ke - 1);
-      av[u] = aload ? A[aro + col_off(va, kc)] : 0.0;
-      bv[u] = (double)B[row_off(vb, kc) + bco];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int kk = lk + 4 * u;
-      const bool kin = k0 + kk < ke;
-      const double a = (kin && avalid) ? av[u] : 0.0;
-      const double b = (kin && bvalid) ? bv[u] : 0.0;
-      As[kk][ln] = a;
-      Bs[kk][ln] = b;
-      bsq = fma(b, b, bsq);
-    }
+    bsq += gemm_store(k0, ke, lk, ln, avalid, bvalid, av, bv, As[buf], Bs[buf]);
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
+    if (k0 + 16 < ke) gemm_load(A, va, aro, aload, B, vb, bco, k0 + 16, ke, lk, av, bv);
+    gemm_tile(As[buf], Bs[buf], tx, ty, acc);
+    buf ^= 1;
   }
+  __syncthreads();
 
   if (bnorm != nullptr && blockIdx.y == 0) {
     red[t] = bsq;
@@ -164,17 +193,46 @@ __global__ __launch_bounds__(256) void k_splitk_finish(int32_t M, int32_t N, int
   const int tx = t & 15, ty = t >> 4;
   const int32_t m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int64_t MN = (int64_t)M * N;
+  // clamped in-bounds offsets of the thread's 16 elements (masked below)
+  int64_t off[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      off[i][j] = (int64_t)min(m0 + ty + 16 * i, M - 1) * N + min(n0 + tx + 16 * j, N - 1);
   double acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int32_t m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
-      double s = 0.0;
-      if (m < M && n < N)
-        for (int32_t z = 0; z < S; ++z) s += part[z * MN + (int64_t)m * N + n];
-      acc[i][j] = s;
-    }
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  // partials z = 0, 1, ... added in order; the loads of four partials of
+  // all 16 elements are in flight together
+  int32_t z = 0;
+  for (; z + 4 <= S; z += 4) {
+    double q[4][4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q[u][i][j] = part[(z + u) * MN + off[i][j]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += q[u][i][j];
+  }
+  for (; z < S; ++z)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] += part[z * MN + off[i][j]];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (m0 + ty + 16 * i >= M || n0 + tx + 16 * j >= N) acc[i][j] = 0.0;
   gemm_epilogue<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, D, vd, colpart, red);
 }
 
@@ -406,8 +464,10 @@ hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk,
   if (N <= 0) return hipSuccess;
   const int32_t gx = (N + 63) / 64, gy = gemm_row_blocks(M);
   const int64_t tiles = (int64_t)gx * gy;
-  if ((kchunk <= 0 || kchunk >= K) && ws.p && !bnorm && M > 0 && K >= 512 && tiles < 96) {
-    int64_t S = std::min<int64_t>((K + 255) / 256, std::max<int64_t>(2, 192 / tiles));
+  if ((kchunk <= 0 || kchunk >= K) && ws.p && !bnorm && M > 0 && K >= 192 && tiles < 96) {
+    // each split covers at least eight K tiles of 16, and at most 16 splits
+    // (the finish kernel adds them in order)
+    int64_t S = std::min<int64_t>({(K + 127) / 128, std::max<int64_t>(2, 192 / tiles), (int64_t)16});
     const int64_t MN = (int64_t)M * N;
     S = std::min<int64_t>(S, ws.len / std::max<int64_t>(MN, 1));
     if (S >= 2) {

@@ -152,6 +152,21 @@ double shfl_xor(double v, int mask) {
   return r;
 }
 
+double quad_perm(double v, int ctrl) {
+  if (ctrl < 0 || ctrl >= 0x100) {
+    fprintf(stderr, "hipemu: only DPP quad permutations are emulated\n");
+    abort();
+  }
+  const unsigned tid = cur;
+  shfl_buf[tid] = v;
+  wave_barrier();
+  const unsigned l = tid & 3u;
+  const unsigned src = (tid & ~3u) | ((unsigned)(ctrl >> (2 * l)) & 3u);
+  const double r = src < nthreads ? shfl_buf[src] : v;
+  wave_barrier();
+  return r;
+}
+
 unsigned long long ballot(int pred) {
   const unsigned tid = cur;
   shfl_buf[tid] = pred ? 1.0 : 0.0;

@@ -52,6 +52,7 @@ extern dim3 g_blockDim, g_gridDim;
 void barrier();
 double shfl_down(double v, int off);
 double shfl_xor(double v, int mask);
+double quad_perm(double v, int ctrl);
 unsigned long long ballot(int pred);
 double wave_reduce_add(double v);
 typedef double d4 __attribute__((vector_size(4 * sizeof(double))));
@@ -77,6 +78,21 @@ extern "C" double __ockl_wfred_add_f64(double v);
 inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
 // only ever applied to wave-uniform values in the kernels
 inline int __builtin_amdgcn_readfirstlane(int x) { return x; }
+// DPP move, quad permutations only (dpp_ctrl < 0x100): lane reads lane
+// 4*(l/4) + ((ctrl >> 2*(l%4)) & 3) of its wave
+inline int __builtin_amdgcn_mov_dpp(int src, int ctrl, int, int, bool) {
+  return (int)hipemu::quad_perm((double)src, ctrl);
+}
+inline long long __double_as_longlong(double x) {
+  long long r;
+  memcpy(&r, &x, 8);
+  return r;
+}
+inline double __longlong_as_double(long long x) {
+  double r;
+  memcpy(&r, &x, 8);
+  return r;
+}
 // clang's 4 x double vector type, as GCC's generic vector of the same size
 // (the kernels only use it for FP64 MFMA accumulators)
 #define ext_vector_type(n) vector_size((n) * sizeof(double))
