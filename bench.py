@@ -8,7 +8,8 @@ increment already resident in HBM.  value = tensors/s = 2048 * steps /
 (summed wall time of the steps).
 
 Both arms run at the same eps and must reach the same TT-ranks: the chosen
-precision (--prec, default fp32 projections) and the plain FP64 path.
+precision (--prec, default FP32 matrix-core projections; the residual SVD is
+FP64 in every arm) and the plain FP64 path.
 """
 import argparse
 import json
@@ -31,7 +32,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"],
+                    help="arithmetic of the level projections in the chosen arm (the residual SVD is FP64)")
     ap.add_argument("--frames", type=int, default=WORKLOAD["frames"])
     ap.add_argument("--cpu-increments", type=int, default=6,
                     help="increments of the stream the CPU oracle baseline compresses")
@@ -89,27 +91,34 @@ def time_arm(Yd, prec, steps, warmup):
                 kstats=kstats)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_proj_mfma_video240_traffic.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2211_12487_amd", "csrc", "proj.hip")
+# level-1 projection kernel of each arm: (name, source file)
+PROJ_KERNEL = {
+    "fp64": ("k_proj_mfma", "proj.hip"),
+    "fp32": ("k_proj_f32", "proj_lp.hip"),
+    "bf16x3": ("k_proj_bf3", "proj_lp.hip"),
+}
 
 
-def measured_traffic():
-    """HBM bytes per launch of the projection kernel from the committed
+def measured_traffic(prec):
+    """HBM bytes per launch of the arm's projection kernel from the committed
     counter summary, or None when that summary is missing or was taken on
-    another revision of the kernel source."""
+    another revision of the kernel's source."""
     import hashlib
+    name, src_file = PROJ_KERNEL[prec]
+    path = os.path.join(ROOT, "profiles", f"{name}_video240_traffic.txt")
     try:
-        fields = dict(line.split(":", 1) for line in open(TRAFFIC_FILE).read().splitlines()
+        fields = dict(line.split(":", 1) for line in open(path).read().splitlines()
                       if ":" in line and not line.startswith("#"))
-        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-        if fields.get("kernel_source_sha256", "").strip() != src:
+        src = os.path.join(ROOT, "paper_2211_12487_amd", "csrc", src_file)
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if fields.get("kernel_source_sha256", "").strip() != digest:
             return None
         return float(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
 
 
-def roofline(kstats):
+def roofline(kstats, prec):
     """Level-1 fused projection kernel (U_1^T Y, ||Y(b)||^2 and the residual
     energy in one pass): algorithmic bytes per launch = the increment read
     once + the r_1 coefficient rows written; duration = mean of its HIP-event
@@ -121,7 +130,8 @@ def roofline(kstats):
     bytes_per_launch = kstats["bytes"] / n
     achieved = bytes_per_launch / avg_s / 1e9
     return dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                traffic=measured_traffic(), kernel="k_proj_mfma (level-1 projection + residual energy)",
+                traffic=measured_traffic(prec),
+                kernel=f"{PROJ_KERNEL[prec][0]} (level-1 projection + residual energy, {prec} products)",
                 launches=n, avg_us=avg_s * 1e6, bytes_per_launch=bytes_per_launch)
 
 
@@ -185,7 +195,7 @@ def main():
         final_ranks=chosen["ranks"], p50_update_ms=chosen["p50_ms"], p99_update_ms=chosen["p99_ms"],
         fp64_arm=(dict(value=fp64["tensors_per_s"], p50_update_ms=fp64["p50_ms"], p99_update_ms=fp64["p99_ms"])
                   if fp64 else None),
-        roofline=roofline(chosen["kstats"]),
+        roofline=roofline(chosen["kstats"], a.prec),
         cpu_baseline=cpu,
     )
     print(json.dumps(out), flush=True)

@@ -46,8 +46,17 @@ enum ttice_status {
 
 enum ttice_dtype { TTICE_F32 = 0, TTICE_F64 = 1 };
 
-/* Arithmetic used for the bulk projections / contractions U^T Y, U (U^T Y).
- * FP64 norms, the residual's SVD and re-orthogonalisation are FP64 always. */
+/* Arithmetic of the one-pass level projections (C = U_i^T Z_i with the
+ * residual energy, eq:first_resid / eq:project_further) in Algorithm 1's
+ * update loop, the HBM-bound step: FP64 matrix cores; FP32 matrix cores with
+ * FP32 accumulation; or split BF16 (each FP32 operand as hi + lo bf16, the
+ * three products hi*hi + hi*lo + lo*hi on BF16 matrix cores, FP32
+ * accumulation).  ||Y||, the residual energies, the residual's SVD, the
+ * re-orthogonalisation, the TT-ICE* check and every rank decision are FP64
+ * in all modes; a norm test whose reduced-precision residual energy lies
+ * within its rounding band of the tolerance is decided again on an FP64
+ * projection.  Reconstructions agree with the FP64 path to about 1e-5
+ * relative in the reduced modes. */
 enum ttice_prec { TTICE_PREC_FP64 = 0, TTICE_PREC_FP32 = 1, TTICE_PREC_BF16X3 = 2 };
 
 /* Algorithm 1 (TT-ICE) or Algorithm 2 (TT-ICE*). */

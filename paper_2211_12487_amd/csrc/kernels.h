@@ -78,12 +78,24 @@ __device__ __forceinline__ int64_t col_off(const View& v, int32_t j) {
 // start (the values there are never used).
 constexpr int kProjTail = 64;
 bool proj_fits(int32_t rows, int32_t r);
-// With ev_start/ev_stop given, the launch carries them as its own start and
-// end timestamps (the dispatch packet's, so they time the kernel alone).
+// prec selects the product's arithmetic (kProj*): FP64 matrix cores; FP32
+// matrix cores with FP32 accumulation; or split-BF16, each FP32 operand as a
+// hi + lo pair of bf16 and the three products hi*hi + hi*lo + lo*hi on BF16
+// matrix cores with FP32 accumulation.  ||z||^2 and the residual energy are
+// FP64 in every mode.  With ev_start/ev_stop given, the launch carries them
+// as its own start and end timestamps (the dispatch packet's, so they time
+// the kernel alone).
+constexpr int kProjFP64 = 0, kProjFP32 = 1, kProjBF16x3 = 2;
 template <typename TIn>
 hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
                         const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
-                        hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                        int prec = kProjFP64, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// The reduced-precision launches behind proj_columns (vec = columns per lane,
+// already checked for alignment).
+template <typename TIn>
+hipError_t proj_columns_lp(hipStream_t st, int prec, int vec, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z,
+                           View vz, const double* U, int64_t ldu, double* C, View vc, double* znorm2,
+                           double* rho2, hipEvent_t ev_start, hipEvent_t ev_stop);
 
 // Scratch the product may use to split a long K-sum across workgroups.
 struct GemmWs {

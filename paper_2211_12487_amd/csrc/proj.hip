@@ -26,48 +26,16 @@
 // base pointers of Z and C to be VEC-aligned (checked on the host).
 #include <hip/hip_ext.h>
 
-#include "kernels.h"
+#include "proj_common.h"
 
 namespace ttice {
 namespace {
 
+using proj::aligned_cols;
+using proj::kChunkQuads;
+using proj::store_vec;
+using proj::Vec;
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int kChunkQuads = 8;  // row quads whose loads are issued together
-
-template <typename T, int VEC>
-struct Vec;
-template <typename T>
-struct Vec<T, 1> {
-  T v[1];
-  __device__ static Vec load(const T* p) { return Vec{{p[0]}}; }
-};
-template <typename T>
-struct Vec<T, 2> {
-  T v[2];
-  __device__ static Vec load(const T* p) {
-    Vec r;
-    __builtin_memcpy(&r.v[0], __builtin_assume_aligned(p, 2 * sizeof(T)), 2 * sizeof(T));
-    return r;
-  }
-};
-template <typename T>
-struct Vec<T, 4> {
-  T v[4];
-  __device__ static Vec load(const T* p) {
-    Vec r;
-    __builtin_memcpy(&r.v[0], __builtin_assume_aligned(p, 4 * sizeof(T)), 4 * sizeof(T));
-    return r;
-  }
-};
-
-template <int VEC>
-__device__ __forceinline__ void store_vec(double* p, const double* v) {
-  if constexpr (VEC == 1) {
-    p[0] = v[0];
-  } else {
-    __builtin_memcpy(__builtin_assume_aligned(p, VEC * sizeof(double)), v, VEC * sizeof(double));
-  }
-}
 
 template <typename TIn, int VEC, int RT, int W>
 __global__ __launch_bounds__(64 * W) void k_proj_mfma(int32_t rows, int32_t r, int32_t Ncol, View vz,
@@ -189,17 +157,12 @@ __global__ __launch_bounds__(64 * W) void k_proj_mfma(int32_t rows, int32_t r, i
   }
 }
 
-template <int W, int NV>
-constexpr size_t red_bytes() {
-  return (size_t)(W / 2) * NV * 64 * sizeof(double);
-}
-
 template <typename TIn, int VEC, int RT>
 hipError_t launch_proj(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
                        const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
                        hipEvent_t ev0, hipEvent_t ev1) {
   constexpr int W = RT == 4 ? 4 : 8;
-  constexpr size_t lds = red_bytes<W, RT * VEC * 4 + VEC>();
+  constexpr size_t lds = proj::red_bytes(W, RT * VEC * 4 + VEC);
   static_assert(lds <= 80 * 1024, "reduction buffer");
   static bool attr = false;
   if (!attr) {
@@ -228,38 +191,35 @@ hipError_t launch_rt(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, cons
   return launch_proj<TIn, VEC, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
 }
 
-// Widest VEC such that every lane's VEC columns are consecutive in memory
-// and VEC-aligned, for Z (elements of TIn) and C.
-bool aligned_cols(const View& v, const void* base, size_t esize, int vec) {
-  if (v.cs != 1 || (v.rs % vec) != 0) return false;
-  if (v.cpf != kUnframed && ((v.cpf % vec) != 0 || (v.cfs % vec) != 0)) return false;
-  return ((uintptr_t)base % (vec * esize)) == 0;
-}
-
 }  // namespace
 
 bool proj_fits(int32_t rows, int32_t r) { return r <= 64 && rows > 0; }
 
 template <typename TIn>
 hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
-                        const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
+                        const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2, int prec,
                         hipEvent_t ev0, hipEvent_t ev1) {
   if (Ncol <= 0) return hipSuccess;
   if (vz.rpf != kUnframed || vc.rpf != kUnframed || r > 64 || rows <= 0) return hipErrorInvalidValue;
   // the widest instantiation reads 16 * 4 doubles of every row of U
   static_assert(kProjTail >= 64, "core allocations must cover the widest row read");
-  for (int vec : {4, 2}) {
-    if ((Ncol % vec) == 0 && aligned_cols(vz, Z, sizeof(TIn), vec) && (!C || aligned_cols(vc, C, sizeof(double), vec))) {
-      if (vec == 4) return launch_rt<TIn, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
-      return launch_rt<TIn, 2>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  int vec = 1;
+  for (int v : {4, 2}) {
+    if ((Ncol % v) == 0 && aligned_cols(vz, Z, sizeof(TIn), v) && (!C || aligned_cols(vc, C, sizeof(double), v))) {
+      vec = v;
+      break;
     }
   }
+  if (prec != kProjFP64)
+    return proj_columns_lp<TIn>(st, prec, vec, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  if (vec == 4) return launch_rt<TIn, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  if (vec == 2) return launch_rt<TIn, 2>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
   return launch_rt<TIn, 1>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
 }
 
 template hipError_t proj_columns<float>(hipStream_t, int32_t, int32_t, int32_t, const float*, View, const double*,
-                                        int64_t, double*, View, double*, double*, hipEvent_t, hipEvent_t);
+                                        int64_t, double*, View, double*, double*, int, hipEvent_t, hipEvent_t);
 template hipError_t proj_columns<double>(hipStream_t, int32_t, int32_t, int32_t, const double*, View, const double*,
-                                         int64_t, double*, View, double*, double*, hipEvent_t, hipEvent_t);
+                                         int64_t, double*, View, double*, double*, int, hipEvent_t, hipEvent_t);
 
 }  // namespace ttice

@@ -1,0 +1,330 @@
+// Reduced-precision variants of the fused column projection (see proj.hip
+// for the FP64 kernel, the layout and the quantities computed):
+//
+//  * FP32: v_mfma_f32_16x16x4f32 on a 16 x 4 tile of U^T (rounded to FP32)
+//    times a 4 x 16 tile of Z, FP32 accumulation;
+//  * split BF16 ("BF16x3"): each FP32 operand x is written as hi + lo with
+//    hi = bf16(x) and lo = bf16(x - hi) (16 significant bits together), and
+//    U^T z is accumulated in FP32 from the three products hi*hi + hi*lo +
+//    lo*hi on v_mfma_f32_16x16x32_bf16 (the lo*lo term is below FP32
+//    rounding of the sum).
+//
+// In both, ||z||^2 is accumulated in FP64 from the input values and the
+// residual energy ||z||^2 - ||c||^2 is formed in FP64 from the rounded
+// coefficients.  The host engine takes the decision of the norm test again
+// in FP64 when that energy lands within the rounding band of the tolerance.
+//
+// Output element i of an FP32-accumulated 16 x 16 tile on lane (kq, n) is
+// row 4*kq + i, column n (measured on the device).
+#include <hip/hip_ext.h>
+
+#include "proj_common.h"
+
+namespace ttice {
+namespace {
+
+using proj::kChunkQuads;
+using proj::store_vec;
+using proj::Vec;
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+// bf16 of an FP32 value, rounded to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// Fixed-order tree over the W waves' FP64 partials (NV per lane), ending in
+// wave 0; the same as the FP64 kernel's.
+template <int W, int NV>
+__device__ __forceinline__ void wave_tree(double (&v)[NV], double* red, int wid, int lane) {
+#pragma unroll
+  for (int h = W / 2; h >= 1; h /= 2) {
+    if (wid >= h && wid < 2 * h) {
+      double* o = red + (int64_t)(wid - h) * NV * 64 + lane;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) o[q * 64] = v[q];
+    }
+    __syncthreads();
+    if (wid < h) {
+      const double* o = red + (int64_t)wid * NV * 64 + lane;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[q] += o[q * 64];
+    }
+    __syncthreads();
+  }
+}
+
+// Wave 0's epilogue: v holds the RT x VEC x 4 tile values (element i of tile
+// (t, g) is row 16t + 4kq + i) then the VEC column energies.
+template <int VEC, int RT, int NV>
+__device__ __forceinline__ void proj_store(const double (&v)[NV], int kq, bool valid, int32_t j, int32_t r,
+                                           double* __restrict__ C, const View& vc, double* __restrict__ znorm2,
+                                           double* __restrict__ rho2) {
+  double cc[VEC], zz[VEC];
+#pragma unroll
+  for (int g = 0; g < VEC; ++g) {
+    cc[g] = 0.0;
+    zz[g] = v[RT * VEC * 4 + g];
+  }
+  const int64_t co = valid ? col_off(vc, j) : 0;
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = 16 * t + 4 * kq + i;
+      if (m < r) {
+        double c[VEC];
+#pragma unroll
+        for (int g = 0; g < VEC; ++g) {
+          c[g] = v[(t * VEC + g) * 4 + i];
+          cc[g] = fma(c[g], c[g], cc[g]);
+        }
+        if (C && valid) store_vec<VEC>(C + row_off(vc, m) + co, c);
+      }
+    }
+#pragma unroll
+  for (int g = 0; g < VEC; ++g) {
+    cc[g] += __shfl_xor(cc[g], 16);
+    cc[g] += __shfl_xor(cc[g], 32);
+    zz[g] += __shfl_xor(zz[g], 16);
+    zz[g] += __shfl_xor(zz[g], 32);
+  }
+  if (kq == 0 && valid) {
+    if (znorm2) store_vec<VEC>(znorm2 + j, zz);
+    if (rho2) {
+      double e[VEC];
+#pragma unroll
+      for (int g = 0; g < VEC; ++g) e[g] = zz[g] - cc[g];
+      store_vec<VEC>(rho2 + j, e);
+    }
+  }
+}
+
+// ---- FP32 matrix cores: row quads, as the FP64 kernel
+template <typename TIn, int VEC, int RT, int W>
+__global__ __launch_bounds__(64 * W) void k_proj_f32(int32_t rows, int32_t r, int32_t Ncol, View vz,
+                                                     const TIn* __restrict__ Z, const double* __restrict__ U,
+                                                     int64_t ldu, double* __restrict__ C, View vc,
+                                                     double* __restrict__ znorm2, double* __restrict__ rho2) {
+  constexpr int NV = RT * VEC * 4 + VEC;
+  HIP_DYNAMIC_SHARED(double, red);
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int kq = lane >> 4, n = lane & 15;
+  const int32_t j = (int32_t)blockIdx.x * (16 * VEC) + VEC * n;
+  const bool valid = j < Ncol;
+  const int64_t coff = valid ? col_off(vz, j) : 0;
+  const int64_t rs = vz.rs;
+  const int32_t nq = (rows + 3) >> 2;
+  const int32_t per = (nq + W - 1) / W;
+  const int32_t q0 = wid * per, q1 = min(nq, q0 + per);
+
+  f4 acc[RT][VEC];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int g = 0; g < VEC; ++g) acc[t][g] = f4{0.f, 0.f, 0.f, 0.f};
+  double zz[VEC];
+#pragma unroll
+  for (int g = 0; g < VEC; ++g) zz[g] = 0.0;
+
+  for (int32_t qb = q0; qb < q1; qb += kChunkQuads) {
+    Vec<TIn, VEC> zr[kChunkQuads];
+    float ur[kChunkQuads][RT];
+#pragma unroll
+    for (int u = 0; u < kChunkQuads; ++u) {
+      const int32_t i = min((qb + u) * 4 + kq, rows - 1);
+      zr[u] = Vec<TIn, VEC>::load(Z + (int64_t)i * rs + coff);
+#pragma unroll
+      for (int t = 0; t < RT; ++t) ur[u][t] = (float)U[(int64_t)i * ldu + 16 * t + n];
+    }
+#pragma unroll
+    for (int u = 0; u < kChunkQuads; ++u) {
+      const bool live = qb + u < q1 && (qb + u) * 4 + kq < rows;
+#pragma unroll
+      for (int g = 0; g < VEC; ++g) {
+        const double zd = live ? (double)zr[u].v[g] : 0.0;
+        zz[g] = fma(zd, zd, zz[g]);
+        const float z = (float)zd;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) acc[t][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[u][t], z, acc[t][g], 0, 0, 0);
+      }
+    }
+  }
+  double v[NV];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int g = 0; g < VEC; ++g)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[(t * VEC + g) * 4 + i] = (double)acc[t][g][i];
+#pragma unroll
+  for (int g = 0; g < VEC; ++g) v[RT * VEC * 4 + g] = zz[g];
+  wave_tree<W, NV>(v, red, wid, lane);
+  if (wid != 0) return;
+  proj_store<VEC, RT, NV>(v, kq, valid, j, r, C, vc, znorm2, rho2);
+}
+
+// ---- split BF16 on BF16 matrix cores: row blocks of 32, lane (kq, n) holds
+// rows 8kq .. 8kq+7 of the block (the 16x16x32 operand layout)
+constexpr int kOcts = 2;  // 32-row blocks whose loads are issued together
+
+template <typename TIn, int VEC, int RT, int W>
+__global__ __launch_bounds__(64 * W) void k_proj_bf3(int32_t rows, int32_t r, int32_t Ncol, View vz,
+                                                     const TIn* __restrict__ Z, const double* __restrict__ U,
+                                                     int64_t ldu, double* __restrict__ C, View vc,
+                                                     double* __restrict__ znorm2, double* __restrict__ rho2) {
+  constexpr int NV = RT * VEC * 4 + VEC;
+  HIP_DYNAMIC_SHARED(double, red);
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int kq = lane >> 4, n = lane & 15;
+  const int32_t j = (int32_t)blockIdx.x * (16 * VEC) + VEC * n;
+  const bool valid = j < Ncol;
+  const int64_t coff = valid ? col_off(vz, j) : 0;
+  const int64_t rs = vz.rs;
+  const int32_t no = (rows + 31) >> 5;
+  const int32_t per = (no + W - 1) / W;
+  const int32_t o0 = wid * per, o1 = min(no, o0 + per);
+
+  f4 acc[RT][VEC];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int g = 0; g < VEC; ++g) acc[t][g] = f4{0.f, 0.f, 0.f, 0.f};
+  double zz[VEC];
+#pragma unroll
+  for (int g = 0; g < VEC; ++g) zz[g] = 0.0;
+
+  for (int32_t ob = o0; ob < o1; ob += kOcts) {
+    Vec<TIn, VEC> zr[kOcts][8];
+    double ur[kOcts][8][RT];
+#pragma unroll
+    for (int o = 0; o < kOcts; ++o)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int32_t i = min((ob + o) * 32 + 8 * kq + q, rows - 1);
+        zr[o][q] = Vec<TIn, VEC>::load(Z + (int64_t)i * rs + coff);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) ur[o][q][t] = U[(int64_t)i * ldu + 16 * t + n];
+      }
+#pragma unroll
+    for (int o = 0; o < kOcts; ++o) {
+      if (ob + o >= o1) break;  // uniform over the wave
+      u16x8 ahi[RT], alo[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const bool live = (ob + o) * 32 + 8 * kq + q < rows;
+          const float a = live ? (float)ur[o][q][t] : 0.f;
+          const unsigned short h = bf16_bits(a);
+          ahi[t][q] = h;
+          alo[t][q] = bf16_bits(a - bf16_value(h));
+        }
+#pragma unroll
+      for (int g = 0; g < VEC; ++g) {
+        u16x8 bhi, blo;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const bool live = (ob + o) * 32 + 8 * kq + q < rows;
+          const double zd = live ? (double)zr[o][q].v[g] : 0.0;
+          zz[g] = fma(zd, zd, zz[g]);
+          const float z = (float)zd;
+          const unsigned short h = bf16_bits(z);
+          bhi[q] = h;
+          blo[q] = bf16_bits(z - bf16_value(h));
+        }
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, bhi), bl = __builtin_bit_cast(bf16x8, blo);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const bf16x8 ah = __builtin_bit_cast(bf16x8, ahi[t]), al = __builtin_bit_cast(bf16x8, alo[t]);
+          acc[t][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[t][g], 0, 0, 0);
+          acc[t][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[t][g], 0, 0, 0);
+          acc[t][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[t][g], 0, 0, 0);
+        }
+      }
+    }
+  }
+  double v[NV];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int g = 0; g < VEC; ++g)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[(t * VEC + g) * 4 + i] = (double)acc[t][g][i];
+#pragma unroll
+  for (int g = 0; g < VEC; ++g) v[RT * VEC * 4 + g] = zz[g];
+  wave_tree<W, NV>(v, red, wid, lane);
+  if (wid != 0) return;
+  proj_store<VEC, RT, NV>(v, kq, valid, j, r, C, vc, znorm2, rho2);
+}
+
+template <int P, typename TIn, int VEC, int RT>
+hipError_t launch_lp(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz, const double* U,
+                     int64_t ldu, double* C, View vc, double* znorm2, double* rho2, hipEvent_t ev0,
+                     hipEvent_t ev1) {
+  constexpr int W = RT == 4 ? 4 : 8;
+  constexpr size_t lds = proj::red_bytes(W, RT * VEC * 4 + VEC);
+  static_assert(lds <= 80 * 1024, "reduction buffer");
+  const void* fn = P == kProjFP32 ? (const void*)k_proj_f32<TIn, VEC, RT, W> : (const void*)k_proj_bf3<TIn, VEC, RT, W>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const dim3 grid((unsigned)((Ncol + 16 * VEC - 1) / (16 * VEC)));
+  if constexpr (P == kProjFP32)
+    hipExtLaunchKernelGGL((k_proj_f32<TIn, VEC, RT, W>), grid, dim3(64 * W), (uint32_t)lds, st, ev0, ev1, 0u, rows, r,
+                          Ncol, vz, Z, U, ldu, C, vc, znorm2, rho2);
+  else
+    hipExtLaunchKernelGGL((k_proj_bf3<TIn, VEC, RT, W>), grid, dim3(64 * W), (uint32_t)lds, st, ev0, ev1, 0u, rows, r,
+                          Ncol, vz, Z, U, ldu, C, vc, znorm2, rho2);
+  return hipGetLastError();
+}
+
+template <int P, typename TIn, int VEC>
+hipError_t launch_lp_rt(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
+                        const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
+                        hipEvent_t ev0, hipEvent_t ev1) {
+  if (r <= 16) return launch_lp<P, TIn, VEC, 1>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  if (r <= 32) return launch_lp<P, TIn, VEC, 2>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  return launch_lp<P, TIn, VEC, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+}
+
+template <int P, typename TIn>
+hipError_t launch_lp_vec(hipStream_t st, int vec, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
+                         const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
+                         hipEvent_t ev0, hipEvent_t ev1) {
+  if (vec == 4) return launch_lp_rt<P, TIn, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  if (vec == 2) return launch_lp_rt<P, TIn, 2>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  return launch_lp_rt<P, TIn, 1>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+}
+
+}  // namespace
+
+template <typename TIn>
+hipError_t proj_columns_lp(hipStream_t st, int prec, int vec, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z,
+                           View vz, const double* U, int64_t ldu, double* C, View vc, double* znorm2,
+                           double* rho2, hipEvent_t ev0, hipEvent_t ev1) {
+  if (prec == kProjFP32)
+    return launch_lp_vec<kProjFP32, TIn>(st, vec, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  if (prec == kProjBF16x3)
+    return launch_lp_vec<kProjBF16x3, TIn>(st, vec, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  return hipErrorInvalidValue;
+}
+
+template hipError_t proj_columns_lp<float>(hipStream_t, int, int, int32_t, int32_t, int32_t, const float*, View,
+                                           const double*, int64_t, double*, View, double*, double*, hipEvent_t,
+                                           hipEvent_t);
+template hipError_t proj_columns_lp<double>(hipStream_t, int, int, int32_t, int32_t, int32_t, const double*, View,
+                                            const double*, int64_t, double*, View, double*, double*, hipEvent_t,
+                                            hipEvent_t);
+
+}  // namespace ttice

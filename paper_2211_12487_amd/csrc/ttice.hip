@@ -133,6 +133,8 @@ struct ttice_state {
   // scratch for K-split products (allocated once per state)
   GemmWs gws() { return GemmWs{as<double>(splitk), (int64_t)(splitk.bytes / sizeof(double))}; }
   int sync_scalars(int n);
+  double lp_band(int pp, int64_t rows) const;
+  int64_t lp_rechecks = 0;  // norm tests taken again in FP64 (reduced precision)
   template <typename TIn>
   int core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, double tol_in, int64_t* rk_pend,
                 ttice_update_info* info, bool use_occ, double* last_out, int64_t last_ld);
@@ -251,6 +253,17 @@ int32_t gram_kchunk(int32_t m, int64_t K) {
 // rk_pend holds the ranks being built (starts as the committed ones).
 // The last level's coefficients go to last_out (row j = frame j, stride
 // last_ld); last_out == nullptr means "into the last core after n_total".
+// Width of the band around the tolerance, as a fraction of tol2, within
+// which a reduced-precision residual energy does not decide the norm test.
+// The energy's error is at most 2 g ||Z_i||^2, with g the relative error of
+// one coefficient (K = rows products rounded to FP32, plus 2^-15 per operand
+// for the bf16 hi + lo split), and ||Z_i||^2 <= ||Y||^2 <= d tol2 / eps^2
+// (Corollary 1; in Algorithm 2 eps_upd >= eps); a factor 2 of slack.
+double ttice_state::lp_band(int pp, int64_t rows) const {
+  const double g = (double)rows * std::ldexp(1.0, -24) + (pp == kProjBF16x3 ? std::ldexp(1.0, -14) : 0.0);
+  return 4.0 * g * (double)d / (eps * eps);
+}
+
 template <typename TIn>
 int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, double tol_in,
                            int64_t* rk_pend, ttice_update_info* info, bool use_occ, double* last_out,
@@ -307,20 +320,23 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
     const bool small = rows * Ncol <= ((int64_t)1 << 22);
     bool have_R = false;
     double* cp = occ_skip ? nullptr : as<double>(colpart);
-    if (fused) {
-      // one pass: ||(I - U U^T) z||^2 = ||z||^2 - ||U^T z||^2 (orthonormal U)
+    // one pass: ||(I - U U^T) z||^2 = ||z||^2 - ||U^T z||^2 (orthonormal U),
+    // in the state's precision (pp) or in FP64
+    auto fused_pass = [&](int pp, bool timed) -> hipError_t {
       hipEvent_t e0 = nullptr, e1 = nullptr;
-      const bool timed = profile && i == 0;
       if (timed) {
-        CKS(prof_begin(&e0, &e1));
+        if (prof_begin(&e0, &e1) != TTICE_OK) return hipErrorOutOfMemory;
         ev_bytes.push_back((double)N * P * sizeof(TIn) + (double)r * Ncol * sizeof(double));
       }
       if (zin_is_input)
-        CK((proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p, Ui.ld, out,
-                              vout, bn, cp, e0, e1)));
-      else
-        CK((proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz, Ui.p, Ui.ld,
-                                 out, vout, bn, cp, e0, e1)));
+        return proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p, Ui.ld, out,
+                                 vout, bn, cp, pp, e0, e1);
+      return proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz, Ui.p, Ui.ld,
+                                  out, vout, bn, cp, pp, e0, e1);
+    };
+    const int pp = prec == TTICE_PREC_FP32 ? kProjFP32 : prec == TTICE_PREC_BF16X3 ? kProjBF16x3 : kProjFP64;
+    if (fused) {
+      CK(fused_pass(pp, profile && i == 0));
     } else {
       if (zin_is_input) {
         CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
@@ -367,6 +383,17 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       }
       rho2 = hs[0];
       if (hs[1] != 0.0 || !isfinite(rho2)) return TTICE_EINVAL;
+      if (fused && pp != kProjFP64 && fabs(rho2 - tol2) <= lp_band(pp, rows) * tol2) {
+        // the reduced-precision energy is within its rounding band of the
+        // tolerance: take the decision on the FP64 projection instead
+        CK(fused_pass(kProjFP64, false));
+        CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
+        CK(total_sum(st, as<double>(fres), N, as<double>(scal)));
+        CKS(sync_scalars(4));
+        rho2 = hs[0];
+        if (hs[1] != 0.0 || !isfinite(rho2)) return TTICE_EINVAL;
+        ++lp_rechecks;
+      }
       rho2 = std::max(rho2, 0.0);
       tail2 = rho2;
 

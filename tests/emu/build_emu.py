@@ -26,7 +26,7 @@ def build(outdir: str, asan: bool = True) -> str:
         cmd += ["-fsanitize=address", "-fno-omit-frame-pointer"]
     objs = []
     for src in SRCS + [os.path.join(HERE, "hipemu.cpp"), os.path.join(HERE, "eig_probe.cpp"),
-                          os.path.join(HERE, "proj_probe.cpp")]:
+                          os.path.join(HERE, "proj_probe.cpp"), os.path.join(HERE, "proj_lp_stub.cpp")]:
         obj = os.path.join(outdir, os.path.basename(src) + ".o")
         lang = ["-x", "c++"] if src.endswith(".hip") else []
         subprocess.run(cmd + ["-c"] + lang + [src, "-o", obj], check=True)
