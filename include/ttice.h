@@ -182,6 +182,77 @@ void ttice_destroy(ttice_state* st);
 /* Static description of a status code. */
 const char* ttice_strerror(int code);
 
+/* ---- Serving: many independent streams on one device --------------------
+ *
+ * A server owns a set of TT-ICE states (one per stream, resident in device
+ * memory) and `workers` host threads, each with its own HIP stream.
+ * Increments submitted to a stream are applied in submission order, one at
+ * a time (Algorithm 1, or Algorithm 2 per the stream's options); increments
+ * of different streams run concurrently on different workers, so the small,
+ * latency-bound launches of one stream's update overlap with other streams'
+ * on the device.  A free worker always takes the stream that has waited
+ * longest (continuous, work-conserving scheduling).  Every stream's result
+ * is independent of the mix it ran in: the library's reductions have a
+ * fixed order, so a stream alone and the same stream among others give
+ * bit-identical cores.
+ *
+ * Admission: each stream reserves a projected footprint for increments of
+ * up to max_batch tensors (level buffers, residual, Gram and eigen
+ * workspace, and cores at the rank bound min(n_1..n_i, n_{i+1}..n_d), but
+ * not the last core, which grows by one row per stored tensor); a stream
+ * whose reservation would exceed the server's budget is refused.
+ *
+ * Ownership: a submitted batch (device pointer) must stay valid and
+ * unchanged until its ticket completes.  Tickets are released once their
+ * completion has been reported by ttice_server_wait or ttice_server_poll. */
+typedef struct ttice_server ttice_server;
+
+/* workers in [1, 64]; budget_bytes > 0.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int ttice_server_create(int32_t workers, int64_t budget_bytes, ttice_server** out);
+
+/* New stream of order-d tensors (ttice_create's arguments) with precision
+ * prec (enum ttice_prec) and algorithm algo (enum ttice_algo), for
+ * increments of at most max_batch tensors; *stream_id receives its id.
+ * Errors: EINVAL, ENOMEM (state allocation, or the reservation exceeds the
+ * remaining budget), ESTATE. */
+int ttice_server_add_stream(ttice_server* srv, int32_t d, const int64_t* dims, double eps, int32_t prec,
+                            int32_t algo, int64_t max_batch, int32_t* stream_id);
+
+/* Queue an increment (ttice_update's batch, n, dtype) on a stream; *ticket
+ * receives its id.  Errors: EINVAL (unknown stream, n < 0 or > max_batch,
+ * bad dtype, null batch with n > 0), ESTATE. */
+int ttice_server_submit(ttice_server* srv, int32_t stream_id, const void* batch, int64_t n, int32_t dtype,
+                        int64_t* ticket);
+
+/* *done = 1 when the ticket has completed; then *status receives
+ * ttice_update's return code, info (host, may be NULL) its report, and the
+ * ticket is released.  Errors: EINVAL (unknown ticket), ESTATE. */
+int ttice_server_poll(ttice_server* srv, int64_t ticket, int32_t* done, int32_t* status,
+                      struct ttice_update_info* info);
+
+/* Block until the ticket completes; as poll with done = 1. */
+int ttice_server_wait(ttice_server* srv, int64_t ticket, int32_t* status, struct ttice_update_info* info);
+
+/* Borrow a stream's state for the read-only calls (ttice_ranks,
+ * ttice_reconstruct, ttice_get_core, ttice_project) once its queue has
+ * drained; the server keeps ownership.  Errors: EINVAL, ESTATE (stream busy
+ * or with queued increments). */
+int ttice_server_stream_state(ttice_server* srv, int32_t stream_id, ttice_state** st);
+
+/* Destroy an idle stream and return its reservation.  Errors: EINVAL,
+ * ESTATE (busy or queued). */
+int ttice_server_remove_stream(ttice_server* srv, int32_t stream_id);
+
+/* Reserved bytes, budget and queued-or-running increments (each may be
+ * NULL).  Errors: ESTATE. */
+int ttice_server_stats(ttice_server* srv, int64_t* reserved_bytes, int64_t* budget_bytes, int64_t* pending);
+
+/* Stop the workers after the increments already running (queued ones are
+ * completed with status ESTATE), then destroy every stream.  No other call
+ * on the server may run concurrently with (or after) this one.  NULL is a
+ * no-op. */
+void ttice_server_destroy(ttice_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -727,15 +727,15 @@ int32_t sym_eig_max() { return kEigMax; }
 hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* w) {
   if (m <= 0) return hipSuccess;
   if (m > kEigMax) return hipErrorInvalidValue;
-  static bool attr = false;
-  if (!attr) {
+  // once per process (thread-safe static initialisation)
+  static const hipError_t attr = [] {
     hipError_t er = set_lds_attr((const void*)k_tridiag);
     if (er == hipSuccess) er = set_lds_attr((const void*)k_bisect);
     if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_eigvecs<true>);
     if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_eigvecs<false>);
-    if (er != hipSuccess) return er;
-    attr = true;
-  }
+    return er;
+  }();
+  if (attr != hipSuccess) return attr;
   // threads: H per column, whole waves
   auto reg_threads = [m](int H) { return (unsigned)(((int64_t)m * H + 63) / 64 * 64); };
   // (measured: the register variant wins for one wave; from two waves on,

@@ -164,13 +164,10 @@ hipError_t launch_proj(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, co
   constexpr int W = RT == 4 ? 4 : 8;
   constexpr size_t lds = proj::red_bytes(W, RT * VEC * 4 + VEC);
   static_assert(lds <= 80 * 1024, "reduction buffer");
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_proj_mfma<TIn, VEC, RT, W>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  // once per process (thread-safe static initialisation)
+  static const hipError_t attr = hipFuncSetAttribute((const void*)k_proj_mfma<TIn, VEC, RT, W>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
   const int32_t cols_per_block = 16 * VEC;
   const dim3 grid((unsigned)((Ncol + cols_per_block - 1) / cols_per_block));
   if (ev0 || ev1)

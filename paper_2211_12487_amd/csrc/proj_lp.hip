@@ -273,12 +273,9 @@ hipError_t launch_lp(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, cons
   constexpr size_t lds = proj::red_bytes(W, RT * VEC * 4 + VEC);
   static_assert(lds <= 80 * 1024, "reduction buffer");
   const void* fn = P == kProjFP32 ? (const void*)k_proj_f32<TIn, VEC, RT, W> : (const void*)k_proj_bf3<TIn, VEC, RT, W>;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  // once per process (thread-safe static initialisation)
+  static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
   const dim3 grid((unsigned)((Ncol + 16 * VEC - 1) / (16 * VEC)));
   if constexpr (P == kProjFP32)
     hipExtLaunchKernelGGL((k_proj_f32<TIn, VEC, RT, W>), grid, dim3(64 * W), (uint32_t)lds, st, ev0, ev1, 0u, rows, r,

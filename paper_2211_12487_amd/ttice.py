@@ -14,7 +14,7 @@ from typing import List, Optional, Sequence
 
 import torch  # loads the HIP runtime the library binds to (same soname)
 
-__all__ = ["lib", "TTICE", "TTICEError", "UpdateInfo", "library_path", "EXPORTS"]
+__all__ = ["lib", "TTICE", "Server", "TTICEError", "UpdateInfo", "library_path", "EXPORTS"]
 
 TTICE_MAX_D = 16
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,6 +37,15 @@ EXPORTS = [
     "ttice_get_kernel_stats",
     "ttice_destroy",
     "ttice_strerror",
+    "ttice_server_create",
+    "ttice_server_add_stream",
+    "ttice_server_submit",
+    "ttice_server_poll",
+    "ttice_server_wait",
+    "ttice_server_stream_state",
+    "ttice_server_remove_stream",
+    "ttice_server_stats",
+    "ttice_server_destroy",
 ]
 
 
@@ -108,8 +117,23 @@ def lib():
     L.ttice_destroy.restype = None
     L.ttice_strerror.argtypes = [ctypes.c_int]
     L.ttice_strerror.restype = ctypes.c_char_p
+    L.ttice_server_create.argtypes = [c_i32, c_i64, ctypes.POINTER(c_vp)]
+    L.ttice_server_add_stream.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i64), c_dbl, c_i32, c_i32, c_i64,
+                                          ctypes.POINTER(c_i32)]
+    L.ttice_server_submit.argtypes = [c_vp, c_i32, c_vp, c_i64, c_i32, ctypes.POINTER(c_i64)]
+    L.ttice_server_poll.argtypes = [c_vp, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
+                                    ctypes.POINTER(UpdateInfo)]
+    L.ttice_server_wait.argtypes = [c_vp, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(UpdateInfo)]
+    L.ttice_server_stream_state.argtypes = [c_vp, c_i32, ctypes.POINTER(c_vp)]
+    L.ttice_server_remove_stream.argtypes = [c_vp, c_i32]
+    L.ttice_server_stats.argtypes = [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
+    L.ttice_server_destroy.argtypes = [c_vp]
+    L.ttice_server_destroy.restype = None
     for name in ("ttice_create", "ttice_set_option", "ttice_update", "ttice_reconstruct",
-                 "ttice_project", "ttice_ranks", "ttice_get_core", "ttice_get_kernel_stats"):
+                 "ttice_project", "ttice_ranks", "ttice_get_core", "ttice_get_kernel_stats",
+                 "ttice_server_create", "ttice_server_add_stream", "ttice_server_submit", "ttice_server_poll",
+                 "ttice_server_wait", "ttice_server_stream_state", "ttice_server_remove_stream",
+                 "ttice_server_stats"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -137,6 +161,21 @@ def _dtype_code(t: torch.dtype) -> int:
 
 class TTICE:
     """One TT-ICE accumulation living on the current HIP device."""
+
+    _owner = True
+
+    @classmethod
+    def _borrowed(cls, handle: ctypes.c_void_p, dims: Sequence[int], eps: float) -> "TTICE":
+        """A view of a state owned elsewhere (a server stream): read-only use,
+        never destroyed from here."""
+        self = cls.__new__(cls)
+        self.dims = tuple(int(n) for n in dims)
+        self.d = len(self.dims)
+        self.eps = float(eps)
+        self._h = handle
+        self.stream = None
+        self._owner = False
+        return self
 
     def __init__(self, dims: Sequence[int], eps: float, prec: str = "fp64", algo: str = "plain",
                  skip_rule: str = "mean", tau: float = 1.0, stream: Optional[torch.cuda.Stream] = None):
@@ -231,8 +270,93 @@ class TTICE:
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
-            lib().ttice_destroy(self._h)
+            if self._owner:
+                lib().ttice_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Many independent TT-ICE streams on one device (ttice_server_*): a
+    native scheduler with `workers` threads, each on its own HIP stream."""
+
+    def __init__(self, workers: int = 4, budget_bytes: int = 64 << 30):
+        h = ctypes.c_void_p()
+        _check(lib().ttice_server_create(int(workers), int(budget_bytes), ctypes.byref(h)), "ttice_server_create")
+        self._h = h
+        self._streams = {}
+        self._inflight = {}  # ticket -> batch tensor kept alive until completion
+
+    def add_stream(self, dims: Sequence[int], eps: float, prec: str = "fp64", algo: str = "plain",
+                   max_batch: int = 64) -> int:
+        dims = tuple(int(n) for n in dims)
+        arr = (ctypes.c_int64 * len(dims))(*dims)
+        sid = ctypes.c_int32()
+        _check(lib().ttice_server_add_stream(self._h, len(dims), arr, float(eps), PREC[prec], ALGO[algo],
+                                             int(max_batch), ctypes.byref(sid)), "ttice_server_add_stream")
+        self._streams[sid.value] = (dims, float(eps))
+        return sid.value
+
+    def submit(self, sid: int, Y: torch.Tensor) -> int:
+        dims = self._streams[sid][0]
+        if not Y.is_cuda:
+            raise ValueError("batch must be a device tensor")
+        if tuple(Y.shape) == dims:
+            Y = Y.unsqueeze(0)
+        if tuple(Y.shape[1:]) != dims:
+            raise ValueError(f"batch shape {tuple(Y.shape)} does not match dims {dims}")
+        Y = Y.contiguous()
+        t = ctypes.c_int64()
+        _check(lib().ttice_server_submit(self._h, int(sid), ctypes.c_void_p(Y.data_ptr()), Y.shape[0],
+                                         _dtype_code(Y.dtype), ctypes.byref(t)), "ttice_server_submit")
+        self._inflight[t.value] = Y
+        return t.value
+
+    def poll(self, ticket: int):
+        """(done, status, info) without blocking; info is None until done."""
+        done, status, info = ctypes.c_int32(), ctypes.c_int32(), UpdateInfo()
+        _check(lib().ttice_server_poll(self._h, int(ticket), ctypes.byref(done), ctypes.byref(status),
+                                       ctypes.byref(info)), "ttice_server_poll")
+        if not done.value:
+            return False, None, None
+        self._inflight.pop(ticket, None)
+        return True, status.value, info.as_dict()
+
+    def wait(self, ticket: int):
+        """(status, info) once the ticket completes."""
+        status, info = ctypes.c_int32(), UpdateInfo()
+        _check(lib().ttice_server_wait(self._h, int(ticket), ctypes.byref(status), ctypes.byref(info)),
+               "ttice_server_wait")
+        self._inflight.pop(ticket, None)
+        return status.value, info.as_dict()
+
+    def stream(self, sid: int) -> TTICE:
+        """The stream's state for read-only calls (its queue must have drained)."""
+        h = ctypes.c_void_p()
+        _check(lib().ttice_server_stream_state(self._h, int(sid), ctypes.byref(h)), "ttice_server_stream_state")
+        dims, eps = self._streams[sid]
+        return TTICE._borrowed(h, dims, eps)
+
+    def remove_stream(self, sid: int) -> None:
+        _check(lib().ttice_server_remove_stream(self._h, int(sid)), "ttice_server_remove_stream")
+        self._streams.pop(sid, None)
+
+    def stats(self) -> dict:
+        r, b, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().ttice_server_stats(self._h, ctypes.byref(r), ctypes.byref(b), ctypes.byref(p)),
+               "ttice_server_stats")
+        return dict(reserved_bytes=r.value, budget_bytes=b.value, pending=p.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ttice_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._inflight.clear()
 
     def __del__(self):  # pragma: no cover
         try:

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 sys.path.insert(0, HERE)
 
-from emu_ttice import EmuError, EmuTTICE, load  # noqa: E402
+from emu_ttice import EmuError, EmuTTICE, UpdateInfo, load  # noqa: E402
 from oracle import TTICE as Oracle  # noqa: E402
 from paper_2211_12487_amd import synth  # noqa: E402
 
@@ -257,6 +257,77 @@ def case_proj_kernel():
                     assert np.abs(zn[b * cols:(b + 1) * cols] - z2).max() <= 1e-13 * z2.max()
                     res = z2 - (Cref * Cref).sum(axis=0)
                     assert np.abs(rh[b * cols:(b + 1) * cols] - res).max() <= 1e-12 * z2.max()
+
+
+def case_server():
+    """The serving layer (one worker thread: the emulation runs one launch at
+    a time): per-stream FIFO order, tickets and statuses, an error that
+    leaves its stream usable, admission against the byte budget, removal,
+    and alone-vs-mix: every stream's cores and reconstructions are
+    bit-identical to the same stream run on its own."""
+    import ctypes
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    srv = vp()
+    assert L.ttice_server_create(1, 1 << 30, ctypes.byref(srv)) == 0
+    specs = [((16, 16, 3), 0.05, 0), ((12, 9, 4), 0.02, 0), ((8, 8, 8), 0.05, 1)]
+    sids, data = [], []
+    for k, (dims, eps, algo) in enumerate(specs):
+        sid = i32()
+        arr = (ctypes.c_int64 * len(dims))(*dims)
+        assert L.ttice_server_add_stream(srv, len(dims), arr, eps, 0, algo, 4, ctypes.byref(sid)) == 0
+        sids.append(sid.value)
+        data.append(list(synth.smooth_separable_stream(10, dims, 3, 1e-3, 1 + k, 40 + k, dtype=np.float64)))
+    # interleave the increments of the three streams; one bad batch on stream 1
+    bad = np.full((2,) + specs[1][0], np.nan)
+    tickets = []  # (stream index, increment index or -1, ticket)
+    keep = []
+    for j in range(max(len(x) for x in data)):
+        for k, sid in enumerate(sids):
+            if j < len(data[k]):
+                Y = np.ascontiguousarray(data[k][j])
+                keep.append(Y)
+                t = i64()
+                assert L.ttice_server_submit(srv, sid, Y.ctypes.data, Y.shape[0], 1, ctypes.byref(t)) == 0
+                tickets.append((k, j, t.value))
+            if k == 1 and j == 2:
+                t = i64()
+                assert L.ttice_server_submit(srv, sid, bad.ctypes.data, 2, 1, ctypes.byref(t)) == 0
+                tickets.append((k, -1, t.value))
+    for k, j, t in tickets:
+        status, info = i32(), UpdateInfo()
+        assert L.ttice_server_wait(srv, t, ctypes.byref(status), ctypes.byref(info)) == 0
+        assert status.value == (-1 if j < 0 else 0), (k, j, status.value)
+        done = i32()
+        assert L.ttice_server_poll(srv, t, ctypes.byref(done), None, None) == -1  # released
+    for k, sid in enumerate(sids):
+        h = vp()
+        assert L.ttice_server_stream_state(srv, sid, ctypes.byref(h)) == 0
+        mixed = EmuTTICE.borrowed(L, h, specs[k][0])
+        alone = EmuTTICE(L, specs[k][0], specs[k][1], algo=specs[k][2])
+        for Y in data[k]:
+            alone.update(Y)
+        assert mixed.ranks() == alone.ranks(), k
+        assert np.array_equal(mixed.reconstruct(), alone.reconstruct()), k
+        for i in range(len(specs[k][0]) + 1):
+            assert np.array_equal(mixed.core(i), alone.core(i)), (k, i)
+        alone.close()
+    reserved, budget, pending = i64(), i64(), i64()
+    assert L.ttice_server_stats(srv, ctypes.byref(reserved), ctypes.byref(budget), ctypes.byref(pending)) == 0
+    assert pending.value == 0 and 0 < reserved.value <= budget.value
+    # admission: a stream whose reservation exceeds what is left is refused
+    big = (ctypes.c_int64 * 3)(512, 512, 512)
+    sid = i32()
+    assert L.ttice_server_add_stream(srv, 3, big, 0.1, 0, 0, 64, ctypes.byref(sid)) == -2
+    # removal returns the reservation; the id is then unknown
+    before = reserved.value
+    assert L.ttice_server_remove_stream(srv, sids[0]) == 0
+    assert L.ttice_server_stats(srv, ctypes.byref(reserved), None, None) == 0
+    assert reserved.value < before
+    t = i64()
+    Y = keep[0]
+    assert L.ttice_server_submit(srv, sids[0], Y.ctypes.data, Y.shape[0], 1, ctypes.byref(t)) == -1
+    assert L.ttice_server_submit(srv, sids[1], None, 5, 1, ctypes.byref(t)) == -1  # null batch / over max_batch
+    L.ttice_server_destroy(srv)
 
 
 CASES = {k[5:]: v for k, v in globals().items() if k.startswith("case_")}

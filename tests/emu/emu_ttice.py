@@ -50,10 +50,29 @@ def load(path):
     L.ttice_destroy.restype = None
     L.hipemu_fail_alloc_after.argtypes = [ctypes.c_longlong]
     L.hipemu_fail_alloc_after.restype = None
+    L.ttice_server_create.argtypes = [i32, i64, ctypes.POINTER(vp)]
+    L.ttice_server_add_stream.argtypes = [vp, i32, ctypes.POINTER(i64), dbl, i32, i32, i64, ctypes.POINTER(i32)]
+    L.ttice_server_submit.argtypes = [vp, i32, vp, i64, i32, ctypes.POINTER(i64)]
+    L.ttice_server_poll.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(UpdateInfo)]
+    L.ttice_server_wait.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(UpdateInfo)]
+    L.ttice_server_stream_state.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    L.ttice_server_remove_stream.argtypes = [vp, i32]
+    L.ttice_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.ttice_server_destroy.argtypes = [vp]
+    L.ttice_server_destroy.restype = None
     return L
 
 
 class EmuTTICE:
+    @classmethod
+    def borrowed(cls, L, handle, dims):
+        """Read-only view of a state owned by a server stream."""
+        self = cls.__new__(cls)
+        self.L, self.dims, self.d, self.h, self.owner = L, tuple(dims), len(dims), handle, False
+        return self
+
+    owner = True
+
     def __init__(self, L, dims, eps, algo=0, prec=0, tau=None, skip_rule=None):
         self.L = L
         self.dims = tuple(dims)
@@ -125,5 +144,6 @@ class EmuTTICE:
 
     def close(self):
         if self.h:
-            self.L.ttice_destroy(self.h)
+            if self.owner:
+                self.L.ttice_destroy(self.h)
             self.h = None

@@ -138,6 +138,8 @@ hipError_t hipMemcpy2DAsync(void* dst, size_t dpitch, const void* src, size_t sp
                             size_t height, hipMemcpyKind k, hipStream_t s);
 hipError_t hipMemsetAsync(void* dst, int v, size_t n, hipStream_t s);
 hipError_t hipStreamSynchronize(hipStream_t s);
+hipError_t hipStreamCreate(hipStream_t* s);
+hipError_t hipStreamDestroy(hipStream_t s);
 hipError_t hipDeviceSynchronize();
 hipError_t hipGetLastError();
 hipError_t hipGetDevice(int* d);
