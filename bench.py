@@ -39,6 +39,13 @@ def parse():
                     help="increments of the stream the CPU oracle baseline compresses")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-arm", action="store_true")
+    ap.add_argument("--workload", default="video240", choices=["video240", "serving"],
+                    help="video240: the headline stream (default); serving: the many-stream mix, reported "
+                         "as arrival-to-completion latency")
+    ap.add_argument("--seconds", type=float, default=10.0, help="serving: length of the arrival trace")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrivals per second")
+    ap.add_argument("--streams", type=int, default=256, help="serving: number of streams")
+    ap.add_argument("--workers", type=int, default=8, help="serving: worker threads of the server")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy one increment device-to-device (a plain copy kernel of known "
                          "size whose FETCH_SIZE / WRITE_SIZE counters calibrate the projection kernel's)")
@@ -150,6 +157,102 @@ def cpu_baseline(Y, n_inc):
                        f"NumPy FP64 + LAPACK, BLAS threads up to {cores}", seconds=dt)
 
 
+SERVING_SHAPES = [(32, 32, 3), (64, 64, 3), (128, 128, 3), (32, 32, 32)]
+SERVING_EPS = [0.01, 0.05, 0.1]
+
+
+def serving(a):
+    """Many-stream serving mix: `streams` streams with shapes drawn from
+    SERVING_SHAPES and eps from SERVING_EPS; Poisson arrivals at `rate` per
+    second, each an increment of 1..64 tensors for a uniformly drawn stream.
+    Every increment is generated on the device before the clock starts (a sum
+    of five separable products of random cosine profiles with N(0,1) weights
+    plus 1e-3 noise, FP32), so inputs are resident in HBM; at its arrival time
+    it is submitted to the server.  Latency = completion - scheduled arrival
+    (the driver's polling adds up to one loop period)."""
+    import torch
+    from paper_2211_12487_amd.ttice import Server
+    rng = np.random.default_rng(0)
+    srv = Server(workers=a.workers, budget_bytes=200 << 30)
+    kinds = [(SERVING_SHAPES[int(rng.integers(len(SERVING_SHAPES)))], SERVING_EPS[int(rng.integers(3))])
+             for _ in range(a.streams)]
+    sids = [srv.add_stream(dims, eps, max_batch=64) for dims, eps in kinds]
+    n_req = int(rng.poisson(a.rate * a.seconds))
+    times = np.sort(rng.uniform(0.0, a.seconds, n_req))
+    who = rng.integers(0, a.streams, n_req)
+    sizes = rng.integers(1, 65, n_req)
+    gen = torch.cuda.Stream()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+
+    def make(dims, n):
+        with torch.cuda.stream(gen):
+            parts = []
+            for ax, nn in enumerate(dims):
+                t = torch.arange(nn, device="cuda", dtype=torch.float32) / max(nn - 1, 1)
+                w = torch.rand((n, 5, 1), device="cuda", generator=g) * 3.0
+                ph = torch.rand((n, 5, 1), device="cuda", generator=g) * (2 * math.pi)
+                parts.append(torch.cos(math.pi * w * t + ph))
+            wt = torch.randn((n, 5), device="cuda", generator=g)
+            Y = (wt[:, :, None, None, None] * parts[0][:, :, :, None, None] * parts[1][:, :, None, :, None]
+                 * parts[2][:, :, None, None, :]).sum(1)
+            Y += 1e-3 * torch.randn(Y.shape, device="cuda", generator=g)
+        gen.synchronize()
+        return Y
+
+    print(f"serving: generating {n_req} increments", file=sys.stderr, flush=True)
+    data = []
+    for k in range(n_req):
+        data.append(make(kinds[int(who[k])][0], int(sizes[k])))
+        if k % 2000 == 1999:
+            print(f"serving: generated {k + 1}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    print(f"serving: {a.streams} streams, {n_req} increments over {a.seconds:.0f} s", file=sys.stderr, flush=True)
+    outstanding = {}
+    lag = []
+    lat, tensors = [], 0
+    t0 = time.perf_counter()
+    k = 0
+    last_report = t0
+    while k < n_req or outstanding:
+        now = time.perf_counter() - t0
+        busy = False
+        while k < n_req and times[k] <= now:
+            outstanding[srv.submit(sids[int(who[k])], data[k])] = (times[k], int(sizes[k]))
+            lag.append(time.perf_counter() - t0 - times[k])
+            data[k] = None  # the server's ticket keeps the tensor alive
+            k += 1
+            busy = True
+        for t in list(outstanding):
+            done, status, _ = srv.poll(t)
+            if done:
+                if status != 0:
+                    raise RuntimeError(f"serving update failed with status {status}")
+                arr, n = outstanding.pop(t)
+                lat.append(time.perf_counter() - t0 - arr)
+                tensors += n
+                busy = True
+        if time.perf_counter() - last_report > 5.0:
+            last_report = time.perf_counter()
+            print(f"serving: {k}/{n_req} submitted, {len(lat)} done", file=sys.stderr, flush=True)
+        if not busy:
+            time.sleep(50e-6)
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat_ms = np.array(lat) * 1e3
+    return dict(
+        metric="serving arrival-to-completion latency p99", value=float(np.percentile(lat_ms, 99)), unit="ms",
+        n_gpus=1, steps=1, warmup=0, ms_per_step=wall * 1e3, higher_is_better=False, scaling="weak",
+        vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=f"serving: {a.streams} streams of {SERVING_SHAPES}, eps in {SERVING_EPS}, "
+                             f"increments of 1..64 tensors, Poisson {a.rate:.0f}/s for {a.seconds:.0f} s, "
+                             f"{a.workers} workers"),
+        p50_ms=float(np.percentile(lat_ms, 50)), p99_ms=float(np.percentile(lat_ms, 99)),
+        max_ms=float(lat_ms.max()), submit_lag_p99_ms=float(np.percentile(np.array(lag) * 1e3, 99)),
+        increments=len(lat), tensors_per_s=tensors / wall,
+        offered_tensors_per_s=float(sizes.sum()) / a.seconds)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -159,6 +262,9 @@ def main():
     import torch
     from paper_2211_12487_amd import ttice
     ttice.lib()
+    if a.workload == "serving":
+        print(json.dumps(serving(a)), flush=True)
+        return
     w = WORKLOAD
     print(f"generating {a.frames} frames", file=sys.stderr, flush=True)
     Y = gen_stream(a.frames)

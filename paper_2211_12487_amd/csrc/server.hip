@@ -131,7 +131,8 @@ int ttice_server_create(int32_t workers, int64_t budget_bytes, ttice_server** ou
   srv->budget = budget_bytes;
   for (int w = 0; w < workers; ++w) {
     hipStream_t s = nullptr;
-    if (hipStreamCreate(&s) != hipSuccess) {
+    // non-blocking: a worker's stream never waits for work on the null stream
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
       (void)hipGetLastError();
       for (hipStream_t x : srv->hip_streams) (void)hipStreamDestroy(x);
       delete srv;

@@ -63,8 +63,9 @@ int status_of(hipError_t e) {
     if (s_ != TTICE_OK) return s_;     \
   } while (0)
 
-// grow-only scratch (contents not preserved)
-int ensure(DevBuf& b, size_t bytes) {
+// grow-only scratch (contents not preserved); the old buffer is freed once
+// the work queued on st (the only stream that uses it) has finished
+int ensure_on(DevBuf& b, size_t bytes, hipStream_t st) {
   if (bytes <= b.bytes && b.p) return TTICE_OK;
   size_t nb = std::max(bytes, b.bytes + b.bytes / 2);
   nb = std::max<size_t>(nb, 256);
@@ -75,7 +76,7 @@ int ensure(DevBuf& b, size_t bytes) {
     return TTICE_ENOMEM;
   }
   if (b.p) {
-    (void)hipDeviceSynchronize();  // the old buffer may still be read by queued work
+    (void)hipStreamSynchronize(st);  // the old buffer may still be read by queued work
     (void)hipFree(b.p);
   }
   b.p = p;
@@ -130,6 +131,7 @@ struct ttice_state {
     return c;
   }
   int grow_core(Core& c, int64_t need_rows, int64_t need_cols, int64_t keep_rows, int64_t keep_cols);
+  int ensure(DevBuf& b, size_t bytes) { return ensure_on(b, bytes, stream); }
   // scratch for K-split products (allocated once per state)
   GemmWs gws() { return GemmWs{as<double>(splitk), (int64_t)(splitk.bytes / sizeof(double))}; }
   int sync_scalars(int n);
@@ -879,10 +881,10 @@ int ttice_project(ttice_state* st, const void* batch, int64_t n, int32_t dtype, 
   if (dtype != TTICE_F32 && dtype != TTICE_F64) return TTICE_EINVAL;
   if (n == 0) return TTICE_OK;
   if (hipSetDevice(st->device) != hipSuccess) return TTICE_EDEVICE;
-  int rc = ensure(st->z[0], (size_t)n * st->P * sizeof(double));
-  if (rc == TTICE_OK) rc = ensure(st->z[1], (size_t)n * st->P * sizeof(double));
-  if (rc == TTICE_OK) rc = ensure(st->scal, 64 * sizeof(double));
-  if (rc == TTICE_OK) rc = ensure(st->splitk, ((size_t)1 << 20) * sizeof(double));
+  int rc = st->ensure(st->z[0], (size_t)n * st->P * sizeof(double));
+  if (rc == TTICE_OK) rc = st->ensure(st->z[1], (size_t)n * st->P * sizeof(double));
+  if (rc == TTICE_OK) rc = st->ensure(st->scal, 64 * sizeof(double));
+  if (rc == TTICE_OK) rc = st->ensure(st->splitk, ((size_t)1 << 20) * sizeof(double));
   int nonfinite = 0;
   if (rc == TTICE_OK) {
     const int64_t rd = std::max<int64_t>(st->rk[st->d], 1);

@@ -139,6 +139,8 @@ hipError_t hipMemcpy2DAsync(void* dst, size_t dpitch, const void* src, size_t sp
 hipError_t hipMemsetAsync(void* dst, int v, size_t n, hipStream_t s);
 hipError_t hipStreamSynchronize(hipStream_t s);
 hipError_t hipStreamCreate(hipStream_t* s);
+#define hipStreamNonBlocking 1
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned flags);
 hipError_t hipStreamDestroy(hipStream_t s);
 hipError_t hipDeviceSynchronize();
 hipError_t hipGetLastError();
