@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: length of the arrival trace")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrivals per second")
     ap.add_argument("--streams", type=int, default=256, help="serving: number of streams")
-    ap.add_argument("--workers", type=int, default=8, help="serving: worker threads of the server")
+    ap.add_argument("--workers", type=int, default=32, help="serving: worker threads of the server")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy one increment device-to-device (a plain copy kernel of known "
                          "size whose FETCH_SIZE / WRITE_SIZE counters calibrate the projection kernel's)")

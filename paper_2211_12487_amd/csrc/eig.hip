@@ -15,6 +15,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace ttice {
 namespace {
 
@@ -227,16 +229,18 @@ __device__ void tri_tail(int32_t n, const double* A, int64_t ld, double* d, doub
 // trailing block is wider than kTriLdsMax run on A in global memory (one
 // thread per column); the remaining block is then copied to LDS and reduced
 // there.  The reflectors end up in A's rows either way.
+// multi_cu: the reflections before the LDS block were already applied by
+// k_tri_mv / k_tri_up.
 __global__ __launch_bounds__(kTriThreads) void k_tridiag(int32_t m, double* __restrict__ A,
                                                          double* __restrict__ d, double* __restrict__ e,
-                                                         double* __restrict__ tau) {
+                                                         double* __restrict__ tau, int32_t multi_cu) {
   HIP_DYNAMIC_SHARED(double, lds);
   __shared__ double red[kWaves];
   __shared__ double red2[kWaves];
   int32_t ksw = 0;
   if (m > kTriLdsMax) {
     ksw = m - kTriLdsMax;
-    tri_steps<1, false>(m, A, m, ksw, lds, red, red2, d, e, tau);
+    if (!multi_cu) tri_steps<1, false>(m, A, m, ksw, lds, red, red2, d, e, tau);
   }
   const int32_t n = m - ksw;
   double* Ab = A + (int64_t)ksw * m + ksw;
@@ -438,6 +442,123 @@ __global__ __launch_bounds__(512) void k_tridiag_reg(int32_t m, double* __restri
     tau[m - 1] = 0.0;
   }
 }
+
+// ---- Reflections of a large Gram matrix spread over many workgroups.
+// Reflection k is two launches over the trailing block (indices k+1..m-1,
+// L = m-k-1 of them), each workgroup owning a contiguous range of its rows:
+//  k_tri_mv: every workgroup forms v_k from row k (the same fixed-order sum
+//    for ||x[1:]||^2 in each, so all agree bit for bit) and computes
+//    p_i = tau_k (A v_k)_i for its rows and its share of p.v;
+//  k_tri_up: gamma = tau_k p.v / 2 from the shares (fixed order),
+//    w = p - gamma v, and A -= v w^T + w v^T on its rows; workgroup 0 stores
+//    v_k in row k of A for the back-transformation.
+// Workspace: vbuf (m), pbuf (m), part (kMaxMvBlocks) doubles.
+constexpr int kMvThreads = 256;
+constexpr int kMaxMvBlocks = 256;
+
+__device__ double block_sum_mv(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  const double s = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(kMvThreads) void k_tri_mv(int32_t m, int32_t k, const double* __restrict__ A,
+                                                       double* __restrict__ d, double* __restrict__ e,
+                                                       double* __restrict__ tau, double* __restrict__ vbuf,
+                                                       double* __restrict__ pbuf, double* __restrict__ part) {
+  HIP_DYNAMIC_SHARED(double, v);  // L
+  __shared__ double red[4];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int32_t L = m - k - 1;
+  const double* rowk = A + (int64_t)k * m + (k + 1);
+  double s = 0.0;
+  for (int32_t j = 1 + t; j < L; j += kMvThreads) s = fma(rowk[j], rowk[j], s);
+  const double sigma = block_sum_mv(s, red);
+  const double alpha = rowk[0];
+  double beta, tk, scale;
+  if (sigma == 0.0) {
+    tk = 0.0;
+    beta = alpha;
+    scale = 0.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+    tk = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  for (int32_t j = t; j < L; j += kMvThreads) {
+    const double vj = (j == 0) ? 1.0 : rowk[j] * scale;
+    v[j] = vj;
+    if (blockIdx.x == 0) vbuf[j] = vj;
+  }
+  if (blockIdx.x == 0 && t == 0) {
+    d[k] = A[(int64_t)k * m + k];
+    e[k] = beta;
+    tau[k] = tk;
+  }
+  __syncthreads();
+  const int32_t G = (int32_t)gridDim.x;
+  const int32_t per = (L + G - 1) / G;
+  const int32_t r0 = (int32_t)blockIdx.x * per, r1 = min(L, r0 + per);
+  double pv = 0.0;
+  for (int32_t i = r0 + wid; i < r1; i += kMvThreads / 64) {
+    const double* row = A + (int64_t)(k + 1 + i) * m + (k + 1);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int32_t j = lane;
+    for (; j + 192 < L; j += 256) {
+      acc[0] = fma(row[j], v[j], acc[0]);
+      acc[1] = fma(row[j + 64], v[j + 64], acc[1]);
+      acc[2] = fma(row[j + 128], v[j + 128], acc[2]);
+      acc[3] = fma(row[j + 192], v[j + 192], acc[3]);
+    }
+    for (; j < L; j += 64) acc[0] = fma(row[j], v[j], acc[0]);
+    const double pi = tk * wave_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    if (lane == 0) {
+      pbuf[i] = pi;
+      pv = fma(pi, v[i], pv);
+    }
+  }
+  pv = block_sum_mv(pv, red);
+  if (t == 0) part[blockIdx.x] = pv;
+}
+
+__global__ __launch_bounds__(kMvThreads) void k_tri_up(int32_t m, int32_t k, double* __restrict__ A,
+                                                       const double* __restrict__ tau,
+                                                       const double* __restrict__ vbuf,
+                                                       const double* __restrict__ pbuf,
+                                                       const double* __restrict__ part, int32_t nparts) {
+  HIP_DYNAMIC_SHARED(double, sh);  // v (L), w (L)
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int32_t L = m - k - 1;
+  const double tk = tau[k];
+  double* v = sh;
+  double* w = sh + L;
+  double pv = 0.0;
+  for (int32_t g = 0; g < nparts; ++g) pv += part[g];
+  const double gam = 0.5 * tk * pv;
+  for (int32_t j = t; j < L; j += kMvThreads) {
+    const double vj = vbuf[j];
+    v[j] = vj;
+    w[j] = tk != 0.0 ? pbuf[j] - gam * vj : 0.0;
+    if (blockIdx.x == 0) A[(int64_t)k * m + (k + 1) + j] = vj;  // v_k kept for the back-transformation
+  }
+  __syncthreads();
+  if (tk == 0.0) return;
+  const int32_t G = (int32_t)gridDim.x;
+  const int32_t per = (L + G - 1) / G;
+  const int32_t r0 = (int32_t)blockIdx.x * per, r1 = min(L, r0 + per);
+  for (int32_t i = r0 + wid; i < r1; i += kMvThreads / 64) {
+    double* row = A + (int64_t)(k + 1 + i) * m + (k + 1);
+    const double vi = v[i], wi = w[i];
+    for (int32_t j = lane; j < L; j += 64) row[j] = row[j] - vi * w[j] - wi * v[j];
+  }
+}
+
+int32_t mv_blocks(int32_t L) { return std::max(1, std::min(kMaxMvBlocks, (L + 15) / 16)); }
 
 size_t tridiag_lds_bytes(int32_t m) {
   const int32_t n = m < kTriLdsMax ? m : kTriLdsMax;
@@ -724,7 +845,8 @@ hipError_t set_lds_attr(const void* f) {
 
 int32_t sym_eig_max() { return kEigMax; }
 
-hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* w) {
+hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* w,
+                       double* ws) {
   if (m <= 0) return hipSuccess;
   if (m > kEigMax) return hipErrorInvalidValue;
   // once per process (thread-safe static initialisation)
@@ -733,6 +855,8 @@ hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* 
     if (er == hipSuccess) er = set_lds_attr((const void*)k_bisect);
     if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_eigvecs<true>);
     if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_eigvecs<false>);
+    if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_up);
+    if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_mv);
     return er;
   }();
   if (attr != hipSuccess) return attr;
@@ -742,8 +866,26 @@ hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* 
   // its per-lane LDS broadcasts make it slower than the LDS kernel)
   if (m <= 32)
     hipLaunchKernelGGL((k_tridiag_reg<2, 16>), dim3(1), dim3(reg_threads(2)), 0, st, m, A, d, e, tau);
-  else
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kTriThreads), tridiag_lds_bytes(m), st, m, A, d, e, tau);
+  else {
+    // reflections whose trailing block is wider than the LDS block run on
+    // many workgroups when a workspace is given
+    const bool multi = ws != nullptr && m > kTriLdsMax;
+    if (multi) {
+      double* vbuf = ws;
+      double* pbuf = ws + m;
+      double* part = ws + 2 * (int64_t)m;
+      for (int32_t k = 0; k < m - kTriLdsMax; ++k) {
+        const int32_t L = m - k - 1;
+        const int32_t G = mv_blocks(L);
+        hipLaunchKernelGGL(k_tri_mv, dim3(G), dim3(kMvThreads), (size_t)L * sizeof(double), st, m, k, A, d, e, tau,
+                           vbuf, pbuf, part);
+        hipLaunchKernelGGL(k_tri_up, dim3(G), dim3(kMvThreads), (size_t)2 * L * sizeof(double), st, m, k, A, tau,
+                           vbuf, pbuf, part, G);
+      }
+    }
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kTriThreads), tridiag_lds_bytes(m), st, m, A, d, e, tau,
+                       (int32_t)multi);
+  }
   hipError_t er = hipGetLastError();
   if (er != hipSuccess) return er;
   hipLaunchKernelGGL(k_bisect, dim3((m + (256 / kSect) - 1) / (256 / kSect)), dim3(256),

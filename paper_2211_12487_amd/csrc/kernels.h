@@ -135,7 +135,11 @@ hipError_t gram_reduce(hipStream_t st, const double* part, int32_t S, int32_t m,
 // sym_eig_max()): A is reduced in place to tridiagonal form T = Q^T A Q (d, e;
 // reflectors kept in A's rows and tau; d, e, tau: m doubles each) and w
 // receives all eigenvalues in decreasing order.
-hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* w);
+// ws: sym_eig_ws(m) doubles of device workspace, or null (then every
+// reflection runs in one workgroup).
+hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* w,
+                       double* ws);
+inline int64_t sym_eig_ws(int32_t m) { return 2 * (int64_t)m + 256; }
 // Eigenvectors of A for its r largest eigenvalues lam[0..r) (from
 // sym_eigvals, decreasing): X (m x r, row-major).  ws: 7*m*r doubles.
 hipError_t sym_eigvecs(hipStream_t st, int32_t m, int32_t r, const double* d, const double* e,

@@ -422,7 +422,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         const int64_t Sg = (K + kchunk - 1) / kchunk;
         CKS(ensure(gpart, (size_t)Sg * m * m * sizeof(double)));
         CKS(ensure(gram, (size_t)m * m * sizeof(double)));
-        CKS(ensure(tri, (size_t)4 * m * sizeof(double)));  // d, e, tau, w
+        CKS(ensure(tri, (size_t)(4 * m + sym_eig_ws((int32_t)m)) * sizeof(double)));  // d, e, tau, w, workspace
         CKS(ensure(order, (size_t)m * sizeof(int32_t)));
         CKS(ensure(lam, (size_t)m * sizeof(double)));
         CKS(ensure(tail, (size_t)(m + 1) * sizeof(double)));
@@ -436,7 +436,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
                                          m * m, nullptr, nullptr)));
         CK(gram_reduce(st, as<double>(gpart), (int32_t)Sg, (int32_t)m, as<double>(gram)));
         if (m > sym_eig_max()) return TTICE_EINVAL;  // documented size limit of the residual's SVD
-        CK(sym_eigvals(st, (int32_t)m, as<double>(gram), dd, ee, tauv, wv));
+        CK(sym_eigvals(st, (int32_t)m, as<double>(gram), dd, ee, tauv, wv, dd + 4 * m));
         const int64_t cap = rows - r;
         CK(select_rank(st, (int32_t)m, wv, tol2, cap, as<int32_t>(order), as<double>(lam),
                        as<double>(tail), as<double>(scal)));

@@ -10,7 +10,9 @@
 extern "C" int hipemu_sym_eig(int m, const double* A_in, double* w, int r, double* X) {
   std::vector<double> A(A_in, A_in + (size_t)m * m);
   std::vector<double> d(m), e(m), tau(m), ws((size_t)7 * m * (r > 0 ? r : 1));
-  if (ttice::sym_eigvals(nullptr, m, A.data(), d.data(), e.data(), tau.data(), w) != hipSuccess) return -1;
+  std::vector<double> ews(ttice::sym_eig_ws(m));
+  if (ttice::sym_eigvals(nullptr, m, A.data(), d.data(), e.data(), tau.data(), w, ews.data()) != hipSuccess)
+    return -1;
   if (r > 0 && ttice::sym_eigvecs(nullptr, m, r, d.data(), e.data(), w, A.data(), tau.data(), ws.data(), X) !=
                    hipSuccess)
     return -2;
@@ -21,5 +23,6 @@ extern "C" int hipemu_sym_eig(int m, const double* A_in, double* w, int r, doubl
 extern "C" int hipemu_tridiag(int m, const double* A_in, double* d, double* e) {
   std::vector<double> A(A_in, A_in + (size_t)m * m);
   std::vector<double> tau(m), w(m);
-  return ttice::sym_eigvals(nullptr, m, A.data(), d, e, tau.data(), w.data()) == hipSuccess ? 0 : -1;
+  std::vector<double> ews(ttice::sym_eig_ws(m));
+  return ttice::sym_eigvals(nullptr, m, A.data(), d, e, tau.data(), w.data(), ews.data()) == hipSuccess ? 0 : -1;
 }

@@ -189,7 +189,7 @@ def case_eigensolver():
         assert L.hipemu_sym_eig(m, G.ctypes.data, w.ctypes.data, r, X.ctypes.data) == 0
         return w, X[:, :r]
 
-    for m in (1, 2, 3, 5, 16, 32, 33, 40, 64, 65, 96, 124, 125, 128, 129, 131):
+    for m in (1, 2, 3, 5, 16, 32, 33, 40, 64, 65, 96, 124, 125, 128, 129, 131, 230):
         B = rng.standard_normal((m, m + 3))
         G = B @ B.T
         w, X = run(G, min(m, 5))
