@@ -98,9 +98,13 @@ hipError_t proj_columns_lp(hipStream_t st, int prec, int vec, int32_t rows, int3
                            double* rho2, hipEvent_t ev_start, hipEvent_t ev_stop);
 
 // Scratch the product may use to split a long K-sum across workgroups.
+// Workspace of K-split products: partial products (len doubles) and one
+// arrival counter per output tile (ncnt of them, zero between products).
 struct GemmWs {
   double* p = nullptr;
   int64_t len = 0;  // doubles
+  int* cnt = nullptr;
+  int32_t ncnt = 0;
 };
 
 // D = alpha * A * B + beta * E over an M x N output, K-sum split into

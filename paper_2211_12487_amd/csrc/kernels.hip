@@ -119,13 +119,14 @@ __device__ __forceinline__ void gemm_tile(const double (*As)[65], const double (
 // 4 x 4 register micro-tiles strided by 16 to spread LDS banks, K staged in
 // chunks of 16 through LDS, FP64 accumulation).
 // ---------------------------------------------------------------------------
-template <typename TB, typename TE, typename TD>
+template <typename TB, typename TE, typename TD, bool kSplit>
 __global__ __launch_bounds__(256) void k_gemm(int32_t M, int32_t N, int32_t K, int32_t kchunk,
                                                double alpha, const double* __restrict__ A, View va,
                                                const TB* __restrict__ B, View vb, double beta,
                                                const TE* __restrict__ E, View ve, TD* __restrict__ D,
                                                View vd, int64_t dz, double* __restrict__ colpart,
-                                               double* __restrict__ bnorm) {
+                                               double* __restrict__ bnorm, double* __restrict__ part,
+                                               int* __restrict__ cnt) {
   __shared__ double As[2][16][65];
   __shared__ double Bs[2][16][65];
   __shared__ double red[256];
@@ -176,64 +177,62 @@ __global__ __launch_bounds__(256) void k_gemm(int32_t M, int32_t N, int32_t K, i
     __syncthreads();
   }
 
-  TD* Dz = D ? D + dz * (int64_t)blockIdx.z : nullptr;
-  gemm_epilogue<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, Dz, vd, colpart, red);
-}
-
-// Second pass of a K-split product: sum the S partial products (fixed
-// order), then the same epilogue as k_gemm.
-template <typename TE, typename TD>
-__global__ __launch_bounds__(256) void k_splitk_finish(int32_t M, int32_t N, int32_t S,
-                                                        const double* __restrict__ part, double alpha,
-                                                        double beta, const TE* __restrict__ E, View ve,
-                                                        TD* __restrict__ D, View vd,
-                                                        double* __restrict__ colpart) {
-  __shared__ double red[256];
-  const int t = threadIdx.x;
-  const int tx = t & 15, ty = t >> 4;
-  const int32_t m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  const int64_t MN = (int64_t)M * N;
-  // clamped in-bounds offsets of the thread's 16 elements (masked below)
-  int64_t off[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      off[i][j] = (int64_t)min(m0 + ty + 16 * i, M - 1) * N + min(n0 + tx + 16 * j, N - 1);
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  // partials z = 0, 1, ... added in order; the loads of four partials of
-  // all 16 elements are in flight together
-  int32_t z = 0;
-  for (; z + 4 <= S; z += 4) {
-    double q[4][4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) q[u][i][j] = part[(z + u) * MN + off[i][j]];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += q[u][i][j];
-  }
-  for (; z < S; ++z)
+  if (kSplit) {
+    // K split over the gridDim.z blocks of this tile: each stores its
+    // partial product; the last one to arrive adds all of them in the order
+    // z = 0, 1, ... (deterministic) and applies the epilogue, then resets
+    // the tile's arrival counter for the next product.
+    const int64_t MN = (int64_t)M * N;
+    const int32_t S = (int32_t)gridDim.z;
+    int64_t off[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] += part[z * MN + off[i][j]];
+      for (int j = 0; j < 4; ++j)
+        off[i][j] = (int64_t)min(m0 + ty + 16 * i, max(M - 1, 0)) * N + min(n0 + tx + 16 * j, N - 1);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (m0 + ty + 16 * i >= M || n0 + tx + 16 * j >= N) acc[i][j] = 0.0;
-  gemm_epilogue<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, D, vd, colpart, red);
+      for (int j = 0; j < 4; ++j)
+        if (m0 + ty + 16 * i < M && n0 + tx + 16 * j < N) part[(int64_t)blockIdx.z * MN + off[i][j]] = acc[i][j];
+    __threadfence();
+    __shared__ int last;
+    const int tile = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if (t == 0) last = atomicAdd(&cnt[tile], 1) == S - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    int32_t z = 0;
+    for (; z + 4 <= S; z += 4) {  // four partials of all 16 elements in flight
+      double q[4][4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) q[u][i][j] = part[(z + u) * MN + off[i][j]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] += q[u][i][j];
+    }
+    for (; z < S; ++z)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += part[z * MN + off[i][j]];
+    if (t == 0) cnt[tile] = 0;
+    gemm_epilogue<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, D, vd, colpart, red);
+    return;
+  }
+  TD* Dz = D ? D + dz * (int64_t)blockIdx.z : nullptr;
+  gemm_epilogue<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, Dz, vd, colpart, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -464,31 +463,29 @@ hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk,
   if (N <= 0) return hipSuccess;
   const int32_t gx = (N + 63) / 64, gy = gemm_row_blocks(M);
   const int64_t tiles = (int64_t)gx * gy;
-  if ((kchunk <= 0 || kchunk >= K) && ws.p && !bnorm && M > 0 && K >= 192 && tiles < 96) {
-    // each split covers at least eight K tiles of 16, and at most 16 splits
-    // (the finish kernel adds them in order)
-    int64_t S = std::min<int64_t>({(K + 127) / 128, std::max<int64_t>(2, 192 / tiles), (int64_t)16});
+  if ((kchunk <= 0 || kchunk >= K) && ws.p && ws.cnt && !bnorm && M > 0 && K >= 64 && tiles <= ws.ncnt &&
+      tiles < 96) {
+    // few output tiles and a long K: split K over grid z (at least two K
+    // tiles of 16 per split, at most 16 splits, about 192 blocks in all);
+    // the last block of each tile adds the partials in order
+    int64_t S = std::min<int64_t>({(K + 31) / 32, std::max<int64_t>(2, 192 / tiles), (int64_t)16});
     const int64_t MN = (int64_t)M * N;
     S = std::min<int64_t>(S, ws.len / std::max<int64_t>(MN, 1));
     if (S >= 2) {
       int64_t chunk = (K + S - 1) / S;
       chunk = ((chunk + 15) / 16) * 16;
       S = (K + chunk - 1) / chunk;
-      hipLaunchKernelGGL((k_gemm<TB, double, double>), dim3(gx, gy, (unsigned)S), dim3(256), 0, st, M, N, K,
-                         (int32_t)chunk, 1.0, A, va, B, vb, 0.0, (const double*)nullptr, View(), ws.p,
-                         row_major(N), MN, (double*)nullptr, (double*)nullptr);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((k_splitk_finish<TE, TD>), dim3(gx, gy), dim3(256), 0, st, M, N, (int32_t)S, ws.p,
-                         alpha, beta, E, ve, D, vd, colpart);
+      hipLaunchKernelGGL((k_gemm<TB, TE, TD, true>), dim3(gx, gy, (unsigned)S), dim3(256), 0, st, M, N, K, (int32_t)chunk,
+                         alpha, A, va, B, vb, beta, E, ve, D, vd, (int64_t)0, colpart, (double*)nullptr, ws.p,
+                         ws.cnt);
       return hipGetLastError();
     }
   }
   if (kchunk <= 0) kchunk = K > 0 ? K : 1;
   const int32_t S = K > 0 ? (K + kchunk - 1) / kchunk : 1;
   dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)S);
-  hipLaunchKernelGGL((k_gemm<TB, TE, TD>), grid, dim3(256), 0, st, M, N, K, kchunk, alpha, A, va, B,
-                     vb, beta, E, ve, D, vd, dz, colpart, bnorm);
+  hipLaunchKernelGGL((k_gemm<TB, TE, TD, false>), grid, dim3(256), 0, st, M, N, K, kchunk, alpha, A, va, B,
+                     vb, beta, E, ve, D, vd, dz, colpart, bnorm, (double*)nullptr, (int*)nullptr);
   return hipGetLastError();
 }
 

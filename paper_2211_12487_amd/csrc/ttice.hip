@@ -89,6 +89,10 @@ T* as(DevBuf& b) {
   return static_cast<T*>(b.p);
 }
 
+// arrival counters of K-split products (one per output tile; such products
+// have fewer than 96 tiles)
+constexpr int32_t kTileCounters = 128;
+
 }  // namespace
 
 struct ttice_state {
@@ -110,7 +114,7 @@ struct ttice_state {
 
   // workspace
   DevBuf z[2], rbuf, colpart, bnorm, fres, fy2, e2acc, scal, gpart, gram, tri, order, lam, tail, W, W2, T,
-      S, dlist, eigws, splitk;
+      S, dlist, eigws, splitk, tilecnt;
   double* hs = nullptr;  // pinned host scalars (64 doubles)
 
   // kernel profiling (TTICE_OPT_PROFILE): event pairs recorded during one
@@ -133,7 +137,19 @@ struct ttice_state {
   int grow_core(Core& c, int64_t need_rows, int64_t need_cols, int64_t keep_rows, int64_t keep_cols);
   int ensure(DevBuf& b, size_t bytes) { return ensure_on(b, bytes, stream); }
   // scratch for K-split products (allocated once per state)
-  GemmWs gws() { return GemmWs{as<double>(splitk), (int64_t)(splitk.bytes / sizeof(double))}; }
+  // K-split products' workspace: partials, and arrival counters that start
+  // at zero and are left at zero by every product
+  int gemm_ws() {
+    CKS(ensure(splitk, ((size_t)1 << 20) * sizeof(double)));
+    if (!tilecnt.p) {
+      CKS(ensure(tilecnt, kTileCounters * sizeof(int)));
+      CK(hipMemsetAsync(tilecnt.p, 0, kTileCounters * sizeof(int), stream));
+    }
+    return TTICE_OK;
+  }
+  GemmWs gws() {
+    return GemmWs{as<double>(splitk), (int64_t)(splitk.bytes / sizeof(double)), as<int>(tilecnt), kTileCounters};
+  }
   int sync_scalars(int n);
   double lp_band(int pp, int64_t rows) const;
   int64_t lp_rechecks = 0;  // norm tests taken again in FP64 (reduced precision)
@@ -181,7 +197,7 @@ ttice_state::~ttice_state() {
     if (U[i].p) (void)hipFree(U[i].p);
   if (Gt.p) (void)hipFree(Gt.p);
   DevBuf* bufs[] = {&z[0], &z[1], &rbuf, &colpart, &bnorm, &fres, &fy2, &e2acc, &scal, &gpart, &gram,
-                    &tri, &order, &lam, &tail, &W, &W2, &T, &S, &dlist, &eigws, &splitk};
+                    &tri, &order, &lam, &tail, &W, &W2, &T, &S, &dlist, &eigws, &splitk, &tilecnt};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (hs) (void)hipHostFree(hs);
@@ -629,7 +645,7 @@ int ttice_state::update_impl(const TIn* batch, int64_t N, ttice_update_info* inf
   CKS(ensure(z[0], (size_t)N * P * sizeof(double)));
   CKS(ensure(z[1], (size_t)N * P * sizeof(double)));
   CKS(ensure(scal, 64 * sizeof(double)));
-  CKS(ensure(splitk, ((size_t)1 << 20) * sizeof(double)));
+  CKS(gemm_ws());
   CKS(grow_core(Gt, n_total + N, std::max<int64_t>(rk[d], 1), n_total, rk[d]));
 
   int64_t rkp[TTICE_MAX_D + 1];
@@ -713,7 +729,7 @@ int ttice_state::reconstruct_impl(int64_t first, int64_t count, TD* out) {
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(count, ((int64_t)1 << 26) / P));
   CKS(ensure(z[0], (size_t)chunk * P * sizeof(double)));
   CKS(ensure(z[1], (size_t)chunk * P * sizeof(double)));
-  CKS(ensure(splitk, ((size_t)1 << 20) * sizeof(double)));
+  CKS(gemm_ws());
   for (int64_t f0 = 0; f0 < count; f0 += chunk) {
     const int64_t cnt = std::min(chunk, count - f0);
     // level d-1 input: the last-core rows of the chosen tensors
@@ -884,7 +900,7 @@ int ttice_project(ttice_state* st, const void* batch, int64_t n, int32_t dtype, 
   int rc = st->ensure(st->z[0], (size_t)n * st->P * sizeof(double));
   if (rc == TTICE_OK) rc = st->ensure(st->z[1], (size_t)n * st->P * sizeof(double));
   if (rc == TTICE_OK) rc = st->ensure(st->scal, 64 * sizeof(double));
-  if (rc == TTICE_OK) rc = st->ensure(st->splitk, ((size_t)1 << 20) * sizeof(double));
+  if (rc == TTICE_OK) rc = st->gemm_ws();
   int nonfinite = 0;
   if (rc == TTICE_OK) {
     const int64_t rd = std::max<int64_t>(st->rk[st->d], 1);

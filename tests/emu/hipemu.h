@@ -70,6 +70,12 @@ extern long long g_fail_alloc_after;  // failure injection: fail the k-th alloca
 inline void __syncthreads() { hipemu::barrier(); }
 inline void __threadfence_block() {}
 inline void __threadfence() {}
+// blocks run one after another here, so a plain add is atomic
+inline int atomicAdd(int* p, int v) {
+  const int o = *p;
+  *p = o + v;
+  return o;
+}
 inline double __shfl_down(double v, int off, int = 64) { return hipemu::shfl_down(v, off); }
 inline double __shfl_xor(double v, int mask, int = 64) { return hipemu::shfl_xor(v, mask); }
 inline unsigned long long __ballot(int pred) { return hipemu::ballot(pred); }
