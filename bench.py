@@ -8,8 +8,8 @@ increment already resident in HBM.  value = tensors/s = 2048 * steps /
 (summed wall time of the steps).
 
 Both arms run at the same eps and must reach the same TT-ranks: the chosen
-precision (--prec, default FP32 matrix-core projections; the residual SVD is
-FP64 in every arm) and the plain FP64 path.
+precision (--prec, default split-BF16 matrix-core projections; the residual
+SVD is FP64 in every arm) and the plain FP64 path.
 """
 import argparse
 import json
@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"],
+    ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
                     help="arithmetic of the level projections in the chosen arm (the residual SVD is FP64)")
     ap.add_argument("--frames", type=int, default=WORKLOAD["frames"])
     ap.add_argument("--cpu-increments", type=int, default=6,

@@ -145,6 +145,13 @@ int ttice_set_option(ttice_state* st, int32_t key, const void* val);
 int ttice_update(ttice_state* st, const void* batch, int64_t n, int32_t dtype,
                  struct ttice_update_info* info);
 
+/* Allocate now the workspace that increments of up to max_batch tensors
+ * use (level buffers, residual, per-column energies, product workspace), so
+ * that later ttice_update calls of that size do not allocate it on their
+ * critical path.  Optional; the Gram matrix and eigen workspace still grow
+ * on demand.  Errors: EINVAL (max_batch < 1), ENOMEM, EDEVICE, ESTATE. */
+int ttice_reserve(ttice_state* st, int64_t max_batch);
+
 /* Write the approximations of stored tensors first .. first+count-1
  * (eq:last_core_latent) to out: device pointer, [count][n_1]...[n_d] C-order,
  * element type dtype.  Errors: EINVAL (range outside [0, n_total), bad

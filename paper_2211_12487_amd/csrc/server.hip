@@ -177,6 +177,7 @@ int ttice_server_add_stream(ttice_server* srv, int32_t d, const int64_t* dims, d
   int rc = ttice_create(d, dims, eps, &st);
   if (rc == TTICE_OK) rc = ttice_set_option(st, TTICE_OPT_PREC, &prec);
   if (rc == TTICE_OK) rc = ttice_set_option(st, TTICE_OPT_ALGO, &algo);
+  if (rc == TTICE_OK) rc = ttice_reserve(st, max_batch);  // resident workspace: no allocation per update
   if (rc != TTICE_OK) {
     ttice_destroy(st);
     release();

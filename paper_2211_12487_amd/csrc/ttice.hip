@@ -847,6 +847,28 @@ int ttice_set_option(ttice_state* st, int32_t key, const void* val) {
   }
 }
 
+int ttice_reserve(ttice_state* st, int64_t max_batch) {
+  if (!st) return TTICE_ESTATE;
+  if (max_batch < 1) return TTICE_EINVAL;
+  if (hipSetDevice(st->device) != hipSuccess) return TTICE_EDEVICE;
+  const size_t np = (size_t)max_batch * (size_t)st->P * sizeof(double);
+  // level buffers, the residual and the level-1 column energies grow with the
+  // batch; the column partials are sized for level 1 (one row per 64-row
+  // block of its rows) and grow on demand at later levels
+  CKS(st->ensure(st->z[0], np));
+  CKS(st->ensure(st->z[1], np));
+  CKS(st->ensure(st->rbuf, np));
+  CKS(st->ensure(st->scal, 64 * sizeof(double)));
+  CKS(st->gemm_ws());
+  CKS(st->ensure(st->bnorm, (size_t)max_batch * st->cols(0) * sizeof(double)));
+  CKS(st->ensure(st->colpart, (size_t)gemm_row_blocks((int32_t)st->dims[0]) * (size_t)max_batch * st->cols(0) *
+                                  sizeof(double)));
+  CKS(st->ensure(st->fres, (size_t)max_batch * sizeof(double)));
+  CKS(st->ensure(st->fy2, (size_t)max_batch * sizeof(double)));
+  CK(hipStreamSynchronize(st->stream));
+  return TTICE_OK;
+}
+
 int ttice_update(ttice_state* st, const void* batch, int64_t n, int32_t dtype, ttice_update_info* info) {
   if (!st) return TTICE_ESTATE;
   if (n < 0 || (n > 0 && !batch)) return TTICE_EINVAL;

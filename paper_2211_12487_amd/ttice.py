@@ -32,6 +32,7 @@ EXPORTS = [
     "ttice_update",
     "ttice_reconstruct",
     "ttice_project",
+    "ttice_reserve",
     "ttice_ranks",
     "ttice_get_core",
     "ttice_get_kernel_stats",
@@ -110,6 +111,7 @@ def lib():
     L.ttice_update.argtypes = [c_vp, c_vp, c_i64, c_i32, ctypes.POINTER(UpdateInfo)]
     L.ttice_reconstruct.argtypes = [c_vp, c_i64, c_i64, c_vp, c_i32]
     L.ttice_project.argtypes = [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp]
+    L.ttice_reserve.argtypes = [c_vp, c_i64]
     L.ttice_ranks.argtypes = [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
     L.ttice_get_core.argtypes = [c_vp, c_i32, c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
     L.ttice_get_kernel_stats.argtypes = [c_vp, c_i32, ctypes.POINTER(KernelStats)]
@@ -130,7 +132,7 @@ def lib():
     L.ttice_server_destroy.argtypes = [c_vp]
     L.ttice_server_destroy.restype = None
     for name in ("ttice_create", "ttice_set_option", "ttice_update", "ttice_reconstruct",
-                 "ttice_project", "ttice_ranks", "ttice_get_core", "ttice_get_kernel_stats",
+                 "ttice_project", "ttice_reserve", "ttice_ranks", "ttice_get_core", "ttice_get_kernel_stats",
                  "ttice_server_create", "ttice_server_add_stream", "ttice_server_submit", "ttice_server_poll",
                  "ttice_server_wait", "ttice_server_stream_state", "ttice_server_remove_stream",
                  "ttice_server_stats"):
@@ -258,6 +260,10 @@ class TTICE:
         if out.numel():
             _check(lib().ttice_get_core(self._h, i, ctypes.c_void_p(out.data_ptr()), None, None), "ttice_get_core")
         return out
+
+    def reserve(self, max_batch: int) -> None:
+        """Allocate the workspace of increments up to max_batch tensors now."""
+        _check(lib().ttice_reserve(self._h, int(max_batch)), "ttice_reserve")
 
     def profile(self, on: bool = True) -> None:
         """Time the profiled kernels with HIP events (resets the counters)."""

@@ -238,3 +238,28 @@ def test_video_full_stream_properties():
             log(f"  video increment {k}: ranks {gi['ranks']} err {err:.4f}")
     assert orthogonality(g) <= 1e-12
     log(f"  worst increment error {worst:.4f}")
+
+
+@pytest.mark.parametrize("skip_rule", ["mean", "batch"])
+def test_star_occupancy_heuristic(skip_rule):
+    """Algorithm 2 with the paper's occupancy threshold tau = 0.8
+    (eq:coreoccupancy) and both skip rules: cores at least 80% full are not
+    updated; decisions, ranks and reconstructions against the oracle."""
+    log(f"case TT-ICE* tau=0.8 skip={skip_rule}")
+    dims, eps = (6, 8, 10), 0.02
+    g = make(dims, eps, algo="star", tau=0.8, skip_rule=skip_rule)
+    o = Oracle(dims, eps, algo="star", tau=0.8, skip_rule=skip_rule)
+    rng = np.random.default_rng(11)
+    batches = [Y + 3e-3 * rng.standard_normal(Y.shape)
+               for Y in synth.tt_lowrank_stream(dims, (5, 12, 6), 48, 4, seed=11)]
+    occ = 0
+    for k, Y in enumerate(batches):
+        gi = g.update(to_dev(Y))
+        oi = o.update(Y)
+        assert gi["skipped"] == oi["skipped"] and gi["used"] == oi["used"], k
+        assert gi["ranks"][1:-1] == oi["ranks"][1:-1], (k, gi["ranks"], oi["ranks"])
+        occ += sum(1 for s in oi.get("occupancy_skip", []) if s)
+    full_reconstruction_error(g, o, 1e-10)
+    assert orthogonality(g) <= 1e-12
+    assert occ > 0
+    log(f"  occupancy skips in the oracle: {occ}")
