@@ -209,7 +209,7 @@ def serving(a):
     torch.cuda.synchronize()
     print(f"serving: {a.streams} streams, {n_req} increments over {a.seconds:.0f} s", file=sys.stderr, flush=True)
     outstanding = {}
-    lag = []
+    lag, arrivals = [], []
     lat, tensors = [], 0
     t0 = time.perf_counter()
     k = 0
@@ -230,6 +230,7 @@ def serving(a):
                     raise RuntimeError(f"serving update failed with status {status}")
                 arr, n = outstanding.pop(t)
                 lat.append(time.perf_counter() - t0 - arr)
+                arrivals.append(arr)
                 tensors += n
                 busy = True
         if time.perf_counter() - last_report > 5.0:
@@ -240,6 +241,7 @@ def serving(a):
     wall = time.perf_counter() - t0
     srv.close()
     lat_ms = np.array(lat) * 1e3
+    steady = lat_ms[np.array(arrivals) >= min(1.0, a.seconds / 2)]  # after the streams' first increments
     return dict(
         metric="serving arrival-to-completion latency p99", value=float(np.percentile(lat_ms, 99)), unit="ms",
         n_gpus=1, steps=1, warmup=0, ms_per_step=wall * 1e3, higher_is_better=False, scaling="weak",
@@ -249,6 +251,7 @@ def serving(a):
                              f"{a.workers} workers"),
         p50_ms=float(np.percentile(lat_ms, 50)), p99_ms=float(np.percentile(lat_ms, 99)),
         max_ms=float(lat_ms.max()), submit_lag_p99_ms=float(np.percentile(np.array(lag) * 1e3, 99)),
+        steady_p50_ms=float(np.percentile(steady, 50)), steady_p99_ms=float(np.percentile(steady, 99)),
         increments=len(lat), tensors_per_s=tensors / wall,
         offered_tensors_per_s=float(sizes.sum()) / a.seconds)
 
