@@ -7,10 +7,12 @@
 // back-transformation with the stored reflectors.
 //
 // Everything here is latency-bound (one workgroup, long dependent chains),
-// so the working sets live in LDS wherever they fit: the trailing block of
-// the reduction once it is at most kTriLdsMax wide, the tridiagonal matrix
-// in the Sturm counts, the per-vector LU factors of inverse iteration and
-// chunks of reflectors in the back-transformation.
+// so the working sets stay on chip: the trailing block of the reduction
+// once it is at most 128 wide in the registers of one workgroup's waves
+// (the first reflections of a larger matrix run on many workgroups), the
+// tridiagonal matrix in the Sturm counts in LDS, the per-vector LU factors
+// of inverse iteration and chunks of reflectors in the back-transformation
+// in LDS.
 #include "kernels.h"
 
 #include <math.h>
@@ -228,19 +230,18 @@ __device__ void tri_tail(int32_t n, const double* A, int64_t ld, double* d, doub
 // Tridiagonalise A (m x m, row-major, ld = m) in place.  Reflections whose
 // trailing block is wider than kTriLdsMax run on A in global memory (one
 // thread per column); the remaining block is then copied to LDS and reduced
-// there.  The reflectors end up in A's rows either way.
-// multi_cu: the reflections before the LDS block were already applied by
-// k_tri_mv / k_tri_up.
+// there.  The reflectors end up in A's rows either way.  (Used when no
+// workspace is given for the many-workgroup reflections.)
 __global__ __launch_bounds__(kTriThreads) void k_tridiag(int32_t m, double* __restrict__ A,
                                                          double* __restrict__ d, double* __restrict__ e,
-                                                         double* __restrict__ tau, int32_t multi_cu) {
+                                                         double* __restrict__ tau) {
   HIP_DYNAMIC_SHARED(double, lds);
   __shared__ double red[kWaves];
   __shared__ double red2[kWaves];
   int32_t ksw = 0;
   if (m > kTriLdsMax) {
     ksw = m - kTriLdsMax;
-    if (!multi_cu) tri_steps<1, false>(m, A, m, ksw, lds, red, red2, d, e, tau);
+    tri_steps<1, false>(m, A, m, ksw, lds, red, red2, d, e, tau);
   }
   const int32_t n = m - ksw;
   double* Ab = A + (int64_t)ksw * m + ksw;
@@ -440,6 +441,173 @@ __global__ __launch_bounds__(512) void k_tridiag_reg(int32_t m, double* __restri
       d[0] = xbuf[0];
     }
     tau[m - 1] = 0.0;
+  }
+}
+
+// ---- Register-distributed variant for blocks up to kRwMax wide: the
+// n x n trailing block at (ksw, ksw) of A (ld = lda) lives in registers,
+// wave w holding the RPW consecutive rows from w * RPW and lane l the
+// columns l, l + 64 (CPL of them).  Reflection k:
+//  * the lane holding column k writes the wave's part of it to LDS (by
+//    symmetry this is x = A[k+1:, k]); one barrier;
+//  * every wave reads all of column k, one entry per lane, and forms
+//    ||x[1:]||^2 with a wave sum (the same sum in every wave), beta, tau and
+//    v_j for the lane's columns;
+//  * v of the wave's own rows comes back from a wave-private LDS copy as
+//    broadcast 16-byte reads, so per-row work is never repeated in every
+//    lane; p = tau A v is formed as column sums of the wave's rows, one
+//    partial row per wave through LDS; one barrier;
+//  * every wave adds the partials in the order w = 0, 1, ..., forms
+//    w = p - (tau/2)(p.v) v on its columns and, through the private copy,
+//    on its rows, and updates its registers.
+// Rows and columns use the same v, built from column k (a mixed row/column
+// v loses the similarity once rounding makes the block slightly
+// asymmetric).  Same outputs as k_tridiag (dsytd2 order; v_k in row ksw+k,
+// columns ksw+k+1 ..; d, e, tau from ksw).
+constexpr int kRwWaves = 8;
+constexpr int kRwMax = 128;
+
+template <int CPL>
+__global__ __launch_bounds__(kRwWaves * 64) void k_tridiag_rw(int32_t n, int32_t ksw, int32_t lda,
+                                                             double* __restrict__ A, double* __restrict__ d,
+                                                             double* __restrict__ e, double* __restrict__ tau) {
+  static_assert(CPL == 1 || CPL == 2, "one or two columns per lane");
+  typedef double dbl2 __attribute__((ext_vector_type(2)));
+  constexpr int NW = kRwWaves;
+  constexpr int NC = 64 * CPL;  // largest n
+  constexpr int RPW = NC / NW;  // rows per wave (even)
+  __shared__ __attribute__((aligned(16))) double xcol[2][NC];      // column k
+  __shared__ __attribute__((aligned(16))) double part[2][NW][NC];  // per-wave partial column sums of A v
+  __shared__ __attribute__((aligned(16))) double vw[NW][2][NC];    // wave-private v and w
+  const int l = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int32_t r0 = w * RPW;
+  double* Ab = A + (int64_t)ksw * lda + ksw;
+
+  double a[RPW][CPL];
+#pragma unroll
+  for (int q = 0; q < RPW; ++q)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int32_t i = r0 + q, j = l + 64 * c;
+      a[q][c] = (i < n && j < n) ? Ab[(int64_t)i * lda + j] : 0.0;
+    }
+
+  for (int32_t k = 0; k + 2 < n; ++k) {
+    const int buf = k & 1;
+    const int kc = k >> 6, kl = k & 63;
+    if (l == kl) {  // this lane holds column k of the wave's rows
+      dbl2* dst = (dbl2*)&xcol[buf][r0];
+      if (kc == 0) {
+#pragma unroll
+        for (int u = 0; u < RPW / 2; ++u) dst[u] = dbl2{a[2 * u][0], a[2 * u + 1][0]};
+      } else {
+#pragma unroll
+        for (int u = 0; u < RPW / 2; ++u) dst[u] = dbl2{a[2 * u][CPL - 1], a[2 * u + 1][CPL - 1]};
+      }
+    }
+    __syncthreads();
+
+    double xl[CPL];
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int32_t j = l + 64 * c;
+      xl[c] = xcol[buf][j];
+      s = fma(xl[c], (j >= k + 2 && j < n) ? xl[c] : 0.0, s);
+    }
+    const double sigma = wave_sum(s);
+    const double alpha = xcol[buf][k + 1];
+    double beta, tk, scale;
+    if (sigma == 0.0) {
+      tk = 0.0;
+      beta = alpha;
+      scale = 0.0;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+      tk = (beta - alpha) * recip(beta);
+      scale = recip(alpha - beta);
+    }
+    double vc[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int32_t j = l + 64 * c;
+      vc[c] = (j == k + 1) ? 1.0 : ((j > k + 1 && j < n) ? xl[c] * scale : 0.0);
+      if (w == 0 && j > k && j < n) Ab[(int64_t)k * lda + j] = vc[c];  // v_k for the back-transformation
+    }
+    if (threadIdx.x == 0) {
+      d[ksw + k] = xcol[buf][k];
+      e[ksw + k] = beta;
+      tau[ksw + k] = tk;
+    }
+    double vq[RPW];
+    if (tk != 0.0) {  // uniform over the block
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) vw[w][0][l + 64 * c] = vc[c];
+      __builtin_amdgcn_wave_barrier();
+      const dbl2* src = (const dbl2*)&vw[w][0][r0];
+#pragma unroll
+      for (int u = 0; u < RPW / 2; ++u) {
+        const dbl2 t = src[u];
+        vq[2 * u] = t[0];
+        vq[2 * u + 1] = t[1];
+      }
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        double p4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) p4[q & 3] = fma(a[q][c], vq[q], p4[q & 3]);
+        part[buf][w][l + 64 * c] = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+      }
+    }
+    __syncthreads();
+    if (tk != 0.0) {
+      double pc[CPL];
+      double pv = 0.0;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int32_t j = l + 64 * c;
+        double pp[NW];
+#pragma unroll
+        for (int u = 0; u < NW; ++u) pp[u] = part[buf][u][j];
+        const double sp = ((pp[0] + pp[1]) + (pp[2] + pp[3])) + ((pp[4] + pp[5]) + (pp[6] + pp[7]));
+        pc[c] = (j > k && j < n) ? tk * sp : 0.0;
+        pv = fma(pc[c], vc[c], pv);
+      }
+      pv = wave_sum(pv);
+      const double gam = 0.5 * tk * pv;
+      double wc[CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        wc[c] = pc[c] - gam * vc[c];
+        vw[w][1][l + 64 * c] = wc[c];
+      }
+      __builtin_amdgcn_wave_barrier();
+      const dbl2* src = (const dbl2*)&vw[w][1][r0];
+#pragma unroll
+      for (int u = 0; u < RPW / 2; ++u) {
+        const dbl2 t = src[u];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          a[2 * u][c] = a[2 * u][c] - vq[2 * u] * wc[c] - t[0] * vc[c];
+          a[2 * u + 1][c] = a[2 * u + 1][c] - vq[2 * u + 1] * wc[c] - t[1] * vc[c];
+        }
+      }
+    }
+  }
+  // the last 2 x 2 block (or the single entry when n = 1)
+#pragma unroll
+  for (int q = 0; q < RPW; ++q)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int32_t i = r0 + q, j = l + 64 * c;
+      if (i == n - 2 && j == n - 2) d[ksw + n - 2] = a[q][c];
+      if (i == n - 2 && j == n - 1) e[ksw + n - 2] = a[q][c];
+      if (i == n - 1 && j == n - 1) d[ksw + n - 1] = a[q][c];
+    }
+  if (threadIdx.x == 0) {
+    if (n >= 2) tau[ksw + n - 2] = 0.0;
+    tau[ksw + n - 1] = 0.0;
   }
 }
 
@@ -862,29 +1030,32 @@ hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* 
   if (attr != hipSuccess) return attr;
   // threads: H per column, whole waves
   auto reg_threads = [m](int H) { return (unsigned)(((int64_t)m * H + 63) / 64 * 64); };
-  // (measured: the register variant wins for one wave; from two waves on,
-  // its per-lane LDS broadcasts make it slower than the LDS kernel)
-  if (m <= 32)
+  // (measured: the one-wave register variant wins up to m = 32)
+  if (m <= 32) {
     hipLaunchKernelGGL((k_tridiag_reg<2, 16>), dim3(1), dim3(reg_threads(2)), 0, st, m, A, d, e, tau);
-  else {
-    // reflections whose trailing block is wider than the LDS block run on
-    // many workgroups when a workspace is given
-    const bool multi = ws != nullptr && m > kTriLdsMax;
-    if (multi) {
-      double* vbuf = ws;
-      double* pbuf = ws + m;
-      double* part = ws + 2 * (int64_t)m;
-      for (int32_t k = 0; k < m - kTriLdsMax; ++k) {
-        const int32_t L = m - k - 1;
-        const int32_t G = mv_blocks(L);
-        hipLaunchKernelGGL(k_tri_mv, dim3(G), dim3(kMvThreads), (size_t)L * sizeof(double), st, m, k, A, d, e, tau,
-                           vbuf, pbuf, part);
-        hipLaunchKernelGGL(k_tri_up, dim3(G), dim3(kMvThreads), (size_t)2 * L * sizeof(double), st, m, k, A, tau,
-                           vbuf, pbuf, part, G);
-      }
+  } else if (m <= kRwMax) {
+    if (m <= 64)
+      hipLaunchKernelGGL(k_tridiag_rw<1>, dim3(1), dim3(kRwWaves * 64), 0, st, m, 0, m, A, d, e, tau);
+    else
+      hipLaunchKernelGGL(k_tridiag_rw<2>, dim3(1), dim3(kRwWaves * 64), 0, st, m, 0, m, A, d, e, tau);
+  } else if (ws != nullptr) {
+    // reflections whose trailing block is wider than kRwMax on many
+    // workgroups, the rest in registers
+    double* vbuf = ws;
+    double* pbuf = ws + m;
+    double* part = ws + 2 * (int64_t)m;
+    const int32_t ksw = m - kRwMax;
+    for (int32_t k = 0; k < ksw; ++k) {
+      const int32_t L = m - k - 1;
+      const int32_t G = mv_blocks(L);
+      hipLaunchKernelGGL(k_tri_mv, dim3(G), dim3(kMvThreads), (size_t)L * sizeof(double), st, m, k, A, d, e, tau,
+                         vbuf, pbuf, part);
+      hipLaunchKernelGGL(k_tri_up, dim3(G), dim3(kMvThreads), (size_t)2 * L * sizeof(double), st, m, k, A, tau,
+                         vbuf, pbuf, part, G);
     }
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kTriThreads), tridiag_lds_bytes(m), st, m, A, d, e, tau,
-                       (int32_t)multi);
+    hipLaunchKernelGGL(k_tridiag_rw<2>, dim3(1), dim3(kRwWaves * 64), 0, st, kRwMax, ksw, m, A, d, e, tau);
+  } else {
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kTriThreads), tridiag_lds_bytes(m), st, m, A, d, e, tau);
   }
   hipError_t er = hipGetLastError();
   if (er != hipSuccess) return er;

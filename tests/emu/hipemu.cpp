@@ -179,6 +179,22 @@ unsigned long long ballot(int pred) {
   return mask;
 }
 
+void wave_sync() { wave_barrier(); }
+
+int readlane(int x, int lane) {
+  const unsigned tid = cur;
+  shfl_buf[tid] = (double)x;  // exact for every int
+  wave_barrier();
+  const unsigned src = (tid & ~63u) | ((unsigned)lane & 63u);
+  if (lane < 0 || lane > 63 || src >= nthreads || fibers[src].state == DONE) {
+    fprintf(stderr, "hipemu: readlane of lane %d, which is not live\n", lane);
+    abort();
+  }
+  const int r = (int)shfl_buf[src];
+  wave_barrier();
+  return r;
+}
+
 double wave_reduce_add(double v) {
   const unsigned tid = cur;
   shfl_buf[tid] = v;

@@ -54,6 +54,8 @@ double shfl_down(double v, int off);
 double shfl_xor(double v, int mask);
 double quad_perm(double v, int ctrl);
 unsigned long long ballot(int pred);
+int readlane(int x, int lane);
+void wave_sync();
 double wave_reduce_add(double v);
 typedef double d4 __attribute__((vector_size(4 * sizeof(double))));
 d4 mfma_f64_16x16x4(double a, double b, d4 c);
@@ -84,6 +86,11 @@ extern "C" double __ockl_wfred_add_f64(double v);
 inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
 // only ever applied to wave-uniform values in the kernels
 inline int __builtin_amdgcn_readfirstlane(int x) { return x; }
+// every live lane of the wave reaches this point before any goes on
+// (wave-synchronous LDS exchanges)
+inline void __builtin_amdgcn_wave_barrier() { hipemu::wave_sync(); }
+// value of x in lane `lane` of the wave (lane uniform over the wave)
+inline int __builtin_amdgcn_readlane(int x, int lane) { return hipemu::readlane(x, lane); }
 // DPP move, quad permutations only (dpp_ctrl < 0x100): lane reads lane
 // 4*(l/4) + ((ctrl >> 2*(l%4)) & 3) of its wave
 inline int __builtin_amdgcn_mov_dpp(int src, int ctrl, int, int, bool) {
