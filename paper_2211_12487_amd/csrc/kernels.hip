@@ -114,6 +114,182 @@ __device__ __forceinline__ void gemm_tile(const double (*As)[65], const double (
   }
 }
 
+// Fixed-order sum of the S K-split partials of the elements e = t, t + 256,
+// ... (EP of them) of a tile's Mt x Nt block at (m0, n0), PZ partials of
+// each element in flight; the sums go to tile_s[em * 65 + en].
+template <int EP, int PZ>
+__device__ __forceinline__ void split_reduce(const double* __restrict__ part, int32_t S, int64_t MN, int32_t N,
+                                             int32_t m0, int32_t n0, int32_t Nt, int32_t Et, double* tile_s) {
+  const int t = threadIdx.x;
+  double acc[EP];
+  int64_t off[EP];
+  int32_t slot[EP];
+#pragma unroll
+  for (int i = 0; i < EP; ++i) {
+    const int32_t e = t + 256 * i;
+    const int32_t ee = e < Et ? e : 0;  // clamped: every load stays in bounds
+    const int32_t em = ee / Nt, en = ee - em * Nt;
+    off[i] = (int64_t)(m0 + em) * N + (n0 + en);
+    slot[i] = e < Et ? em * 65 + en : -1;
+    acc[i] = 0.0;
+  }
+  int32_t z = 0;
+  for (; z + PZ <= S; z += PZ) {
+    double q[PZ][EP];
+#pragma unroll
+    for (int u = 0; u < PZ; ++u)
+#pragma unroll
+      for (int i = 0; i < EP; ++i) q[u][i] = part[(int64_t)(z + u) * MN + off[i]];
+#pragma unroll
+    for (int u = 0; u < PZ; ++u)
+#pragma unroll
+      for (int i = 0; i < EP; ++i) acc[i] += q[u][i];
+  }
+  for (; z < S; ++z)
+#pragma unroll
+    for (int i = 0; i < EP; ++i) acc[i] += part[(int64_t)z * MN + off[i]];
+#pragma unroll
+  for (int i = 0; i < EP; ++i)
+    if (slot[i] >= 0) tile_s[slot[i]] = acc[i];
+}
+
+// End of a K-split product for one 64 x 64 output tile (256 threads, acc in
+// the (ty + 16 i, tx + 16 j) layout): with gridDim.z = S > 1 slices, each
+// block stores its partial tile; the last block to arrive at the tile's
+// counter adds the S partials in the order z = 0, 1, ... (deterministic:
+// the order does not depend on arrival), resets the counter for the next
+// product and applies the epilogue.  The sums are spread over the threads
+// element by element (one element each when the tile's valid block has at
+// most 256), so many partial loads are in flight per thread, and return to
+// the acc layout through tile_s (64 x 65 doubles of LDS).
+template <typename TE, typename TD>
+__device__ void split_finish(double (&acc)[4][4], int32_t M, int32_t N, int32_t m0, int32_t n0, double alpha,
+                             double beta, const TE* __restrict__ E, const View& ve, TD* __restrict__ D,
+                             const View& vd, double* __restrict__ colpart, double* __restrict__ part,
+                             int* __restrict__ cnt, double* tile_s, double* red) {
+  const int t = threadIdx.x;
+  const int tx = t & 15, ty = t >> 4;
+  const int32_t S = (int32_t)gridDim.z;
+  if (S > 1) {
+    const int64_t MN = (int64_t)M * N;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int32_t m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
+        if (m < M && n < N) part[(int64_t)blockIdx.z * MN + (int64_t)m * N + n] = acc[i][j];
+      }
+    __threadfence();
+    __shared__ int last;
+    const int tile = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if (t == 0) last = atomicAdd(&cnt[tile], 1) == S - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const int32_t Mt = min(64, M - m0), Nt = min(64, N - n0);
+    const int32_t Et = Mt * Nt;
+    if (Et <= 256)
+      split_reduce<1, 16>(part, S, MN, N, m0, n0, Nt, Et, tile_s);
+    else if (Et <= 1024)
+      split_reduce<4, 16>(part, S, MN, N, m0, n0, Nt, Et, tile_s);
+    else
+      split_reduce<16, 4>(part, S, MN, N, m0, n0, Nt, Et, tile_s);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int32_t mi = ty + 16 * i, nj = tx + 16 * j;
+        acc[i][j] = (mi < Mt && nj < Nt) ? tile_s[mi * 65 + nj] : 0.0;
+      }
+    if (t == 0) cnt[tile] = 0;
+  }
+  gemm_epilogue<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, D, vd, colpart, red);
+}
+
+// ---------------------------------------------------------------------------
+// K-split product on the FP64 matrix cores for small outputs (each tile's
+// valid block at most four 16 x 16 sub-blocks: M, N <= 32, or one of them
+// <= 16) and a long K whose operands are linear along K
+// (A(m, k) = A[row_off(m) + k sa], B(k, n) = B[k sb + col_off(n)]; no
+// frames along K).  Wave w takes sub-block w, and v_mfma_f64_16x16x4f64
+// reads its operands straight from memory in the instruction's layout:
+// lane (q, i) = (l / 16, l % 16) supplies A(m0 + 16 mb + i, k + q) and
+// B(k + q, n0 + 16 nb + i), so no LDS staging and no barrier sit in the K
+// loop.  A batch of 32 k-steps (128 values of k) is loaded at once, 64
+// operand doubles per lane all in flight together (data written by another
+// kernel is about a microsecond away), then multiplied with two accumulator
+// chains; k is clamped into the slice and masked, so every load is
+// unconditional.  The result goes through LDS to the layout of
+// split_finish.  (Larger outputs stay on the LDS-tiled kernel: their
+// single-block reduction of many partials costs more than the matrix cores
+// save.)
+// ---------------------------------------------------------------------------
+typedef double mf4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaBatch = 32;  // k-steps of 4 per load batch
+
+template <typename TB, typename TE, typename TD>
+__global__ __launch_bounds__(256) void k_gemm_mfma(int32_t M, int32_t N, int32_t K, int32_t kchunk, double alpha,
+                                                    const double* __restrict__ A, View va,
+                                                    const TB* __restrict__ B, View vb, double beta,
+                                                    const TE* __restrict__ E, View ve, TD* __restrict__ D, View vd,
+                                                    double* __restrict__ colpart, double* __restrict__ part,
+                                                    int* __restrict__ cnt) {
+  __shared__ double tile_s[64 * 65];
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  const int l = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int i16 = l & 15, kq = l >> 4;
+  const int32_t m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int32_t kb = (int32_t)blockIdx.z * kchunk;
+  const int32_t ke = min(K, kb + kchunk);  // kb < ke: the host sizes the slices
+  const int32_t Mt = min(64, M - m0), Nt = min(64, N - n0);
+  const int nnb = (Nt + 15) >> 4, nsb = ((Mt + 15) >> 4) * nnb;  // nsb <= 4
+  const int mb = w / nnb, nb = w - (w / nnb) * nnb;
+  const int32_t m = m0 + 16 * mb + i16, n = n0 + 16 * nb + i16;
+  const bool ok = w < nsb && m < M;  // waves past the block multiply zeros
+  const int64_t aro = row_off(va, min(m, M - 1));
+  const int64_t bco = col_off(vb, min(n, N - 1));  // columns past N read column N-1; their outputs are dropped
+  const int64_t sa = va.cs, sb = vb.rs;
+
+  mf4 acc0 = mf4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+  for (int32_t k0 = kb; k0 < ke; k0 += 4 * kMfmaBatch) {
+    double av[kMfmaBatch], bv[kMfmaBatch];
+#pragma unroll
+    for (int u = 0; u < kMfmaBatch; ++u) {
+      const int32_t k = k0 + 4 * u + kq;
+      const int32_t kc = min(k, ke - 1);
+      const double a = A[aro + (int64_t)kc * sa];
+      const double b = (double)B[(int64_t)kc * sb + bco];
+      av[u] = (k < ke && ok) ? a : 0.0;
+      bv[u] = (k < ke) ? b : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kMfmaBatch; u += 2) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u + 1], bv[u + 1], acc1, 0, 0, 0);
+    }
+  }
+  // element i of lane l of sub-block (mb, nb): row 16 mb + l / 16 + 4 i,
+  // column 16 nb + l % 16
+  if (w < nsb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tile_s[(16 * mb + kq + 4 * i) * 65 + 16 * nb + i16] = acc0[i] + acc1[i];
+  __syncthreads();
+  const int tx = t & 15, ty = t >> 4;
+  double c[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int32_t mi = ty + 16 * i, nj = tx + 16 * j;
+      c[i][j] = (mi < Mt && nj < Nt) ? tile_s[mi * 65 + nj] : 0.0;
+    }
+  __syncthreads();  // tile_s is reused by the split reduction
+  split_finish<TE, TD>(c, M, N, m0, n0, alpha, beta, E, ve, D, vd, colpart, part, cnt, tile_s, red);
+}
+
 // ---------------------------------------------------------------------------
 // Generic tiled product  D = alpha A B + beta E  (64 x 64 tiles, 256 threads,
 // 4 x 4 register micro-tiles strided by 16 to spread LDS banks, K staged in
@@ -127,8 +303,11 @@ __global__ __launch_bounds__(256) void k_gemm(int32_t M, int32_t N, int32_t K, i
                                                View vd, int64_t dz, double* __restrict__ colpart,
                                                double* __restrict__ bnorm, double* __restrict__ part,
                                                int* __restrict__ cnt) {
-  __shared__ double As[2][16][65];
-  __shared__ double Bs[2][16][65];
+  // the two K-tile buffers of A and B; a K-split reduction reuses the same
+  // 4160 doubles as a 64 x 65 tile
+  __shared__ double lds_ab[2 * 2 * 16 * 65];
+  double(*As)[16][65] = (double(*)[16][65])lds_ab;
+  double(*Bs)[16][65] = (double(*)[16][65])(lds_ab + 2 * 16 * 65);
   __shared__ double red[256];
   const int t = threadIdx.x;
   const int tx = t & 15, ty = t >> 4;
@@ -178,57 +357,7 @@ __global__ __launch_bounds__(256) void k_gemm(int32_t M, int32_t N, int32_t K, i
   }
 
   if (kSplit) {
-    // K split over the gridDim.z blocks of this tile: each stores its
-    // partial product; the last one to arrive adds all of them in the order
-    // z = 0, 1, ... (deterministic) and applies the epilogue, then resets
-    // the tile's arrival counter for the next product.
-    const int64_t MN = (int64_t)M * N;
-    const int32_t S = (int32_t)gridDim.z;
-    int64_t off[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        off[i][j] = (int64_t)min(m0 + ty + 16 * i, max(M - 1, 0)) * N + min(n0 + tx + 16 * j, N - 1);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (m0 + ty + 16 * i < M && n0 + tx + 16 * j < N) part[(int64_t)blockIdx.z * MN + off[i][j]] = acc[i][j];
-    __threadfence();
-    __shared__ int last;
-    const int tile = (int)(blockIdx.y * gridDim.x + blockIdx.x);
-    if (t == 0) last = atomicAdd(&cnt[tile], 1) == S - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    int32_t z = 0;
-    for (; z + 4 <= S; z += 4) {  // four partials of all 16 elements in flight
-      double q[4][4][4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) q[u][i][j] = part[(z + u) * MN + off[i][j]];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] += q[u][i][j];
-    }
-    for (; z < S; ++z)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += part[z * MN + off[i][j]];
-    if (t == 0) cnt[tile] = 0;
-    gemm_epilogue<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, D, vd, colpart, red);
+    split_finish<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, D, vd, colpart, part, cnt, lds_ab, red);
     return;
   }
   TD* Dz = D ? D + dz * (int64_t)blockIdx.z : nullptr;
@@ -454,6 +583,8 @@ __global__ __launch_bounds__(256) void k_star_decide(int32_t N, const double* __
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+constexpr int64_t kMfmaMaxSplit = 32;
+
 }  // namespace
 
 template <typename TB, typename TE, typename TD>
@@ -465,11 +596,28 @@ hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk,
   const int64_t tiles = (int64_t)gx * gy;
   if ((kchunk <= 0 || kchunk >= K) && ws.p && ws.cnt && !bnorm && M > 0 && K >= 64 && tiles <= ws.ncnt &&
       tiles < 96) {
-    // few output tiles and a long K: split K over grid z (at least two K
-    // tiles of 16 per split, at most 16 splits, about 192 blocks in all);
-    // the last block of each tile adds the partials in order
-    int64_t S = std::min<int64_t>({(K + 31) / 32, std::max<int64_t>(2, 192 / tiles), (int64_t)16});
+    // few output tiles and a long K: split K over grid z; the last block of
+    // each tile adds the partials in order
     const int64_t MN = (int64_t)M * N;
+    // sub-blocks of 16 x 16 per tile: the largest count, that of the first
+    const int64_t nsb = ((std::min<int64_t>(M, 64) + 15) / 16) * ((std::min<int64_t>(N, 64) + 15) / 16);
+    if (nsb <= 4 && va.cpf == kUnframed && vb.rpf == kUnframed) {
+      // small output, operands linear along K: matrix-core kernel, one load
+      // batch (128 values of k) per slice unless that needs more than
+      // kMfmaMaxSplit slices
+      const int64_t batch = 4 * kMfmaBatch;
+      int64_t S = std::min<int64_t>({(K + batch - 1) / batch, std::max<int64_t>(1, 1024 / tiles), (int64_t)kMfmaMaxSplit});
+      S = std::max<int64_t>(1, std::min<int64_t>(S, ws.len / std::max<int64_t>(MN, 1)));
+      int64_t chunk = (K + S - 1) / S;
+      chunk = ((chunk + 15) / 16) * 16;
+      S = (K + chunk - 1) / chunk;
+      hipLaunchKernelGGL((k_gemm_mfma<TB, TE, TD>), dim3(gx, gy, (unsigned)S), dim3(256), 0, st, M, N, K,
+                         (int32_t)chunk, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart, ws.p, ws.cnt);
+      return hipGetLastError();
+    }
+    // otherwise the LDS-tiled kernel: at least two K tiles of 16 per
+    // split, at most 16 splits, about 192 blocks in all
+    int64_t S = std::min<int64_t>({(K + 31) / 32, std::max<int64_t>(2, 192 / tiles), (int64_t)16});
     S = std::min<int64_t>(S, ws.len / std::max<int64_t>(MN, 1));
     if (S >= 2) {
       int64_t chunk = (K + S - 1) / S;
