@@ -3,8 +3,9 @@
 // Householder reflections (one workgroup), all eigenvalues are found by
 // Sturm-sequence multisection (one wave per eigenvalue, returned in
 // decreasing order), and only the eigenvectors that TT-ICE keeps are formed
-// by inverse iteration on the tridiagonal matrix followed by the
-// back-transformation with the stored reflectors.
+// on the tridiagonal matrix (twisted factorization for isolated
+// eigenvalues, inverse iteration with Gram-Schmidt inside clusters)
+// followed by the back-transformation with the stored reflectors.
 //
 // Everything here is latency-bound (one workgroup, long dependent chains),
 // so the working sets stay on chip: the trailing block of the reduction
@@ -806,71 +807,173 @@ __global__ __launch_bounds__(256) void k_bisect(int32_t m, const double* __restr
 }
 
 // LU with partial pivoting of T - lc I (tridiagonal, LAPACK gttrf order)
-// into DL/DD/DU/DU2/piv; zero or tiny pivots become +-pert.  Serial.
-__device__ void tri_factor(int32_t m, const double* d, const double* e, double lc, double pert, double* DL,
-                           double* DD, double* DU, double* DU2, int32_t* piv) {
-  for (int32_t i = 0; i < m; ++i) {
-    DD[i] = d[i] - lc;
-    if (i + 1 < m) {
-      DL[i] = e[i];
-      DU[i] = e[i];
-    }
-    if (i + 2 < m) DU2[i] = 0.0;
-  }
+// into DL/DD/DU/DU2/piv; zero or tiny pivots become +-pert; DD holds the
+// reciprocal pivots.  Serial; the recurrence runs in registers (the
+// current pivot and the current superdiagonal entry), so each step's chain
+// is a reciprocal and one FMA and the stores never wait.
+__device__ void tri_factor(int32_t m, const double* __restrict__ d, const double* __restrict__ e, double lc,
+                           double pert, double* __restrict__ DL, double* __restrict__ DD, double* __restrict__ DU,
+                           double* __restrict__ DU2, int32_t* __restrict__ piv) {
+  auto store_pivot = [&](int32_t i, double x) {
+    if (fabs(x) < pert) x = x < 0.0 ? -pert : pert;
+    DD[i] = 1.0 / x;
+  };
+  double dd = d[0] - lc;              // DD[i] as updated by step i-1
+  double du = m > 1 ? e[0] : 0.0;     // DU[i] as updated by step i-1
+  // branch-free (both cases formed, one selected), so the loads of the
+  // next steps can be issued ahead
+#pragma unroll 4
   for (int32_t i = 0; i + 1 < m; ++i) {
-    if (fabs(DD[i]) >= fabs(DL[i])) {
-      if (DD[i] == 0.0) DD[i] = pert;
-      const double f = DL[i] / DD[i];
-      DL[i] = f;
-      DD[i + 1] -= f * DU[i];
-      if (i + 2 < m) DU2[i] = 0.0;
-      piv[i] = i;
-    } else {
-      const double f = DD[i] / DL[i];
-      DD[i] = DL[i];
-      DL[i] = f;
-      const double tmp = DU[i];
-      DU[i] = DD[i + 1];
-      DD[i + 1] = tmp - f * DD[i + 1];
-      if (i + 2 < m) {
-        DU2[i] = DU[i + 1];
-        DU[i + 1] = -f * DU[i + 1];
-      }
-      piv[i] = i + 1;
-    }
+    const double dl = e[i];                      // DL[i], untouched so far
+    const double dn = d[i + 1] - lc;             // DD[i+1], untouched so far
+    const double un = i + 2 < m ? e[i + 1] : 0.0;  // DU[i+1], untouched so far
+    const bool keep = fabs(dd) >= fabs(dl);      // else rows i and i+1 are exchanged
+    const double p = keep ? (dd == 0.0 ? pert : dd) : dl;  // pivot
+    const double q = keep ? dl : dd;
+    const double f = q * recip(p);
+    DL[i] = f;
+    DU[i] = keep ? du : dn;
+    DU2[i] = keep ? 0.0 : un;
+    piv[i] = keep ? i : i + 1;
+    store_pivot(i, p);
+    const double ndd = keep ? dn - f * du : du - f * dn;
+    du = keep ? un : -f * un;
+    dd = ndd;
   }
-  for (int32_t i = 0; i < m; ++i) {
-    if (fabs(DD[i]) < pert) DD[i] = DD[i] < 0.0 ? -pert : pert;
-    DD[i] = 1.0 / DD[i];  // stored as reciprocals for the solves
-  }
+  store_pivot(m - 1, dd);
 }
 
 // y <- (T - lc I)^{-1} y from the factors (DD holds reciprocal pivots),
-// rescaled by its largest entry.
-__device__ void tri_solve(int32_t m, const double* DL, const double* DD, const double* DU, const double* DU2,
-                          const int32_t* piv, double* y) {
+// rescaled by its largest entry.  Both sweeps carry their recurrence in
+// registers: one dependent FMA per step (the backward step's y[i+2] term
+// and the pivot scaling are formed off the chain).
+__device__ void tri_solve(int32_t m, const double* __restrict__ DL, const double* __restrict__ DD,
+                          const double* __restrict__ DU, const double* __restrict__ DU2,
+                          const int32_t* __restrict__ piv, double* __restrict__ y) {
+  double cur = y[0];  // y[i] after the exchanges of steps < i
+#pragma unroll 4
   for (int32_t i = 0; i + 1 < m; ++i) {
-    if (piv[i] == i) {
-      y[i + 1] -= DL[i] * y[i];
-    } else {
-      const double tmp = y[i] - DL[i] * y[i + 1];
-      y[i] = y[i + 1];
-      y[i + 1] = tmp;
-    }
+    const double nx = y[i + 1];
+    const double l = DL[i];
+    const bool keep = piv[i] == i;
+    y[i] = keep ? cur : nx;
+    cur = keep ? nx - l * cur : cur - l * nx;
   }
-  y[m - 1] *= DD[m - 1];
-  if (m >= 2) y[m - 2] = (y[m - 2] - DU[m - 2] * y[m - 1]) * DD[m - 2];
-  for (int32_t i = m - 3; i >= 0; --i) y[i] = (y[i] - DU[i] * y[i + 1] - DU2[i] * y[i + 2]) * DD[i];
-  double mx = 0.0;
-  for (int32_t i = 0; i < m; ++i) mx = fmax(mx, fabs(y[i]));
+  double y1 = cur * DD[m - 1];  // y[i+1]
+  double y2 = 0.0;              // y[i+2]
+  y[m - 1] = y1;
+  double mx = fabs(y1);
+#pragma unroll 4
+  for (int32_t i = m - 2; i >= 0; --i) {
+    const double di = DD[i];
+    const double t = (y[i] - DU2[i] * y2) * di;  // DU2[m-2] = 0
+    const double yi = t - (DU[i] * di) * y1;
+    y[i] = yi;
+    mx = fmax(mx, fabs(yi));
+    y2 = y1;
+    y1 = yi;
+  }
   const double s = mx > 0.0 ? 1.0 / mx : 1.0;
   for (int32_t i = 0; i < m; ++i) y[i] *= s;
+}
+
+// Eigenvector of T for an eigenvalue lc isolated from the rest of the
+// spectrum, by the twisted factorization of T - lc I: top-down pivots
+// D+_i = (a_i - lc) - e_{i-1}^2 / D+_{i-1}, bottom-up pivots
+// D-_i = (a_i - lc) - e_i^2 / D-_{i+1} (tiny pivots become +-pert), the
+// twist k minimising |gamma_k| with gamma_k = D+_k + D-_k - (a_k - lc), and
+// then z_k = 1, z_i = -(e_i / D+_i) z_{i+1} above k and
+// z_i = -(e_{i-1} / D-_i) z_{i-1} below it: three serial sweeps where
+// inverse iteration needs seven.  z is normalised; false when it is not
+// finite (the caller then uses inverse iteration).  dp, dm: m doubles each.
+__device__ bool twisted_vector(int32_t m, const double* __restrict__ d, const double* __restrict__ e, double lc,
+                               double pert, double* __restrict__ dp, double* __restrict__ dm,
+                               double* __restrict__ z) {
+  auto guard = [pert](double x) { return fabs(x) < pert ? (x < 0.0 ? -pert : pert) : x; };
+  double p = guard(d[0] - lc);
+  dp[0] = p;
+  for (int32_t i = 0; i + 1 < m; ++i) {
+    const double ei = e[i];
+    p = guard(fma(-ei * ei, recip(p), d[i + 1] - lc));
+    dp[i + 1] = p;
+  }
+  double q = guard(d[m - 1] - lc);
+  dm[m - 1] = q;
+  for (int32_t i = m - 2; i >= 0; --i) {
+    const double ei = e[i];
+    q = guard(fma(-ei * ei, recip(q), d[i] - lc));
+    dm[i] = q;
+  }
+  int32_t k = 0;
+  double best = fabs(dp[0] + dm[0] - (d[0] - lc));
+  for (int32_t i = 1; i < m; ++i) {
+    const double g = fabs(dp[i] + dm[i] - (d[i] - lc));
+    if (g < best) {
+      best = g;
+      k = i;
+    }
+  }
+  double nn = 1.0, zz = 1.0;
+  z[k] = 1.0;
+  for (int32_t i = k - 1; i >= 0; --i) {
+    zz = -(e[i] * recip(dp[i])) * zz;
+    z[i] = zz;
+    nn = fma(zz, zz, nn);
+  }
+  zz = 1.0;
+  for (int32_t i = k + 1; i < m; ++i) {
+    zz = -(e[i - 1] * recip(dm[i])) * zz;
+    z[i] = zz;
+    nn = fma(zz, zz, nn);
+  }
+  if (!(nn > 0.0 && nn < 1e300)) return false;
+  const double inv = 1.0 / sqrt(nn);
+  for (int32_t i = 0; i < m; ++i) z[i] *= inv;
+  return true;
 }
 
 __device__ __forceinline__ int64_t refl_offset(int32_t m, int32_t klo, int32_t k) {
   // sum_{j=klo}^{k-1} (m - j - 1)
   const int64_t q = k - klo;
   return q * (m - 1 - klo) - (q * (q - 1)) / 2;
+}
+
+// Reflectors klo..khi (staged in refl, refl_offset layout) applied to the
+// columns of Y (one wave per column) for m <= 64 YR: the column lives in
+// registers, lane l holding y[l + 64 j]; the reflector entries are read
+// unconditionally at clamped positions and masked, and tau = 0 needs no
+// branch (the update then adds zero).  Per reflector the dependent chain is
+// the dot product's wave reduction and one FMA.
+template <int YR>
+__device__ void back_transform_chunk(int32_t m, int32_t r, int32_t klo, int32_t khi, const double* refl,
+                                     const double* __restrict__ tau, double* Y) {
+  const int t = threadIdx.x, l = t & 63;
+  for (int32_t c = t >> 6; c < r; c += kWaves) {
+    double* yc = Y + (int64_t)c * m;
+    double y[YR];
+#pragma unroll
+    for (int j = 0; j < YR; ++j) y[j] = (l + 64 * j < m) ? yc[l + 64 * j] : 0.0;
+    for (int32_t k = khi; k >= klo; --k) {
+      const double tk = tau[k];
+      const int64_t off = refl_offset(m, klo, k) - (k + 1);  // refl[off + a] = v_k[a], a > k
+      double v[YR];
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < YR; ++j) {
+        const int32_t a = l + 64 * j;
+        const bool in = a > k && a < m;
+        const double x = refl[off + (in ? a : k + 1)];
+        v[j] = in ? x : 0.0;
+        acc = fma(v[j], y[j], acc);
+      }
+      const double f = tk * wave_sum(acc);
+#pragma unroll
+      for (int j = 0; j < YR; ++j) y[j] = fma(-f, v[j], y[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < YR; ++j)
+      if (l + 64 * j < m) yc[l + 64 * j] = y[j];
+  }
 }
 
 // Eigenvectors of T for the r largest eigenvalues lam[0..r) (decreasing) by
@@ -900,8 +1003,8 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
   if (kLdsWork) {
     Y = lds + 2 * m;
     scr = Y + (int64_t)m * r;
-    refl = scr + (int64_t)6 * m * r;
-    refl_cap = kLdsDoubles - (2 * (int64_t)m + 7 * (int64_t)m * r);
+    refl = scr + (int64_t)(6 * m + 1) * r;
+    refl_cap = kLdsDoubles - (2 * (int64_t)m + (int64_t)(7 * m + 1) * r);
   } else {
     Y = ws;
     scr = ws + (int64_t)m * r;
@@ -924,13 +1027,18 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
   const double pert = fmax(u * tn, 1e-300);
   const double ortol = 1e-3 * tn;
 
-  // phase 1: every vector on its own thread
+  // phase 1: every vector on its own thread; an eigenvalue isolated from
+  // both neighbours in the whole spectrum (lam holds all m, decreasing)
+  // takes the twisted factorization, the others inverse iteration
   for (int32_t c = t; c < r; c += kTriThreads) {
-    double* base = scr + (int64_t)6 * m * c;
+    double* base = scr + (int64_t)(6 * m + 1) * c;  // odd stride: vectors on different LDS banks
+    const double lc = lam[c];
+    const bool iso = (c == 0 || lam[c - 1] - lc > ortol) && (c + 1 >= m || lc - lam[c + 1] > ortol);
+    if (iso && twisted_vector(m, dS, eS, lc, pert, base, base + m, Y + (int64_t)c * m)) continue;
     double *DL = base, *DD = base + m, *DU = base + 2 * m, *DU2 = base + 3 * m;
     int32_t* piv = (int32_t*)(base + 4 * m);
     double* y = base + 5 * m;
-    tri_factor(m, dS, eS, lam[c], pert, DL, DD, DU, DU2, piv);
+    tri_factor(m, dS, eS, lc, pert, DL, DD, DU, DU2, piv);
     // fixed, non-degenerate start vector (golden-ratio sequence in [0.5, 1.5))
     for (int32_t i = 0; i < m; ++i) {
       const double z = 0.6180339887498949 * (i + 1) + 0.7548776662466927 * (c + 1);
@@ -946,7 +1054,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
   // phase 2: clustered vectors, in order
   for (int32_t c = 1; c < r; ++c) {
     if (!(fabs(lam[c - 1] - lam[c]) <= ortol)) continue;
-    double* base = scr + (int64_t)6 * m * c;
+    double* base = scr + (int64_t)(6 * m + 1) * c;  // odd stride: vectors on different LDS banks
     double *DL = base, *DD = base + m, *DU = base + 2 * m, *DU2 = base + 3 * m;
     int32_t* piv = (int32_t*)(base + 4 * m);
     double* y = Y + (int64_t)c * m;
@@ -985,20 +1093,29 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
       for (int32_t i = t; i < L; i += kTriThreads) refl[off + i] = A[(int64_t)k * m + k + 1 + i];
     }
     __syncthreads();
-    for (int32_t k = khi; k >= klo; --k) {
-      const double tk = tau[k];
-      if (tk == 0.0) continue;
-      const double* vk = refl + refl_offset(m, klo, k);
-      const int32_t L = m - k - 1;
+    // one wave per column, all reflectors of the chunk without a barrier:
+    // lane l always handles the indices a = l (mod 64), so no value passes
+    // between lanes through memory
+    if (m <= 128)
+      back_transform_chunk<2>(m, r, klo, khi, refl, tau, Y);
+    else if (m <= 256)
+      back_transform_chunk<4>(m, r, klo, khi, refl, tau, Y);
+    else
       for (int32_t c = t >> 6; c < r; c += kWaves) {
-        double* yc = Y + (int64_t)c * m + (k + 1);
-        double acc = 0.0;
-        for (int32_t i = t & 63; i < L; i += 64) acc = fma(vk[i], yc[i], acc);
-        const double f = tk * wave_sum(acc);
-        for (int32_t i = t & 63; i < L; i += 64) yc[i] -= f * vk[i];
+        double* yc = Y + (int64_t)c * m;
+        for (int32_t k = khi; k >= klo; --k) {
+          const double tk = tau[k];
+          if (tk == 0.0) continue;
+          const int64_t off = refl_offset(m, klo, k) - (k + 1);  // refl[off + a] = v_k[a], a > k
+          double acc = 0.0;
+          for (int32_t a = t & 63; a < m; a += 64)
+            if (a > k) acc = fma(refl[off + a], yc[a], acc);
+          const double f = tk * wave_sum(acc);
+          for (int32_t a = t & 63; a < m; a += 64)
+            if (a > k) yc[a] -= f * refl[off + a];
+        }
       }
-      __syncthreads();
-    }
+    __syncthreads();
     khi = klo - 1;
   }
   for (int32_t i = t >> 6; i < m; i += kWaves)
@@ -1067,7 +1184,7 @@ hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* 
 hipError_t sym_eigvecs(hipStream_t st, int32_t m, int32_t r, const double* d, const double* e,
                        const double* lam, const double* A, const double* tau, double* ws, double* X) {
   if (m <= 0 || r <= 0) return hipSuccess;
-  const int64_t base_lds = 2 * (int64_t)m + 7 * (int64_t)m * r;
+  const int64_t base_lds = 2 * (int64_t)m + sym_eigvecs_ws(m, r);
   // all work in LDS when that leaves room for at least one reflector
   if (base_lds + m <= kLdsDoubles) {
     hipLaunchKernelGGL(k_tri_eigvecs<true>, dim3(1), dim3(kTriThreads), (size_t)kLdsDoubles * sizeof(double),

@@ -144,8 +144,10 @@ hipError_t gram_reduce(hipStream_t st, const double* part, int32_t S, int32_t m,
 hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* w,
                        double* ws);
 inline int64_t sym_eig_ws(int32_t m) { return 2 * (int64_t)m + 256; }
+inline int64_t sym_eigvecs_ws(int32_t m, int32_t r) { return (7 * (int64_t)m + 1) * r; }
 // Eigenvectors of A for its r largest eigenvalues lam[0..r) (from
-// sym_eigvals, decreasing): X (m x r, row-major).  ws: 7*m*r doubles.
+// sym_eigvals, decreasing): X (m x r, row-major).  ws: sym_eigvecs_ws(m, r)
+// doubles.
 hipError_t sym_eigvecs(hipStream_t st, int32_t m, int32_t r, const double* d, const double* e,
                        const double* lam, const double* A, const double* tau, double* ws, double* X);
 int32_t sym_eig_max();

@@ -464,7 +464,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         if (rR > 0) {
           CKS(ensure(W, (size_t)rows * rR * sizeof(double)));
           CKS(ensure(W2, (size_t)rows * rR * sizeof(double)));
-          CKS(ensure(eigws, (size_t)7 * m * rR * sizeof(double)));
+          CKS(ensure(eigws, (size_t)sym_eigvecs_ws((int32_t)m, (int32_t)rR) * sizeof(double)));
           double* Wp = as<double>(W);
           double* W2p = as<double>(W2);
           const View vW = row_major(rR);

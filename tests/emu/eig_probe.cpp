@@ -9,7 +9,7 @@
 
 extern "C" int hipemu_sym_eig(int m, const double* A_in, double* w, int r, double* X) {
   std::vector<double> A(A_in, A_in + (size_t)m * m);
-  std::vector<double> d(m), e(m), tau(m), ws((size_t)7 * m * (r > 0 ? r : 1));
+  std::vector<double> d(m), e(m), tau(m), ws((size_t)ttice::sym_eigvecs_ws(m, r > 0 ? r : 1));
   std::vector<double> ews(ttice::sym_eig_ws(m));
   if (ttice::sym_eigvals(nullptr, m, A.data(), d.data(), e.data(), tau.data(), w, ews.data()) != hipSuccess)
     return -1;
