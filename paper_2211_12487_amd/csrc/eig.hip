@@ -454,13 +454,14 @@ __global__ __launch_bounds__(512) void k_tridiag_reg(int32_t m, double* __restri
 //  * every wave reads all of column k, one entry per lane, and forms
 //    ||x[1:]||^2 with a wave sum (the same sum in every wave), beta, tau and
 //    v_j for the lane's columns;
-//  * v of the wave's own rows comes back from a wave-private LDS copy as
-//    broadcast 16-byte reads, so per-row work is never repeated in every
-//    lane; p = tau A v is formed as column sums of the wave's rows, one
-//    partial row per wave through LDS; one barrier;
+//  * v of the wave's own rows comes from the same column k as broadcast
+//    16-byte reads; p = tau A v is formed as column sums of the wave's
+//    rows, one partial row per wave through LDS; one barrier;
 //  * every wave adds the partials in the order w = 0, 1, ..., forms
-//    w = p - (tau/2)(p.v) v on its columns and, through the private copy,
-//    on its rows, and updates its registers.
+//    w = p - (tau/2)(p.v) v on its columns and, through a wave-private LDS
+//    copy, on its rows, and updates its registers.
+// A wave whose RPW rows are all finished (<= k) writes zero partials and
+// skips the product and the update, so the block's work shrinks with k.
 // Rows and columns use the same v, built from column k (a mixed row/column
 // v loses the similarity once rounding makes the block slightly
 // asymmetric).  Same outputs as k_tridiag (dsytd2 order; v_k in row ksw+k,
@@ -468,18 +469,18 @@ __global__ __launch_bounds__(512) void k_tridiag_reg(int32_t m, double* __restri
 constexpr int kRwWaves = 8;
 constexpr int kRwMax = 128;
 
-template <int CPL>
+template <int CPL, int RPW>
 __global__ __launch_bounds__(kRwWaves * 64) void k_tridiag_rw(int32_t n, int32_t ksw, int32_t lda,
                                                              double* __restrict__ A, double* __restrict__ d,
                                                              double* __restrict__ e, double* __restrict__ tau) {
   static_assert(CPL == 1 || CPL == 2, "one or two columns per lane");
+  static_assert(RPW % 2 == 0 && RPW * kRwWaves <= 64 * CPL, "rows per wave: even, within the columns");
   typedef double dbl2 __attribute__((ext_vector_type(2)));
   constexpr int NW = kRwWaves;
   constexpr int NC = 64 * CPL;  // largest n
-  constexpr int RPW = NC / NW;  // rows per wave (even)
   __shared__ __attribute__((aligned(16))) double xcol[2][NC];      // column k
   __shared__ __attribute__((aligned(16))) double part[2][NW][NC];  // per-wave partial column sums of A v
-  __shared__ __attribute__((aligned(16))) double vw[NW][2][NC];    // wave-private v and w
+  __shared__ __attribute__((aligned(16))) double wv[NW][NC];       // wave-private w
   const int l = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int32_t r0 = w * RPW;
@@ -497,7 +498,11 @@ __global__ __launch_bounds__(kRwWaves * 64) void k_tridiag_rw(int32_t n, int32_t
   for (int32_t k = 0; k + 2 < n; ++k) {
     const int buf = k & 1;
     const int kc = k >> 6, kl = k & 63;
-    if (l == kl) {  // this lane holds column k of the wave's rows
+    // a wave whose rows are all <= k (or past n) has nothing left to
+    // update; its row k, if it holds it, is still read once below
+    const bool has_k = r0 + RPW - 1 >= k && r0 < n;
+    const bool act = r0 + RPW - 1 > k && r0 < n;
+    if (has_k && l == kl) {  // this lane holds column k of the wave's rows
       dbl2* dst = (dbl2*)&xcol[buf][r0];
       if (kc == 0) {
 #pragma unroll
@@ -516,6 +521,18 @@ __global__ __launch_bounds__(kRwWaves * 64) void k_tridiag_rw(int32_t n, int32_t
       const int32_t j = l + 64 * c;
       xl[c] = xcol[buf][j];
       s = fma(xl[c], (j >= k + 2 && j < n) ? xl[c] : 0.0, s);
+    }
+    // column k on the wave's own rows (broadcast reads, issued with the
+    // above; scaled once beta is known)
+    double xq[RPW];
+    if (act) {
+      const dbl2* src = (const dbl2*)&xcol[buf][r0];
+#pragma unroll
+      for (int u = 0; u < RPW / 2; ++u) {
+        const dbl2 t = src[u];
+        xq[2 * u] = t[0];
+        xq[2 * u + 1] = t[1];
+      }
     }
     const double sigma = wave_sum(s);
     const double alpha = xcol[buf][k + 1];
@@ -543,22 +560,22 @@ __global__ __launch_bounds__(kRwWaves * 64) void k_tridiag_rw(int32_t n, int32_t
     }
     double vq[RPW];
     if (tk != 0.0) {  // uniform over the block
+      if (act) {
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) vw[w][0][l + 64 * c] = vc[c];
-      __builtin_amdgcn_wave_barrier();
-      const dbl2* src = (const dbl2*)&vw[w][0][r0];
+        for (int q = 0; q < RPW; ++q) {
+          const int32_t i = r0 + q;
+          vq[q] = (i == k + 1) ? 1.0 : ((i > k + 1 && i < n) ? xq[q] * scale : 0.0);
+        }
 #pragma unroll
-      for (int u = 0; u < RPW / 2; ++u) {
-        const dbl2 t = src[u];
-        vq[2 * u] = t[0];
-        vq[2 * u + 1] = t[1];
-      }
+        for (int c = 0; c < CPL; ++c) {
+          double p4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        double p4[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int q = 0; q < RPW; ++q) p4[q & 3] = fma(a[q][c], vq[q], p4[q & 3]);
+          part[buf][w][l + 64 * c] = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+        }
+      } else {
 #pragma unroll
-        for (int q = 0; q < RPW; ++q) p4[q & 3] = fma(a[q][c], vq[q], p4[q & 3]);
-        part[buf][w][l + 64 * c] = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+        for (int c = 0; c < CPL; ++c) part[buf][w][l + 64 * c] = 0.0;
       }
     }
     __syncthreads();
@@ -576,22 +593,26 @@ __global__ __launch_bounds__(kRwWaves * 64) void k_tridiag_rw(int32_t n, int32_t
         pv = fma(pc[c], vc[c], pv);
       }
       pv = wave_sum(pv);
-      const double gam = 0.5 * tk * pv;
-      double wc[CPL];
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        wc[c] = pc[c] - gam * vc[c];
-        vw[w][1][l + 64 * c] = wc[c];
-      }
-      __builtin_amdgcn_wave_barrier();
-      const dbl2* src = (const dbl2*)&vw[w][1][r0];
-#pragma unroll
-      for (int u = 0; u < RPW / 2; ++u) {
-        const dbl2 t = src[u];
+      if (act) {
+        const double gam = 0.5 * tk * pv;
+        double wc[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-          a[2 * u][c] = a[2 * u][c] - vq[2 * u] * wc[c] - t[0] * vc[c];
-          a[2 * u + 1][c] = a[2 * u + 1][c] - vq[2 * u + 1] * wc[c] - t[1] * vc[c];
+          wc[c] = pc[c] - gam * vc[c];
+          wv[w][l + 64 * c] = wc[c];
+        }
+        // the wave's own rows of w come back from its private copy (LDS
+        // operations of one wave complete in order)
+        __builtin_amdgcn_wave_barrier();
+        const dbl2* src = (const dbl2*)&wv[w][r0];
+#pragma unroll
+        for (int u = 0; u < RPW / 2; ++u) {
+          const dbl2 t = src[u];
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) {
+            a[2 * u][c] = a[2 * u][c] - vq[2 * u] * wc[c] - t[0] * vc[c];
+            a[2 * u + 1][c] = a[2 * u + 1][c] - vq[2 * u + 1] * wc[c] - t[1] * vc[c];
+          }
         }
       }
     }
@@ -1152,9 +1173,11 @@ hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* 
     hipLaunchKernelGGL((k_tridiag_reg<2, 16>), dim3(1), dim3(reg_threads(2)), 0, st, m, A, d, e, tau);
   } else if (m <= kRwMax) {
     if (m <= 64)
-      hipLaunchKernelGGL(k_tridiag_rw<1>, dim3(1), dim3(kRwWaves * 64), 0, st, m, 0, m, A, d, e, tau);
+      hipLaunchKernelGGL((k_tridiag_rw<1, 8>), dim3(1), dim3(kRwWaves * 64), 0, st, m, 0, m, A, d, e, tau);
+    else if (m <= 96)
+      hipLaunchKernelGGL((k_tridiag_rw<2, 12>), dim3(1), dim3(kRwWaves * 64), 0, st, m, 0, m, A, d, e, tau);
     else
-      hipLaunchKernelGGL(k_tridiag_rw<2>, dim3(1), dim3(kRwWaves * 64), 0, st, m, 0, m, A, d, e, tau);
+      hipLaunchKernelGGL((k_tridiag_rw<2, 16>), dim3(1), dim3(kRwWaves * 64), 0, st, m, 0, m, A, d, e, tau);
   } else if (ws != nullptr) {
     // reflections whose trailing block is wider than kRwMax on many
     // workgroups, the rest in registers
@@ -1170,7 +1193,7 @@ hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* 
       hipLaunchKernelGGL(k_tri_up, dim3(G), dim3(kMvThreads), (size_t)2 * L * sizeof(double), st, m, k, A, tau,
                          vbuf, pbuf, part, G);
     }
-    hipLaunchKernelGGL(k_tridiag_rw<2>, dim3(1), dim3(kRwWaves * 64), 0, st, kRwMax, ksw, m, A, d, e, tau);
+    hipLaunchKernelGGL((k_tridiag_rw<2, 16>), dim3(1), dim3(kRwWaves * 64), 0, st, kRwMax, ksw, m, A, d, e, tau);
   } else {
     hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kTriThreads), tridiag_lds_bytes(m), st, m, A, d, e, tau);
   }

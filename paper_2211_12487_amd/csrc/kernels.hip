@@ -594,29 +594,37 @@ hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk,
   if (N <= 0) return hipSuccess;
   const int32_t gx = (N + 63) / 64, gy = gemm_row_blocks(M);
   const int64_t tiles = (int64_t)gx * gy;
-  if ((kchunk <= 0 || kchunk >= K) && ws.p && ws.cnt && !bnorm && M > 0 && K >= 64 && tiles <= ws.ncnt &&
-      tiles < 96) {
-    // few output tiles and a long K: split K over grid z; the last block of
-    // each tile adds the partials in order
-    const int64_t MN = (int64_t)M * N;
-    // sub-blocks of 16 x 16 per tile: the largest count, that of the first
-    const int64_t nsb = ((std::min<int64_t>(M, 64) + 15) / 16) * ((std::min<int64_t>(N, 64) + 15) / 16);
-    if (nsb <= 4 && va.cpf == kUnframed && vb.rpf == kUnframed) {
-      // small output, operands linear along K: matrix-core kernel, one load
-      // batch (128 values of k) per slice unless that needs more than
-      // kMfmaMaxSplit slices
+  const bool whole_k = kchunk <= 0 || kchunk >= K;
+  const bool can_split = whole_k && ws.p && ws.cnt && !bnorm && M > 0 && K >= 64 && tiles <= ws.ncnt && tiles < 96;
+  // sub-blocks of 16 x 16 per tile: the largest count, that of the first
+  const int64_t nsb = ((std::min<int64_t>(M, 64) + 15) / 16) * ((std::min<int64_t>(N, 64) + 15) / 16);
+  const int64_t MN = (int64_t)M * N;
+  if (whole_k && !bnorm && M > 0 && nsb <= 4 && va.cpf == kUnframed && vb.rpf == kUnframed &&
+      (can_split || K >= 4 * kMfmaBatch)) {
+    // small output tiles, operands linear along K, and either a K split or
+    // at least one full load batch (a short K wastes most of the batch; the
+    // LDS-tiled kernel is faster there): matrix-core kernel.  With few tiles
+    // and a long K the K range is split, one load batch (128 values of k)
+    // per slice unless that needs more than kMfmaMaxSplit slices; the last
+    // block of each tile adds the partials in order.
+    int64_t S = 1;
+    if (can_split) {
       const int64_t batch = 4 * kMfmaBatch;
-      int64_t S = std::min<int64_t>({(K + batch - 1) / batch, std::max<int64_t>(1, 1024 / tiles), (int64_t)kMfmaMaxSplit});
+      S = std::min<int64_t>({(K + batch - 1) / batch, std::max<int64_t>(1, 1024 / tiles), (int64_t)kMfmaMaxSplit});
       S = std::max<int64_t>(1, std::min<int64_t>(S, ws.len / std::max<int64_t>(MN, 1)));
-      int64_t chunk = (K + S - 1) / S;
-      chunk = ((chunk + 15) / 16) * 16;
-      S = (K + chunk - 1) / chunk;
-      hipLaunchKernelGGL((k_gemm_mfma<TB, TE, TD>), dim3(gx, gy, (unsigned)S), dim3(256), 0, st, M, N, K,
-                         (int32_t)chunk, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart, ws.p, ws.cnt);
-      return hipGetLastError();
     }
-    // otherwise the LDS-tiled kernel: at least two K tiles of 16 per
-    // split, at most 16 splits, about 192 blocks in all
+    int64_t chunk = (K + S - 1) / S;
+    chunk = ((chunk + 15) / 16) * 16;
+    S = (K + chunk - 1) / chunk;
+    hipLaunchKernelGGL((k_gemm_mfma<TB, TE, TD>), dim3(gx, gy, (unsigned)S), dim3(256), 0, st, M, N, K,
+                       (int32_t)chunk, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart, ws.p, ws.cnt);
+    return hipGetLastError();
+  }
+  if (can_split) {
+    // few output tiles and a long K on the LDS-tiled kernel: K split over
+    // grid z (at least two K tiles of 16 per split, at most 16 splits, about
+    // 192 blocks in all); the last block of each tile adds the partials in
+    // order
     int64_t S = std::min<int64_t>({(K + 31) / 32, std::max<int64_t>(2, 192 / tiles), (int64_t)16});
     S = std::min<int64_t>(S, ws.len / std::max<int64_t>(MN, 1));
     if (S >= 2) {

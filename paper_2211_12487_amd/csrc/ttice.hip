@@ -434,7 +434,8 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         const int64_t K = left ? Ncol : rows;
         const View vR = vr;                   // rows x Ncol
         const View vRt = transposed(vr);      // Ncol x rows
-        const int32_t kchunk = gram_kchunk((int32_t)m, K);
+        // (m <= 32: one slice, on the matrix-core product kernel)
+        const int32_t kchunk = m <= 32 ? (int32_t)K : gram_kchunk((int32_t)m, K);
         const int64_t Sg = (K + kchunk - 1) / kchunk;
         CKS(ensure(gpart, (size_t)Sg * m * m * sizeof(double)));
         CKS(ensure(gram, (size_t)m * m * sizeof(double)));
@@ -449,7 +450,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         CK((gemm<double, double, double>(st, (int32_t)m, (int32_t)m, (int32_t)K, kchunk, 1.0, as<double>(rbuf),
                                          left ? vR : vRt, as<double>(rbuf), left ? vRt : vR, 0.0,
                                          (const double*)nullptr, View(), as<double>(gpart), row_major(m),
-                                         m * m, nullptr, nullptr)));
+                                         m * m, nullptr, nullptr, gws())));
         CK(gram_reduce(st, as<double>(gpart), (int32_t)Sg, (int32_t)m, as<double>(gram)));
         if (m > sym_eig_max()) return TTICE_EINVAL;  // documented size limit of the residual's SVD
         CK(sym_eigvals(st, (int32_t)m, as<double>(gram), dd, ee, tauv, wv, dd + 4 * m));
