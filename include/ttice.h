@@ -183,6 +183,34 @@ int ttice_ranks(const ttice_state* st, int64_t* ranks, int64_t* n_total);
  * EDEVICE. */
 int ttice_get_core(ttice_state* st, int32_t i, double* out, int64_t* rows, int64_t* cols);
 
+/* Checkpoint / resume.  The cores are the compressed store of the stream
+ * (the paper's storage argument, Sec. 6): a state is fully described by its
+ * options (precision, algorithm, skip rule, tau), eps, dims, ranks, cores
+ * and last core, and ttice_save writes exactly these into a host byte image
+ * (header, cores packed row-major, last core transposed as for
+ * ttice_get_core, and a 64-bit FNV-1a hash of the preceding bytes; host
+ * byte order).  Updating a loaded state gives the same cores, bit for bit,
+ * as updating the state that was saved.
+ *
+ * ttice_save: buf is a host buffer of cap bytes; *size (host) receives the
+ * image size.  With buf == NULL only the size is returned (OK).  The state
+ * is not changed.  Errors: ESTATE (st NULL), EINVAL (size NULL, or cap below
+ * the image size: *size still receives it), EDEVICE. */
+int ttice_save(ttice_state* st, void* buf, int64_t cap, int64_t* size);
+
+/* ttice_load: a new state on the current device from an image of exactly
+ * `size` bytes written by ttice_save; *out receives it (NULL on error).
+ * The stream option starts at the default stream, profiling off.  Errors:
+ * EINVAL (NULL arguments, wrong magic or size, hash mismatch, a shape no
+ * state can have: r_0 != 1, r_i > r_{i-1} n_i, options out of range),
+ * ENOMEM, EDEVICE.  The caller owns the state (ttice_destroy). */
+int ttice_load(const void* buf, int64_t size, ttice_state** out);
+
+/* Shape of a state (for one built by ttice_load): *d (host, may be NULL),
+ * dims (host array of TTICE_MAX_D entries, may be NULL: n_1..n_d written),
+ * *eps (host, may be NULL).  Errors: ESTATE. */
+int ttice_shape(const ttice_state* st, int32_t* d, int64_t* dims, double* eps);
+
 /* Release the state and all device memory it owns.  NULL is a no-op. */
 void ttice_destroy(ttice_state* st);
 

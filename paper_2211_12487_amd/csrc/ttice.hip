@@ -978,6 +978,173 @@ int ttice_get_core(ttice_state* st, int32_t i, double* out, int64_t* rows, int64
   return status_of(e);
 }
 
+// ---- Checkpoint image (the cores are the compressed store: a state is its
+// options, ranks, cores and last core).  Layout, host byte order:
+//   magic (8 bytes), d, prec, algo, skip_rule (int32 each), eps, tau
+//   (double), n_total (int64), dims[d], ranks r_0..r_d (int64 each), the d
+//   cores U_i packed row-major ((r_{i-1} n_i) x r_i doubles), the last core
+//   transposed (n_total x r_d doubles), and the FNV-1a hash (uint64) of all
+//   bytes before it.
+}  // extern "C"
+namespace {
+constexpr char kImageMagic[8] = {'T', 'T', 'I', 'C', 'E', 'i', 'm', '1'};
+
+uint64_t fnv1a(const unsigned char* p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+size_t image_header_bytes(int32_t d) { return 8 + 4 * 4 + 2 * 8 + 8 + 8 * (size_t)d + 8 * (size_t)(d + 1); }
+
+// bytes of the whole image for dims/ranks, or 0 when it would overflow
+size_t image_bytes(int32_t d, const int64_t* dims, const int64_t* rk, int64_t n_total) {
+  double total = (double)image_header_bytes(d) + 8.0;
+  for (int i = 0; i < d; ++i) total += 8.0 * (double)rk[i] * (double)dims[i] * (double)rk[i + 1];
+  total += 8.0 * (double)n_total * (double)rk[d];
+  if (total > 9.0e15) return 0;
+  return (size_t)total;
+}
+}  // namespace
+extern "C" {
+
+int ttice_save(ttice_state* st, void* buf, int64_t cap, int64_t* size) {
+  if (!st) return TTICE_ESTATE;
+  if (!size) return TTICE_EINVAL;
+  const int32_t d = st->d;
+  const size_t need = image_bytes(d, st->dims, st->rk, st->n_total);
+  if (need == 0) return TTICE_EINVAL;
+  *size = (int64_t)need;
+  if (!buf) return TTICE_OK;
+  if (cap < (int64_t)need) return TTICE_EINVAL;
+  if (hipSetDevice(st->device) != hipSuccess) return TTICE_EDEVICE;
+  unsigned char* b = (unsigned char*)buf;
+  size_t o = 0;
+  auto put = [&](const void* v, size_t n) {
+    memcpy(b + o, v, n);
+    o += n;
+  };
+  put(kImageMagic, 8);
+  put(&st->d, 4);
+  put(&st->prec, 4);
+  put(&st->algo, 4);
+  put(&st->skip_rule, 4);
+  put(&st->eps, 8);
+  put(&st->tau, 8);
+  put(&st->n_total, 8);
+  put(st->dims, 8 * (size_t)d);
+  put(st->rk, 8 * (size_t)(d + 1));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < d && e == hipSuccess; ++i) {
+    const int64_t rows = st->rk[i] * st->dims[i], cols = st->rk[i + 1];
+    if (rows > 0 && cols > 0)
+      e = hipMemcpy2DAsync(b + o, cols * sizeof(double), st->U[i].p, st->U[i].ld * sizeof(double),
+                           cols * sizeof(double), rows, hipMemcpyDeviceToHost, st->stream);
+    o += (size_t)rows * cols * sizeof(double);
+  }
+  const int64_t rd = st->rk[d];
+  if (e == hipSuccess && st->n_total > 0 && rd > 0)
+    e = hipMemcpy2DAsync(b + o, rd * sizeof(double), st->Gt.p, st->Gt.ld * sizeof(double), rd * sizeof(double),
+                         st->n_total, hipMemcpyDeviceToHost, st->stream);
+  o += (size_t)st->n_total * rd * sizeof(double);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return status_of(e);
+  }
+  const uint64_t h = fnv1a(b, o);
+  put(&h, 8);
+  return o == need ? TTICE_OK : TTICE_EDEVICE;
+}
+
+int ttice_load(const void* buf, int64_t size, ttice_state** out) {
+  if (!out) return TTICE_EINVAL;
+  *out = nullptr;
+  if (!buf || size < (int64_t)image_header_bytes(1) + 8) return TTICE_EINVAL;
+  const unsigned char* b = (const unsigned char*)buf;
+  if (memcmp(b, kImageMagic, 8) != 0) return TTICE_EINVAL;
+  int32_t d, prec, algo, skip;
+  double eps, tau;
+  int64_t n_total;
+  memcpy(&d, b + 8, 4);
+  memcpy(&prec, b + 12, 4);
+  memcpy(&algo, b + 16, 4);
+  memcpy(&skip, b + 20, 4);
+  memcpy(&eps, b + 24, 8);
+  memcpy(&tau, b + 32, 8);
+  memcpy(&n_total, b + 40, 8);
+  if (d < 1 || d > TTICE_MAX_D || size < (int64_t)image_header_bytes(d) + 8) return TTICE_EINVAL;
+  int64_t dims[TTICE_MAX_D], rk[TTICE_MAX_D + 1];
+  memcpy(dims, b + 48, 8 * (size_t)d);
+  memcpy(rk, b + 48 + 8 * (size_t)d, 8 * (size_t)(d + 1));
+  // the shape rules every state satisfies: r_0 = 1 and orthonormal columns
+  // (r_i <= r_{i-1} n_i), frames >= 0, options in range
+  if (n_total < 0 || rk[0] != 1) return TTICE_EINVAL;
+  for (int i = 0; i < d; ++i) {
+    if (dims[i] < 1 || dims[i] >= ((int64_t)1 << 31)) return TTICE_EINVAL;
+    if (rk[i + 1] < 0 || rk[i + 1] > rk[i] * dims[i]) return TTICE_EINVAL;
+  }
+  if (prec != TTICE_PREC_FP64 && prec != TTICE_PREC_FP32 && prec != TTICE_PREC_BF16X3) return TTICE_EINVAL;
+  if (algo != TTICE_ALG_PLAIN && algo != TTICE_ALG_STAR) return TTICE_EINVAL;
+  if (skip != TTICE_SKIP_MEAN && skip != TTICE_SKIP_BATCH) return TTICE_EINVAL;
+  if (!(tau > 0.0 && tau < 1e300)) return TTICE_EINVAL;
+  const size_t need = image_bytes(d, dims, rk, n_total);
+  if (need == 0 || (int64_t)need != size) return TTICE_EINVAL;
+  uint64_t h;
+  memcpy(&h, b + need - 8, 8);
+  if (h != fnv1a(b, need - 8)) return TTICE_EINVAL;
+
+  ttice_state* s = nullptr;
+  int rc = ttice_create(d, dims, eps, &s);  // checks eps and the dims' product
+  if (rc != TTICE_OK) return rc;
+  s->prec = prec;
+  s->algo = algo;
+  s->skip_rule = skip;
+  s->tau = tau;
+  size_t o = image_header_bytes(d);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < d && rc == TTICE_OK; ++i) {
+    const int64_t rows = rk[i] * dims[i], cols = rk[i + 1];
+    rc = s->grow_core(s->U[i], std::max<int64_t>(rows, 1), std::max<int64_t>(cols, 1), 0, 0);
+    if (rc == TTICE_OK && rows > 0 && cols > 0) {
+      e = hipMemcpy2DAsync(s->U[i].p, s->U[i].ld * sizeof(double), b + o, cols * sizeof(double),
+                           cols * sizeof(double), rows, hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) rc = status_of(e);
+    }
+    o += (size_t)rows * cols * sizeof(double);
+  }
+  const int64_t rd = rk[d];
+  if (rc == TTICE_OK) rc = s->grow_core(s->Gt, std::max<int64_t>(n_total, 1), std::max<int64_t>(rd, 1), 0, 0);
+  if (rc == TTICE_OK && n_total > 0 && rd > 0) {
+    e = hipMemcpy2DAsync(s->Gt.p, s->Gt.ld * sizeof(double), b + o, rd * sizeof(double), rd * sizeof(double),
+                         n_total, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) rc = status_of(e);
+  }
+  if (rc != TTICE_OK) {
+    (void)hipGetLastError();
+    ttice_destroy(s);
+    return rc;
+  }
+  for (int i = 0; i <= d; ++i) s->rk[i] = rk[i];
+  s->n_total = n_total;
+  *out = s;
+  return TTICE_OK;
+}
+
+int ttice_shape(const ttice_state* st, int32_t* d, int64_t* dims, double* eps) {
+  if (!st) return TTICE_ESTATE;
+  if (d) *d = st->d;
+  if (dims)
+    for (int i = 0; i < st->d; ++i) dims[i] = st->dims[i];
+  if (eps) *eps = st->eps;
+  return TTICE_OK;
+}
+
 void ttice_destroy(ttice_state* st) {
   if (!st) return;
   (void)hipSetDevice(st->device);

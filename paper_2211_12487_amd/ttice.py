@@ -36,6 +36,9 @@ EXPORTS = [
     "ttice_ranks",
     "ttice_get_core",
     "ttice_get_kernel_stats",
+    "ttice_save",
+    "ttice_load",
+    "ttice_shape",
     "ttice_destroy",
     "ttice_strerror",
     "ttice_server_create",
@@ -115,6 +118,9 @@ def lib():
     L.ttice_ranks.argtypes = [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
     L.ttice_get_core.argtypes = [c_vp, c_i32, c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
     L.ttice_get_kernel_stats.argtypes = [c_vp, c_i32, ctypes.POINTER(KernelStats)]
+    L.ttice_save.argtypes = [c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]
+    L.ttice_load.argtypes = [c_vp, c_i64, ctypes.POINTER(c_vp)]
+    L.ttice_shape.argtypes = [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl)]
     L.ttice_destroy.argtypes = [c_vp]
     L.ttice_destroy.restype = None
     L.ttice_strerror.argtypes = [ctypes.c_int]
@@ -133,6 +139,7 @@ def lib():
     L.ttice_server_destroy.restype = None
     for name in ("ttice_create", "ttice_set_option", "ttice_update", "ttice_reconstruct",
                  "ttice_project", "ttice_reserve", "ttice_ranks", "ttice_get_core", "ttice_get_kernel_stats",
+                 "ttice_save", "ttice_load", "ttice_shape",
                  "ttice_server_create", "ttice_server_add_stream", "ttice_server_submit", "ttice_server_poll",
                  "ttice_server_wait", "ttice_server_stream_state", "ttice_server_remove_stream",
                  "ttice_server_stats"):
@@ -260,6 +267,34 @@ class TTICE:
         if out.numel():
             _check(lib().ttice_get_core(self._h, i, ctypes.c_void_p(out.data_ptr()), None, None), "ttice_get_core")
         return out
+
+    def save(self) -> bytes:
+        """Checkpoint image of the state (ttice_save)."""
+        n = ctypes.c_int64()
+        _check(lib().ttice_save(self._h, None, 0, ctypes.byref(n)), "ttice_save")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().ttice_save(self._h, buf, n.value, ctypes.byref(n)), "ttice_save")
+        return buf.raw
+
+    @classmethod
+    def load(cls, image: bytes, stream: Optional[torch.cuda.Stream] = None) -> "TTICE":
+        """A new state on the current device from a checkpoint image (ttice_load)."""
+        L = lib()
+        h = ctypes.c_void_p()
+        _check(L.ttice_load(image, len(image), ctypes.byref(h)), "ttice_load")
+        d = ctypes.c_int32()
+        dims = (ctypes.c_int64 * TTICE_MAX_D)()
+        eps = ctypes.c_double()
+        _check(L.ttice_shape(h, ctypes.byref(d), dims, ctypes.byref(eps)), "ttice_shape")
+        self = cls.__new__(cls)
+        self.dims = tuple(int(dims[i]) for i in range(d.value))
+        self.d = d.value
+        self.eps = float(eps.value)
+        self._h = h
+        self.stream = stream
+        if stream is not None:
+            self.set_option(OPT_STREAM, ctypes.c_void_p(stream.cuda_stream))
+        return self
 
     def reserve(self, max_batch: int) -> None:
         """Allocate the workspace of increments up to max_batch tensors now."""

@@ -173,6 +173,60 @@ def case_lowrank():
         assert g.ranks()[0][1:-1] == [2, 3, min(k, 5)], (k, g.ranks())
 
 
+def case_checkpoint():
+    """Checkpoint / resume: a stream saved after some increments, loaded into
+    a new state and continued gives the same ranks, cores and last core, bit
+    for bit, as the stream run without interruption (Algorithm 1 and 2, non-
+    default options); the image carries the options; corrupted, truncated,
+    resized or impossible images are refused with EINVAL."""
+    import ctypes
+    from emu_ttice import EmuError
+    for algo, dims, eps in ((0, (12, 10, 6), 0.05), (1, (9, 7, 11, 3), 0.03)):
+        batches = list(synth.smooth_separable_stream(14, dims, 3, 1e-3, 2, 40 + algo, dtype=np.float32))
+        full = EmuTTICE(L, dims, eps, algo=algo, prec=0, tau=0.8 if algo else None, skip_rule=1 if algo else None)
+        for Y in batches:
+            full.update(Y)
+        for cut in (0, 1, 4):
+            a = EmuTTICE(L, dims, eps, algo=algo, prec=0, tau=0.8 if algo else None,
+                         skip_rule=1 if algo else None)
+            for Y in batches[:cut]:
+                a.update(Y)
+            img = a.save()
+            assert img == a.save()  # saving does not change the state
+            b = EmuTTICE.load(L, img)
+            assert b.dims == tuple(dims) and b.eps == eps
+            assert b.ranks() == a.ranks()
+            a.close()
+            for Y in batches[cut:]:
+                b.update(Y)
+            assert b.ranks() == full.ranks(), (algo, cut)
+            for i in range(len(dims) + 1):
+                assert np.array_equal(b.core(i), full.core(i)), (algo, cut, i)
+            assert b.save() == full.save()
+            b.close()
+        img = full.save()
+        bad = bytearray(img)
+        bad[len(img) // 2] ^= 1
+        for broken in (bytes(bad), img[:-1], img + b"\0", b"XXXXXXXX" + img[8:], b""):
+            h = ctypes.c_void_p()
+            assert L.ttice_load(broken, len(broken), ctypes.byref(h)) == -1 and not h.value
+        # a rank larger than r_{i-1} n_i, with a matching hash, is still refused
+        d = len(dims)
+        off = 48 + 8 * d + 8
+        forged = bytearray(img[:-8])
+        forged[off:off + 8] = (dims[0] + 1).to_bytes(8, "little", signed=True)
+        h = 1469598103934665603
+        for byte in forged:
+            h = ((h ^ byte) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+        forged = bytes(forged) + h.to_bytes(8, "little")
+        hh = ctypes.c_void_p()
+        assert L.ttice_load(forged, len(forged), ctypes.byref(hh)) == -1
+        n = ctypes.c_int64()
+        small = ctypes.create_string_buffer(16)
+        assert L.ttice_save(full.h, small, 16, ctypes.byref(n)) == -1 and n.value == len(img)
+        full.close()
+
+
 def case_eigensolver():
     """The library's eigensolver kernels (tridiagonalisation, bisection,
     inverse iteration) against LAPACK on random, clustered and

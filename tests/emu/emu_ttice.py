@@ -46,6 +46,9 @@ def load(path):
     L.ttice_project.argtypes = [vp, vp, i64, i32, vp, vp, vp]
     L.ttice_ranks.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.ttice_get_core.argtypes = [vp, i32, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.ttice_save.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
+    L.ttice_load.argtypes = [vp, i64, ctypes.POINTER(vp)]
+    L.ttice_shape.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     L.ttice_destroy.argtypes = [vp]
     L.ttice_destroy.restype = None
     L.hipemu_fail_alloc_after.argtypes = [ctypes.c_longlong]
@@ -89,6 +92,34 @@ class EmuTTICE:
             self._opt(4, ctypes.c_double(tau))
         if skip_rule is not None:
             self._opt(3, ctypes.c_int32(skip_rule))
+
+    def save(self):
+        n = ctypes.c_int64()
+        rc = self.L.ttice_save(self.h, None, 0, ctypes.byref(n))
+        if rc:
+            raise EmuError(rc)
+        buf = ctypes.create_string_buffer(n.value)
+        rc = self.L.ttice_save(self.h, buf, n.value, ctypes.byref(n))
+        if rc:
+            raise EmuError(rc)
+        return buf.raw
+
+    @classmethod
+    def load(cls, L, image):
+        h = ctypes.c_void_p()
+        rc = L.ttice_load(image, len(image), ctypes.byref(h))
+        if rc:
+            raise EmuError(rc)
+        d = ctypes.c_int32()
+        dims = (ctypes.c_int64 * TTICE_MAX_D)()
+        eps = ctypes.c_double()
+        L.ttice_shape(h, ctypes.byref(d), dims, ctypes.byref(eps))
+        self = cls.__new__(cls)
+        self.L, self.h = L, h
+        self.dims = tuple(dims[i] for i in range(d.value))
+        self.d = d.value
+        self.eps = eps.value
+        return self
 
     def _opt(self, k, v):
         rc = self.L.ttice_set_option(self.h, k, ctypes.byref(v))
