@@ -39,9 +39,10 @@ def parse():
                     help="increments of the stream the CPU oracle baseline compresses")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-arm", action="store_true")
-    ap.add_argument("--workload", default="video240", choices=["video240", "serving"],
+    ap.add_argument("--workload", default="video240", choices=["video240", "serving", "ablation"],
                     help="video240: the headline stream (default); serving: the many-stream mix, reported "
                          "as arrival-to-completion latency")
+    ap.add_argument("--eps", type=float, default=0.1, help="ablation: eps_des")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: length of the arrival trace")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrivals per second")
     ap.add_argument("--streams", type=int, default=256, help="serving: number of streams")
@@ -256,6 +257,78 @@ def serving(a):
         offered_tensors_per_s=float(sizes.sum()) / a.seconds)
 
 
+# Algorithm 2 ablation on ATARI-shaped synthetic runs: 210x160x3 frames
+# (background, moving sprites, noise) reshaped to 30x28x40x3 as in the
+# experiments, streamed run by run (one run = one increment)
+ABLATION = dict(name="atari-shaped", frame=(210, 160, 3), dims=(30, 28, 40, 3), runs=24, run_len=(64, 160),
+                seed=5)
+VARIANTS = [("TT-ICE", dict(algo="plain")),
+            ("Subselect", dict(algo="star", skip_rule="none", tau=2.0)),
+            ("SS", dict(algo="star", skip_rule="mean", tau=2.0)),
+            ("TT-ICE*", dict(algo="star", skip_rule="mean", tau=0.8))]
+
+
+def ablation(a):
+    """Every Algorithm 2 variant of the experiments on the same runs: wall
+    time, tensors/s, tensors used in core updates, skipped increments, final
+    ranks, compression ratio (eq:compressionratio) and mean relative
+    reconstruction error over the stored tensors (eq:MRRE)."""
+    import torch
+    from paper_2211_12487_amd import synth
+    from paper_2211_12487_amd.ttice import TTICE
+    w = ABLATION
+    rng = np.random.default_rng(w["seed"])
+    lens = rng.integers(w["run_len"][0], w["run_len"][1] + 1, w["runs"])
+    total = int(lens.sum())
+    h, wd, c = w["frame"]
+    print(f"generating {total} frames {w['frame']}", file=sys.stderr, flush=True)
+    Y = np.concatenate(list(synth.video_stream(total, 256, height=h, width=wd, channels=c, seed=w["seed"])))
+    dims = w["dims"]
+    Yd = torch.from_numpy(Y.reshape((total,) + dims)).cuda()
+    starts = np.concatenate([[0], np.cumsum(lens)])
+    warm = TTICE(dims, a.eps)  # first-use allocations and module load, not timed
+    warm.update(Yd[: starts[1]])
+    warm.close()
+    results = {}
+    for name, kw in VARIANTS:
+        print(f"ablation {name}", file=sys.stderr, flush=True)
+        g = TTICE(dims, a.eps, prec="fp64", **kw)
+        used = skipped = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(w["runs"]):
+            info = g.update(Yd[starts[k]:starts[k + 1]])
+            used += info["used"]
+            skipped += int(info["skipped"])
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        ranks = g.ranks()
+        rre = []
+        for k in range(w["runs"]):
+            rec = g.reconstruct(int(starts[k]), int(lens[k]))
+            ref = Yd[starts[k]:starts[k + 1]].double()
+            num = (rec - ref).flatten(1).norm(dim=1)
+            den = ref.flatten(1).norm(dim=1)
+            rre.append((num / den).cpu().numpy())
+        d = len(dims)
+        stored = sum(ranks[i] * dims[i] * ranks[i + 1] for i in range(d)) + ranks[d] * total
+        results[name] = dict(seconds=secs, tensors_per_s=total / secs, tensors_used=int(used),
+                             skipped_increments=skipped, ranks=ranks,
+                             compression_ratio=total * math.prod(dims) / stored,
+                             mean_rre=float(np.concatenate(rre).mean()))
+        g.close()
+    star = results["TT-ICE*"]
+    return dict(
+        metric="TT-ICE* tensors/s on ATARI-shaped runs (all Algorithm 2 variants reported)",
+        value=star["tensors_per_s"], unit="tensors/s", n_gpus=1, steps=1, warmup=1,
+        ms_per_step=star["seconds"] * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload=f"{w['name']}: {w['runs']} runs of {w['run_len'][0]}-{w['run_len'][1]} frames "
+                             f"{h}x{wd}x{c} as {dims}, fp32 input, eps={a.eps}, one run per increment",
+                    frames=total, eps=a.eps),
+        variants=results)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -267,6 +340,9 @@ def main():
     ttice.lib()
     if a.workload == "serving":
         print(json.dumps(serving(a)), flush=True)
+        return
+    if a.workload == "ablation":
+        print(json.dumps(ablation(a)), flush=True)
         return
     w = WORKLOAD
     print(f"generating {a.frames} frames", file=sys.stderr, flush=True)

@@ -63,9 +63,13 @@ enum ttice_prec { TTICE_PREC_FP64 = 0, TTICE_PREC_FP32 = 1, TTICE_PREC_BF16X3 = 
 enum ttice_algo { TTICE_ALG_PLAIN = 0, TTICE_ALG_STAR = 1 };
 
 /* TT-ICE* skip test: mean of the per-tensor relative errors (eq:relerror,
- * the rule Algorithm 2 uses) or the batch relative error
- * (eq:batchrelativeerror). */
-enum ttice_skip_rule { TTICE_SKIP_MEAN = 0, TTICE_SKIP_BATCH = 1 };
+ * the rule Algorithm 2 uses), the batch relative error
+ * (eq:batchrelativeerror), or none: never skip, update with the subselected
+ * tensors only (the experiments' "Subselect" variant, Sec. 5; an increment
+ * whose tensors are all within eps then appends their coefficients without
+ * an update).  With tau above 1 the occupancy test never fires: MEAN is then
+ * the experiments' "SS" variant, and MEAN with tau = 0.8 the full TT-ICE*. */
+enum ttice_skip_rule { TTICE_SKIP_MEAN = 0, TTICE_SKIP_BATCH = 1, TTICE_SKIP_NONE = 2 };
 
 enum ttice_option {
   TTICE_OPT_PREC = 1,      /* int32_t, enum ttice_prec (default FP64)          */

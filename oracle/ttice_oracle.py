@@ -201,6 +201,8 @@ class TTICE:
             raise ValueError("eps must lie in (0, 1)")
         if algo not in ("plain", "star"):
             raise ValueError("algo must be 'plain' or 'star'")
+        if skip_rule not in ("mean", "batch", "none"):
+            raise ValueError("skip_rule must be 'mean', 'batch' or 'none'")
         self.eps = float(eps)
         self.algo = algo
         self.tau = float(tau)
@@ -392,9 +394,13 @@ class TTICE:
         info["rel_err_old"] = rel.tolist()
         if self.skip_rule == "mean":
             skip = float(np.mean(rel)) <= eps
-        else:   # eq:batchrelativeerror
+        elif self.skip_rule == "batch":   # eq:batchrelativeerror
             tot = float(np.sum(nrm2))
             skip = (math.sqrt(float(np.sum(err2)) / tot) if tot > 0 else 0.0) <= eps
+        else:   # "none": the Subselect variant of Sec. 5 never skips
+            skip = False
+        # with no tensor above eps there is nothing to update with
+        skip = skip or not bool(np.any(rel > eps))
         if skip:
             info["skipped"] = True
             info["used"] = 0

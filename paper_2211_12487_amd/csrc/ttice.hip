@@ -685,7 +685,9 @@ int ttice_state::update_impl(const TIn* batch, int64_t N, ttice_update_info* inf
         info->margin[i] = std::numeric_limits<double>::infinity();
       }
     }
-    const bool skip = (skip_rule == TTICE_SKIP_MEAN) ? (mean_rel <= eps) : (batch_rel <= eps);
+    const bool skip = skip_rule == TTICE_SKIP_MEAN    ? mean_rel <= eps
+                      : skip_rule == TTICE_SKIP_BATCH ? batch_rel <= eps
+                                                      : false;
     if (skip || nD == 0) {
       // eq:appendupdate: the coefficients already sit in the last core
       if (info) {
@@ -824,7 +826,7 @@ int ttice_set_option(ttice_state* st, int32_t key, const void* val) {
     }
     case TTICE_OPT_SKIP_RULE: {
       const int32_t v = *(const int32_t*)val;
-      if (v != TTICE_SKIP_MEAN && v != TTICE_SKIP_BATCH) return TTICE_EINVAL;
+      if (v != TTICE_SKIP_MEAN && v != TTICE_SKIP_BATCH && v != TTICE_SKIP_NONE) return TTICE_EINVAL;
       st->skip_rule = v;
       return TTICE_OK;
     }
@@ -1089,7 +1091,7 @@ int ttice_load(const void* buf, int64_t size, ttice_state** out) {
   }
   if (prec != TTICE_PREC_FP64 && prec != TTICE_PREC_FP32 && prec != TTICE_PREC_BF16X3) return TTICE_EINVAL;
   if (algo != TTICE_ALG_PLAIN && algo != TTICE_ALG_STAR) return TTICE_EINVAL;
-  if (skip != TTICE_SKIP_MEAN && skip != TTICE_SKIP_BATCH) return TTICE_EINVAL;
+  if (skip != TTICE_SKIP_MEAN && skip != TTICE_SKIP_BATCH && skip != TTICE_SKIP_NONE) return TTICE_EINVAL;
   if (!(tau > 0.0 && tau < 1e300)) return TTICE_EINVAL;
   const size_t need = image_bytes(d, dims, rk, n_total);
   if (need == 0 || (int64_t)need != size) return TTICE_EINVAL;

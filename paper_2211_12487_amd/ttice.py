@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 ALGO = {"plain": 0, "star": 1}
-SKIP = {"mean": 0, "batch": 1}
+SKIP = {"mean": 0, "batch": 1, "none": 2}
 OPT_PREC, OPT_ALGO, OPT_SKIP_RULE, OPT_TAU, OPT_STREAM, OPT_PROFILE = 1, 2, 3, 4, 5, 6
 KERNEL_PROJ_L1 = 0
 F32, F64 = 0, 1

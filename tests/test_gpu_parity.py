@@ -263,3 +263,34 @@ def test_star_occupancy_heuristic(skip_rule):
     assert orthogonality(g) <= 1e-12
     assert occ > 0
     log(f"  occupancy skips in the oracle: {occ}")
+
+
+@pytest.mark.parametrize("variant,skip_rule,tau", [("Subselect", "none", 2.0), ("SS", "mean", 2.0),
+                                                   ("TT-ICE*", "mean", 0.8)])
+def test_star_ablation_variants(variant, skip_rule, tau):
+    """The experiments' Algorithm 2 variants (Sec. 5): Subselect (never skip,
+    update with the tensors above eps), SS (skip on the mean rule, no
+    occupancy) and the full TT-ICE* (tau = 0.8): skip decisions, tensors
+    used, ranks and reconstructions against the oracle, on a noisy low-rank
+    stream and on a batch of in-span tensors with one large outsider (mean
+    error within eps, so SS skips it and Subselect updates with it alone)."""
+    log(f"case ablation {variant}")
+    dims, eps = (12, 10, 6), 0.05
+    g = make(dims, eps, algo="star", tau=tau, skip_rule=skip_rule)
+    o = Oracle(dims, eps, algo="star", tau=tau, skip_rule=skip_rule)
+    rng = np.random.default_rng(8)
+    batches = [Y + 1e-3 * rng.standard_normal(Y.shape)
+               for Y in synth.tt_lowrank_stream(dims, (3, 4, 4), 40, 4, seed=8)]
+    lo = np.concatenate(list(synth.tt_lowrank_stream(dims, (2, 3, 3), 49, 49, seed=21)))  # mean error ~ 1/40
+    out = 30.0 * np.random.default_rng(22).standard_normal((1,) + dims)
+    batches += [lo[:10], np.concatenate([lo[10:], out])]
+    for k, Y in enumerate(batches):
+        gi = g.update(to_dev(Y))
+        oi = o.update(Y)
+        assert gi["skipped"] == oi["skipped"] and gi["used"] == oi["used"], (k, gi["used"], oi["used"])
+        if not oi["skipped"]:
+            assert gi["eps_upd"] == pytest.approx(oi["eps_upd"], rel=1e-9)
+        assert gi["ranks"][1:-1] == oi["ranks"][1:-1], (k, gi["ranks"], oi["ranks"])
+    assert oi["used"] == (1 if skip_rule == "none" else 0)
+    full_reconstruction_error(g, o, 1e-10)
+    assert orthogonality(g) <= 1e-12

@@ -149,6 +149,53 @@ def test_P8_star_equals_plain_when_all_frames_exceed():
     np.testing.assert_allclose(a.reconstruct(), b.reconstruct(), atol=1e-10 * np.abs(a.reconstruct()).max())
 
 
+def _span_batch_with_outsider(dims, n_in, seed):
+    """n_in tensors of an exactly low-rank stream (in the span of the cores
+    its first batch discovers) followed by one Gaussian tensor large enough
+    to dominate the batch norm (so the relaxed tolerance cannot absorb it)."""
+    lo = np.concatenate(list(synth.tt_lowrank_stream(dims, (2, 3, 3), 10 + n_in, 10 + n_in, seed=seed)))
+    out = 30.0 * np.random.default_rng(seed + 1).standard_normal((1,) + tuple(dims))  # dominates ||Y||
+    return lo[:10], np.concatenate([lo[10:], out])
+
+
+def test_P15_subselect_updates_only_with_frames_above_eps():
+    """Sec. 5 "Subselect" (skip rule none) against "SS" (mean rule): on a
+    batch whose mean relative error is within eps but whose last tensor is
+    not, the mean rule skips while the subselect rule updates with exactly
+    that tensor; the batch error afterwards is within eps (the guarantee of
+    eq:epsilonmodification), checked by brute-force reconstruction."""
+    dims, eps = (8, 6, 5), 0.1
+    first, batch = _span_batch_with_outsider(dims, 19, 3)
+    a = TTICE(dims, eps, algo="star", tau=2.0, skip_rule="mean")
+    b = TTICE(dims, eps, algo="star", tau=2.0, skip_rule="none")
+    a.update(first)
+    b.update(first)
+    ranks0 = list(a.ranks)
+    ia = a.update(batch)
+    ib = b.update(batch)
+    rel = np.array(ib["rel_err_old"])
+    assert rel[:-1].max() < 1e-10 and rel[-1] > eps and rel.mean() <= eps
+    assert ia["skipped"] and list(a.ranks) == ranks0
+    assert not ib["skipped"] and ib["used"] == 1 and sum(ib["rR"]) >= 1
+    Yhat = b.reconstruct()[-batch.shape[0]:]
+    assert float(np.sum((batch - Yhat) ** 2)) <= eps ** 2 * float(np.sum(batch ** 2)) * (1 + 1e-9)
+
+
+def test_P16_subselect_with_every_frame_within_eps_appends_only():
+    """Skip rule none: when every tensor of the batch is already within eps
+    there is no tensor to update with; the coefficients are appended and the
+    ranks do not change."""
+    dims, eps = (8, 6, 5), 0.1
+    first, batch = _span_batch_with_outsider(dims, 6, 5)
+    b = TTICE(dims, eps, algo="star", tau=2.0, skip_rule="none")
+    b.update(first)
+    ranks0 = list(b.ranks)
+    info = b.update(batch[:-1])
+    assert info["skipped"] and info["used"] == 0 and list(b.ranks) == ranks0
+    Yhat = b.reconstruct()[-(batch.shape[0] - 1):]
+    np.testing.assert_allclose(Yhat, batch[:-1], atol=1e-10 * np.abs(batch).max())
+
+
 # -- P9: brute force on the whole accumulation; CR by hand ----------------------------
 
 def test_P9_bruteforce_rre_and_cr():
