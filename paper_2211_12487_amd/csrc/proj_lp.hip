@@ -28,18 +28,42 @@ using proj::store_vec;
 using proj::Vec;
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f8 __attribute__((ext_vector_type(8)));
 
-// bf16 of an FP32 value, rounded to nearest even (finite inputs)
-__device__ __forceinline__ unsigned short bf16_bits(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+// x = hi + lo + O(2^-16 |x|): hi = bf16(x), lo = bf16(x - hi), both rounded
+// to nearest even by the hardware's packed FP32 -> BF16 conversion (two
+// values per instruction; widening back to FP32 is a shift)
+__device__ __forceinline__ void split_bf16(const f8& x, bf16x8& hi, bf16x8& lo) {
+  hi = __builtin_convertvector(x, bf16x8);
+  lo = __builtin_convertvector(x - __builtin_convertvector(hi, f8), bf16x8);
 }
-__device__ __forceinline__ float bf16_value(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
-// Fixed-order tree over the W waves' FP64 partials (NV per lane), ending in
-// wave 0; the same as the FP64 kernel's.
+// Sum of the W waves' FP64 partials (NV per lane) into wave 0, in the fixed
+// order w = 0, 1, ..., W-1: waves 1.. write theirs to LDS, one barrier, wave
+// 0 adds them (one barrier in all, where a pairwise tree needs two per
+// level).  red: (W-1) NV 64 doubles.
+template <int W, int NV>
+__device__ __forceinline__ void waves_to_first(double (&v)[NV], double* red, int wid, int lane) {
+  if (W == 1) return;
+  if (wid > 0) {
+    double* o = red + (int64_t)(wid - 1) * NV * 64 + lane;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) o[q * 64] = v[q];
+  }
+  __syncthreads();
+  if (wid == 0)
+#pragma unroll
+    for (int w = 1; w < W; ++w) {
+      const double* o = red + (int64_t)(w - 1) * NV * 64 + lane;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[q] += o[q * 64];
+    }
+}
+constexpr size_t flat_red_bytes(int W, int NV) { return (size_t)(W > 1 ? W - 1 : 1) * NV * 64 * sizeof(double); }
+constexpr size_t kRedBudget = 80 * 1024;
+
+// Pairwise fixed-order tree (two barriers per level, half the LDS of the
+// flat sum), for partials too wide for the flat buffer.
 template <int W, int NV>
 __device__ __forceinline__ void wave_tree(double (&v)[NV], double* red, int wid, int lane) {
 #pragma unroll
@@ -57,6 +81,18 @@ __device__ __forceinline__ void wave_tree(double (&v)[NV], double* red, int wid,
     }
     __syncthreads();
   }
+}
+
+template <int W, int NV>
+constexpr bool use_flat() { return flat_red_bytes(W, NV) <= kRedBudget; }
+template <int W, int NV>
+constexpr size_t red_lds_bytes() { return use_flat<W, NV>() ? flat_red_bytes(W, NV) : proj::red_bytes(W, NV); }
+template <int W, int NV>
+__device__ __forceinline__ void reduce_waves(double (&v)[NV], double* red, int wid, int lane) {
+  if constexpr (use_flat<W, NV>())
+    waves_to_first<W, NV>(v, red, wid, lane);
+  else
+    wave_tree<W, NV>(v, red, wid, lane);
 }
 
 // Wave 0's epilogue: v holds the RT x VEC x 4 tile values (element i of tile
@@ -165,7 +201,7 @@ __global__ __launch_bounds__(64 * W) void k_proj_f32(int32_t rows, int32_t r, in
       for (int i = 0; i < 4; ++i) v[(t * VEC + g) * 4 + i] = (double)acc[t][g][i];
 #pragma unroll
   for (int g = 0; g < VEC; ++g) v[RT * VEC * 4 + g] = zz[g];
-  wave_tree<W, NV>(v, red, wid, lane);
+  reduce_waves<W, NV>(v, red, wid, lane);
   if (wid != 0) return;
   proj_store<VEC, RT, NV>(v, kq, valid, j, r, C, vc, znorm2, rho2);
 }
@@ -216,37 +252,34 @@ __global__ __launch_bounds__(64 * W) void k_proj_bf3(int32_t rows, int32_t r, in
 #pragma unroll
     for (int o = 0; o < kOcts; ++o) {
       if (ob + o >= o1) break;  // uniform over the wave
-      u16x8 ahi[RT], alo[RT];
+      bf16x8 ahi[RT], alo[RT];
 #pragma unroll
-      for (int t = 0; t < RT; ++t)
+      for (int t = 0; t < RT; ++t) {
+        f8 a;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const bool live = (ob + o) * 32 + 8 * kq + q < rows;
-          const float a = live ? (float)ur[o][q][t] : 0.f;
-          const unsigned short h = bf16_bits(a);
-          ahi[t][q] = h;
-          alo[t][q] = bf16_bits(a - bf16_value(h));
+          a[q] = live ? (float)ur[o][q][t] : 0.f;
         }
+        split_bf16(a, ahi[t], alo[t]);
+      }
 #pragma unroll
       for (int g = 0; g < VEC; ++g) {
-        u16x8 bhi, blo;
+        f8 z;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const bool live = (ob + o) * 32 + 8 * kq + q < rows;
           const double zd = live ? (double)zr[o][q].v[g] : 0.0;
           zz[g] = fma(zd, zd, zz[g]);
-          const float z = (float)zd;
-          const unsigned short h = bf16_bits(z);
-          bhi[q] = h;
-          blo[q] = bf16_bits(z - bf16_value(h));
+          z[q] = (float)zd;
         }
-        const bf16x8 bh = __builtin_bit_cast(bf16x8, bhi), bl = __builtin_bit_cast(bf16x8, blo);
+        bf16x8 bh, bl;
+        split_bf16(z, bh, bl);
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
-          const bf16x8 ah = __builtin_bit_cast(bf16x8, ahi[t]), al = __builtin_bit_cast(bf16x8, alo[t]);
-          acc[t][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[t][g], 0, 0, 0);
-          acc[t][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[t][g], 0, 0, 0);
-          acc[t][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[t][g], 0, 0, 0);
+          acc[t][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[t], bh, acc[t][g], 0, 0, 0);
+          acc[t][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[t], bl, acc[t][g], 0, 0, 0);
+          acc[t][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[t], bh, acc[t][g], 0, 0, 0);
         }
       }
     }
@@ -260,7 +293,7 @@ __global__ __launch_bounds__(64 * W) void k_proj_bf3(int32_t rows, int32_t r, in
       for (int i = 0; i < 4; ++i) v[(t * VEC + g) * 4 + i] = (double)acc[t][g][i];
 #pragma unroll
   for (int g = 0; g < VEC; ++g) v[RT * VEC * 4 + g] = zz[g];
-  wave_tree<W, NV>(v, red, wid, lane);
+  reduce_waves<W, NV>(v, red, wid, lane);
   if (wid != 0) return;
   proj_store<VEC, RT, NV>(v, kq, valid, j, r, C, vc, znorm2, rho2);
 }
@@ -269,9 +302,9 @@ template <int P, typename TIn, int VEC, int RT>
 hipError_t launch_lp(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz, const double* U,
                      int64_t ldu, double* C, View vc, double* znorm2, double* rho2, hipEvent_t ev0,
                      hipEvent_t ev1) {
-  constexpr int W = RT == 4 ? 4 : 8;
-  constexpr size_t lds = proj::red_bytes(W, RT * VEC * 4 + VEC);
-  static_assert(lds <= 80 * 1024, "reduction buffer");
+  constexpr int W = 4;  // four waves split the row blocks (measured: beats eight, whose sum costs more)
+  constexpr size_t lds = red_lds_bytes<W, RT * VEC * 4 + VEC>();
+  static_assert(lds <= kRedBudget, "reduction buffer");
   const void* fn = P == kProjFP32 ? (const void*)k_proj_f32<TIn, VEC, RT, W> : (const void*)k_proj_bf3<TIn, VEC, RT, W>;
   // once per process (thread-safe static initialisation)
   static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
