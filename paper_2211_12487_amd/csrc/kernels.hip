@@ -212,21 +212,26 @@ __device__ void split_finish(double (&acc)[4][4], int32_t M, int32_t N, int32_t 
 // valid block at most four 16 x 16 sub-blocks: M, N <= 32, or one of them
 // <= 16) and a long K whose operands are linear along K
 // (A(m, k) = A[row_off(m) + k sa], B(k, n) = B[k sb + col_off(n)]; no
-// frames along K).  Wave w takes sub-block w, and v_mfma_f64_16x16x4f64
-// reads its operands straight from memory in the instruction's layout:
-// lane (q, i) = (l / 16, l % 16) supplies A(m0 + 16 mb + i, k + q) and
+// frames along K).  The block's four waves cover the nsb sub-blocks, and
+// when there are fewer sub-blocks than waves the spare waves take further
+// parts of the K slice (parts = 4, 2 or 1 for nsb = 1, 2, 3..4): wave w works
+// on sub-block w mod nsb over part w / nsb.  v_mfma_f64_16x16x4f64 reads its
+// operands straight from memory in the instruction's layout: lane
+// (q, i) = (l / 16, l % 16) supplies A(m0 + 16 mb + i, k + q) and
 // B(k + q, n0 + 16 nb + i), so no LDS staging and no barrier sit in the K
-// loop.  A batch of 32 k-steps (128 values of k) is loaded at once, 64
-// operand doubles per lane all in flight together (data written by another
-// kernel is about a microsecond away), then multiplied with two accumulator
-// chains; k is clamped into the slice and masked, so every load is
-// unconditional.  The result goes through LDS to the layout of
-// split_finish.  (Larger outputs stay on the LDS-tiled kernel: their
-// single-block reduction of many partials costs more than the matrix cores
-// save.)
+// loop.  A batch of 32 k-steps (128 values of k) per wave is loaded at once,
+// 64 operand doubles per lane all in flight together (data written by
+// another kernel is about a microsecond away), then multiplied with two
+// accumulator chains; k is clamped into the wave's part and masked, so
+// every load is unconditional.  The parts of a sub-block are added through
+// LDS in the order part 0, 1, ... into the layout of split_finish.  (Larger
+// outputs stay on the LDS-tiled kernel: their single-block reduction of many
+// partials costs more than the matrix cores save.)
 // ---------------------------------------------------------------------------
 typedef double mf4 __attribute__((ext_vector_type(4)));
 constexpr int kMfmaBatch = 32;  // k-steps of 4 per load batch
+
+__host__ __device__ constexpr int mfma_parts(int nsb) { return nsb <= 1 ? 4 : nsb == 2 ? 2 : 1; }
 
 template <typename TB, typename TE, typename TD>
 __global__ __launch_bounds__(256) void k_gemm_mfma(int32_t M, int32_t N, int32_t K, int32_t kchunk, double alpha,
@@ -236,6 +241,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int32_t M, int32_t N, int32_t
                                                     double* __restrict__ colpart, double* __restrict__ part,
                                                     int* __restrict__ cnt) {
   __shared__ double tile_s[64 * 65];
+  __shared__ double part_s[4][256];  // each wave's 16 x 16 accumulator
   __shared__ double red[256];
   const int t = threadIdx.x;
   const int l = t & 63;
@@ -246,24 +252,31 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int32_t M, int32_t N, int32_t
   const int32_t ke = min(K, kb + kchunk);  // kb < ke: the host sizes the slices
   const int32_t Mt = min(64, M - m0), Nt = min(64, N - n0);
   const int nnb = (Nt + 15) >> 4, nsb = ((Mt + 15) >> 4) * nnb;  // nsb <= 4
-  const int mb = w / nnb, nb = w - (w / nnb) * nnb;
+  const int parts = mfma_parts(nsb);
+  const bool active = w < nsb * parts;  // (nsb = 3: wave 3 idles)
+  const int sbk = w % nsb, kp = w / nsb;
+  const int mb = sbk / nnb, nb = sbk - (sbk / nnb) * nnb;
   const int32_t m = m0 + 16 * mb + i16, n = n0 + 16 * nb + i16;
-  const bool ok = w < nsb && m < M;  // waves past the block multiply zeros
+  const bool ok = active && m < M;
   const int64_t aro = row_off(va, min(m, M - 1));
   const int64_t bco = col_off(vb, min(n, N - 1));  // columns past N read column N-1; their outputs are dropped
   const int64_t sa = va.cs, sb = vb.rs;
+  // this wave's part of the slice: contiguous k-steps of 4
+  const int32_t steps = (ke - kb + 3) >> 2, per = (steps + parts - 1) / parts;
+  const int32_t kwb = active ? min(ke, kb + 4 * kp * per) : ke;
+  const int32_t kwe = active ? min(ke, kb + 4 * (kp + 1) * per) : ke;
 
   mf4 acc0 = mf4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-  for (int32_t k0 = kb; k0 < ke; k0 += 4 * kMfmaBatch) {
+  for (int32_t k0 = kwb; k0 < kwe; k0 += 4 * kMfmaBatch) {
     double av[kMfmaBatch], bv[kMfmaBatch];
 #pragma unroll
     for (int u = 0; u < kMfmaBatch; ++u) {
       const int32_t k = k0 + 4 * u + kq;
-      const int32_t kc = min(k, ke - 1);
+      const int32_t kc = min(k, kwe - 1);
       const double a = A[aro + (int64_t)kc * sa];
       const double b = (double)B[(int64_t)kc * sb + bco];
-      av[u] = (k < ke && ok) ? a : 0.0;
-      bv[u] = (k < ke) ? b : 0.0;
+      av[u] = (k < kwe && ok) ? a : 0.0;
+      bv[u] = (k < kwe) ? b : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kMfmaBatch; u += 2) {
@@ -271,11 +284,10 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int32_t M, int32_t N, int32_t
       acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u + 1], bv[u + 1], acc1, 0, 0, 0);
     }
   }
-  // element i of lane l of sub-block (mb, nb): row 16 mb + l / 16 + 4 i,
-  // column 16 nb + l % 16
-  if (w < nsb)
+  // element i of lane l of a sub-block: row l / 16 + 4 i, column l % 16
+  if (active)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) tile_s[(16 * mb + kq + 4 * i) * 65 + 16 * nb + i16] = acc0[i] + acc1[i];
+    for (int i = 0; i < 4; ++i) part_s[w][(kq + 4 * i) * 16 + i16] = acc0[i] + acc1[i];
   __syncthreads();
   const int tx = t & 15, ty = t >> 4;
   double c[4][4];
@@ -284,9 +296,14 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int32_t M, int32_t N, int32_t
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int32_t mi = ty + 16 * i, nj = tx + 16 * j;
-      c[i][j] = (mi < Mt && nj < Nt) ? tile_s[mi * 65 + nj] : 0.0;
+      double v = 0.0;
+      if (mi < Mt && nj < Nt) {
+        const int sub = (mi >> 4) * nnb + (nj >> 4);
+        const int e = (mi & 15) * 16 + (nj & 15);
+        for (int q = 0; q < parts; ++q) v += part_s[sub + nsb * q][e];
+      }
+      c[i][j] = v;
     }
-  __syncthreads();  // tile_s is reused by the split reduction
   split_finish<TE, TD>(c, M, N, m0, n0, alpha, beta, E, ve, D, vd, colpart, part, cnt, tile_s, red);
 }
 
@@ -609,7 +626,7 @@ hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk,
     // block of each tile adds the partials in order.
     int64_t S = 1;
     if (can_split) {
-      const int64_t batch = 4 * kMfmaBatch;
+      const int64_t batch = 4 * kMfmaBatch * mfma_parts((int)nsb);  // k per slice: one batch per wave
       S = std::min<int64_t>({(K + batch - 1) / batch, std::max<int64_t>(1, 1024 / tiles), (int64_t)kMfmaMaxSplit});
       S = std::max<int64_t>(1, std::min<int64_t>(S, ws.len / std::max<int64_t>(MN, 1)));
     }
