@@ -39,10 +39,10 @@ def parse():
                     help="increments of the stream the CPU oracle baseline compresses")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-arm", action="store_true")
-    ap.add_argument("--workload", default="video240", choices=["video240", "serving", "ablation"],
+    ap.add_argument("--workload", default="video240", choices=["video240", "serving", "ablation", "gel"],
                     help="video240: the headline stream (default); serving: the many-stream mix, reported "
                          "as arrival-to-completion latency")
-    ap.add_argument("--eps", type=float, default=0.1, help="ablation: eps_des")
+    ap.add_argument("--eps", type=float, default=None, help="ablation / gel: eps_des (default 0.1 / 0.01)")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: length of the arrival trace")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrivals per second")
     ap.add_argument("--streams", type=int, default=256, help="serving: number of streams")
@@ -268,15 +268,54 @@ VARIANTS = [("TT-ICE", dict(algo="plain")),
             ("TT-ICE*", dict(algo="star", skip_rule="mean", tau=0.8))]
 
 
-def ablation(a):
-    """Every Algorithm 2 variant of the experiments on the same runs: wall
+def run_variants(Yd, starts, dims, eps, variants):
+    """Each variant on the same increments (Yd[starts[k]:starts[k+1]]): wall
     time, tensors/s, tensors used in core updates, skipped increments, final
     ranks, compression ratio (eq:compressionratio) and mean relative
     reconstruction error over the stored tensors (eq:MRRE)."""
     import torch
-    from paper_2211_12487_amd import synth
     from paper_2211_12487_amd.ttice import TTICE
+    total = int(starts[-1])
+    n_inc = len(starts) - 1
+    warm = TTICE(dims, eps)  # first-use allocations and module load, not timed
+    warm.update(Yd[: starts[1]])
+    warm.close()
+    results = {}
+    for name, kw in variants:
+        print(f"variant {name}", file=sys.stderr, flush=True)
+        g = TTICE(dims, eps, prec="fp64", **kw)
+        used = skipped = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n_inc):
+            info = g.update(Yd[starts[k]:starts[k + 1]])
+            used += info["used"]
+            skipped += int(info["skipped"])
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        ranks = g.ranks()
+        rre = []
+        for k in range(0, total, 256):
+            cnt = min(256, total - k)
+            rec = g.reconstruct(k, cnt)
+            ref = Yd[k:k + cnt].double()
+            rre.append(((rec - ref).flatten(1).norm(dim=1) / ref.flatten(1).norm(dim=1)).cpu().numpy())
+        d = len(dims)
+        stored = sum(ranks[i] * dims[i] * ranks[i + 1] for i in range(d)) + ranks[d] * total
+        results[name] = dict(seconds=secs, tensors_per_s=total / secs, tensors_used=int(used),
+                             skipped_increments=skipped, ranks=ranks,
+                             compression_ratio=total * math.prod(dims) / stored,
+                             mean_rre=float(np.concatenate(rre).mean()))
+        g.close()
+    return results
+
+
+def ablation(a):
+    """Every Algorithm 2 variant of the experiments on ATARI-shaped runs."""
+    import torch
+    from paper_2211_12487_amd import synth
     w = ABLATION
+    eps = 0.1 if a.eps is None else a.eps
     rng = np.random.default_rng(w["seed"])
     lens = rng.integers(w["run_len"][0], w["run_len"][1] + 1, w["runs"])
     total = int(lens.sum())
@@ -285,38 +324,7 @@ def ablation(a):
     Y = np.concatenate(list(synth.video_stream(total, 256, height=h, width=wd, channels=c, seed=w["seed"])))
     dims = w["dims"]
     Yd = torch.from_numpy(Y.reshape((total,) + dims)).cuda()
-    starts = np.concatenate([[0], np.cumsum(lens)])
-    warm = TTICE(dims, a.eps)  # first-use allocations and module load, not timed
-    warm.update(Yd[: starts[1]])
-    warm.close()
-    results = {}
-    for name, kw in VARIANTS:
-        print(f"ablation {name}", file=sys.stderr, flush=True)
-        g = TTICE(dims, a.eps, prec="fp64", **kw)
-        used = skipped = 0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(w["runs"]):
-            info = g.update(Yd[starts[k]:starts[k + 1]])
-            used += info["used"]
-            skipped += int(info["skipped"])
-        torch.cuda.synchronize()
-        secs = time.perf_counter() - t0
-        ranks = g.ranks()
-        rre = []
-        for k in range(w["runs"]):
-            rec = g.reconstruct(int(starts[k]), int(lens[k]))
-            ref = Yd[starts[k]:starts[k + 1]].double()
-            num = (rec - ref).flatten(1).norm(dim=1)
-            den = ref.flatten(1).norm(dim=1)
-            rre.append((num / den).cpu().numpy())
-        d = len(dims)
-        stored = sum(ranks[i] * dims[i] * ranks[i + 1] for i in range(d)) + ranks[d] * total
-        results[name] = dict(seconds=secs, tensors_per_s=total / secs, tensors_used=int(used),
-                             skipped_increments=skipped, ranks=ranks,
-                             compression_ratio=total * math.prod(dims) / stored,
-                             mean_rre=float(np.concatenate(rre).mean()))
-        g.close()
+    results = run_variants(Yd, np.concatenate([[0], np.cumsum(lens)]), dims, eps, VARIANTS)
     star = results["TT-ICE*"]
     return dict(
         metric="TT-ICE* tensors/s on ATARI-shaped runs (all Algorithm 2 variants reported)",
@@ -324,8 +332,40 @@ def ablation(a):
         ms_per_step=star["seconds"] * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f64", data="synthetic",
         config=dict(workload=f"{w['name']}: {w['runs']} runs of {w['run_len'][0]}-{w['run_len'][1]} frames "
-                             f"{h}x{wd}x{c} as {dims}, fp32 input, eps={a.eps}, one run per increment",
-                    frames=total, eps=a.eps),
+                             f"{h}x{wd}x{c} as {dims}, fp32 input, eps={eps}, one run per increment",
+                    frames=total, eps=eps),
+        variants=results)
+
+
+# gel-shaped simulations: one 7x13x37x3x10 tensor per increment (the
+# experiments' per-simulation reshape); a family of simulations sharing
+# structure stands in as an exactly low-rank TT stream plus relative noise
+GEL = dict(name="gel-shaped", dims=(7, 13, 37, 3, 10), tensors=400, ranks=(5, 15, 30, 10, 12), noise=1e-3, seed=9)
+
+
+def gel(a):
+    """TT-ICE and TT-ICE* with tau = 1 (the experiments' setting for these
+    simulations) on gel-shaped tensors, one per increment."""
+    import torch
+    from paper_2211_12487_amd import synth
+    w = GEL
+    eps = 0.01 if a.eps is None else a.eps
+    print(f"generating {w['tensors']} tensors {w['dims']}", file=sys.stderr, flush=True)
+    Y = np.concatenate(list(synth.tt_lowrank_stream(w["dims"], w["ranks"], w["tensors"], 64, seed=w["seed"])))
+    rng = np.random.default_rng(w["seed"] + 1)
+    Y = (Y + w["noise"] * Y.std() * rng.standard_normal(Y.shape)).astype(np.float32)
+    Yd = torch.from_numpy(Y).cuda()
+    variants = [("TT-ICE", dict(algo="plain")), ("TT-ICE*", dict(algo="star", skip_rule="mean", tau=1.0))]
+    results = run_variants(Yd, np.arange(w["tensors"] + 1), w["dims"], eps, variants)
+    star = results["TT-ICE*"]
+    return dict(
+        metric="TT-ICE* tensors/s on gel-shaped simulations, one per increment (TT-ICE reported beside it)",
+        value=star["tensors_per_s"], unit="tensors/s", n_gpus=1, steps=1, warmup=1,
+        ms_per_step=star["seconds"] * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload=f"{w['name']}: {w['tensors']} tensors {w['dims']} (TT ranks {w['ranks']}, "
+                             f"relative noise {w['noise']}), fp32 input, eps={eps}, one per increment",
+                    tensors=w["tensors"], eps=eps),
         variants=results)
 
 
@@ -343,6 +383,9 @@ def main():
         return
     if a.workload == "ablation":
         print(json.dumps(ablation(a)), flush=True)
+        return
+    if a.workload == "gel":
+        print(json.dumps(gel(a)), flush=True)
         return
     w = WORKLOAD
     print(f"generating {a.frames} frames", file=sys.stderr, flush=True)
