@@ -115,7 +115,7 @@ struct ttice_state {
   // workspace
   DevBuf z[2], rbuf, colpart, bnorm, fres, fy2, e2acc, scal, gpart, gram, tri, order, lam, tail, W, W2, T,
       S, dlist, eigws, splitk, tilecnt;
-  double* hs = nullptr;  // pinned host scalars (64 doubles)
+  double* hs = nullptr;  // pinned host scalars (64 doubles), written by the decision kernels
 
   // kernel profiling (TTICE_OPT_PROFILE): event pairs recorded during one
   // update and resolved when it has completed
@@ -240,8 +240,9 @@ int ttice_state::grow_core(Core& c, int64_t need_rows, int64_t need_cols, int64_
   return TTICE_OK;
 }
 
-int ttice_state::sync_scalars(int n) {
-  CK(hipMemcpyAsync(hs, scal.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, stream));
+// The decision scalars are written by the kernels straight into the pinned
+// host buffer hs (device-visible), so waiting for them needs no copy kernel.
+int ttice_state::sync_scalars(int /*n*/) {
   CK(hipStreamSynchronize(stream));
   return TTICE_OK;
 }
@@ -384,12 +385,12 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
     if (i == 0 && tol2 < 0) {
       CKS(ensure(fy2, (size_t)N * sizeof(double)));
       CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, as<double>(fy2)));
-      CK(total_sum(st, as<double>(fy2), N, as<double>(scal) + 2));
+      CK(total_sum(st, as<double>(fy2), N, hs + 2));
     }
 
     if (!occ_skip) {
       CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
-      CK(total_sum(st, as<double>(fres), N, as<double>(scal)));
+      CK(total_sum(st, as<double>(fres), N, hs));
       CKS(sync_scalars(4));
       if (i == 0 && tol2 < 0) {
         const double ny2 = hs[2];
@@ -406,7 +407,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         // tolerance: take the decision on the FP64 projection instead
         CK(fused_pass(kProjFP64, false));
         CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
-        CK(total_sum(st, as<double>(fres), N, as<double>(scal)));
+        CK(total_sum(st, as<double>(fres), N, hs));
         CKS(sync_scalars(4));
         rho2 = hs[0];
         if (hs[1] != 0.0 || !isfinite(rho2)) return TTICE_EINVAL;
@@ -456,7 +457,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         CK(sym_eigvals(st, (int32_t)m, as<double>(gram), dd, ee, tauv, wv, dd + 4 * m));
         const int64_t cap = rows - r;
         CK(select_rank(st, (int32_t)m, wv, tol2, cap, as<int32_t>(order), as<double>(lam),
-                       as<double>(tail), as<double>(scal)));
+                       as<double>(tail), hs));
         CKS(sync_scalars(4));
         if (hs[3] != 0.0) return TTICE_EDEVICE;
         rR = (int64_t)hs[0];
@@ -633,7 +634,7 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
     zin_is_input = false;
   }
   if (nonfinite && y2_out) {
-    CK(total_sum(st, y2_out, N, as<double>(scal) + 2));
+    CK(total_sum(st, y2_out, N, hs + 2));
     CKS(sync_scalars(4));
     *nonfinite = (hs[3] != 0.0 || !isfinite(hs[2])) ? 1 : 0;
   }
@@ -670,7 +671,7 @@ int ttice_state::update_impl(const TIn* batch, int64_t N, ttice_update_info* inf
                            &nonfinite));
     if (nonfinite) return TTICE_EINVAL;
     CK(star_decide(st, (int32_t)N, as<double>(e2acc), as<double>(fy2), eps, as<int32_t>(dlist),
-                   as<double>(scal)));
+                   hs));
     CKS(sync_scalars(6));
     const double mean_rel = hs[0], batch_rel = hs[1], sdc = hs[2], nd2 = hs[3];
     const int64_t nD = (int64_t)hs[4];
