@@ -266,185 +266,6 @@ __device__ __forceinline__ double recip(double q) {
   return r;
 }
 
-// Register-resident variant for m <= MR * H (H <= 4): thread t owns column
-// j = t / H and the MR rows h*MR .. of it (h = t % H), so the H threads of a
-// column are consecutive lanes of one quad.  A reflection then needs only the
-// current column x and p = tau A v in LDS: the matrix-vector product is a
-// register dot product plus a quad butterfly (DPP), the rank-2 update
-// A -= v w^T + w v^T is thread-local, and the threads of column k+1 publish
-// the next x and ||x[2:]||^2.  Two barriers per reflection.  Dependent FP64
-// chains are the cost here, so sums run as independent partial sums and
-// reciprocals use the hardware estimate and one Newton step.  Same outputs as
-// k_tridiag (dsytd2 order; v_k in row k of A, columns k+1..m-1).
-
-// v + (v of lane ^ X) over a quad, X = 1 or 2 (DPP quad permutation on the
-// two 32-bit halves)
-template <int X>
-__device__ __forceinline__ double quad_xor_add(double v) {
-  constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
-  const unsigned long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffffu), ctrl, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), ctrl, 0xf, 0xf, false);
-  return v + __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-template <int H>
-__device__ __forceinline__ double col_group_sum(double v) {
-  if (H >= 2) v = quad_xor_add<1>(v);
-  if (H >= 4) v = quad_xor_add<2>(v);
-  return v;
-}
-// sum_ii x[ii] * y[ii] as four interleaved partial sums
-template <int MR>
-__device__ __forceinline__ double dot4(const double (&x)[MR], const double (&y)[MR]) {
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int ii = 0; ii < MR; ++ii) s[ii & 3] = fma(x[ii], y[ii], s[ii & 3]);
-  return (s[0] + s[1]) + (s[2] + s[3]);
-}
-
-template <int H, int MR>
-__global__ __launch_bounds__(512) void k_tridiag_reg(int32_t m, double* __restrict__ A, double* __restrict__ d,
-                                                     double* __restrict__ e, double* __restrict__ tau) {
-  static_assert(H == 2 || H == 4, "columns are split over lanes of one quad");
-  constexpr int M = MR * H;  // largest m
-  __shared__ double xbuf[M];
-  __shared__ double pbuf[M];
-  __shared__ double red[8];
-  __shared__ double sig;
-  const int t = threadIdx.x;
-  const int32_t j = t / H;
-  const int h = t % H;
-  const int32_t i0 = h * MR;
-  const int lane = t & 63, wid = t >> 6;
-  const int nw = (int)((blockDim.x + 63) / 64);
-  const bool col = j < m;
-
-  double a[MR];
-#pragma unroll
-  for (int ii = 0; ii < MR; ++ii) {
-    const int32_t i = i0 + ii;
-    a[ii] = (col && i < m) ? A[(int64_t)i * m + j] : 0.0;
-  }
-  // entries past m stay zero, so both buffers can be read unconditionally
-  for (int32_t i = t; i < M; i += blockDim.x) {
-    pbuf[i] = 0.0;
-    xbuf[i] = 0.0;
-  }
-  __syncthreads();
-  // the column of the first reflection and ||x[2:]||^2 (the butterfly runs
-  // in every lane; only column 0's result is kept)
-  {
-    double sq[MR];
-#pragma unroll
-    for (int ii = 0; ii < MR; ++ii) {
-      const int32_t i = i0 + ii;
-      if (j == 0 && i < m) xbuf[i] = a[ii];
-      sq[ii] = (i >= 2 && i < m) ? a[ii] : 0.0;
-    }
-    const double sn = col_group_sum<H>(dot4<MR>(sq, sq));
-    if (j == 0 && h == 0) sig = sn;
-  }
-  __syncthreads();
-
-  for (int32_t k = 0; k + 2 < m; ++k) {
-    const double alpha = xbuf[k + 1];
-    const double sigma = sig;
-    double beta, tk, scale;
-    if (sigma == 0.0) {
-      tk = 0.0;
-      beta = alpha;
-      scale = 0.0;
-    } else {
-      beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-      tk = (beta - alpha) * recip(beta);
-      scale = recip(alpha - beta);
-    }
-    if (t == 0) {
-      d[k] = xbuf[k];
-      e[k] = beta;
-      tau[k] = tk;
-    }
-    // v = [1, x[1:] * scale] on indices k+1.., zero elsewhere.  The LDS
-    // reads are unconditional (a conditional read is compiled into a branch
-    // and a wait per element; the empty asm keeps them so) and the masking
-    // is arithmetic.
-    double vr[MR];
-#pragma unroll
-    for (int ii = 0; ii < MR; ++ii) vr[ii] = xbuf[i0 + ii];
-    double xj = xbuf[min(j, M - 1)];
-#pragma unroll
-    for (int ii = 0; ii < MR; ++ii) asm volatile("" : "+v"(vr[ii]));
-    asm volatile("" : "+v"(xj));
-#pragma unroll
-    for (int ii = 0; ii < MR; ++ii) {
-      const int32_t i = i0 + ii;
-      vr[ii] = (i == k + 1) ? 1.0 : vr[ii] * ((i > k + 1) ? scale : 0.0);
-    }
-    const double vj = (j == k + 1) ? 1.0 : xj * ((j > k + 1 && col) ? scale : 0.0);
-    if (h == 0 && col && j > k) A[(int64_t)k * m + j] = vj;  // v_k kept for the back-transformation
-    double pj = 0.0;
-    if (tk != 0.0) {
-      const double pp = col_group_sum<H>(dot4<MR>(a, vr));
-      pj = (col && j > k) ? tk * pp : 0.0;
-      double pv = (h == 0) ? pj * vj : 0.0;
-      pv = wave_sum(pv);
-      if (lane == 0) red[wid] = pv;
-      if (h == 0 && col) pbuf[j] = pj;
-    }
-    __syncthreads();
-    if (tk != 0.0) {
-      double rw[8];
-#pragma unroll
-      for (int w = 0; w < 8; ++w) rw[w] = w < nw ? red[w] : 0.0;
-      const double pv = ((rw[0] + rw[1]) + (rw[2] + rw[3])) + ((rw[4] + rw[5]) + (rw[6] + rw[7]));
-      const double gam = 0.5 * tk * pv;
-      const double wj = pj - gam * vj;
-      double pr[MR];
-#pragma unroll
-      for (int ii = 0; ii < MR; ++ii) pr[ii] = pbuf[i0 + ii];
-#pragma unroll
-      for (int ii = 0; ii < MR; ++ii) asm volatile("" : "+v"(pr[ii]));
-#pragma unroll
-      for (int ii = 0; ii < MR; ++ii) {
-        const double wi = pr[ii] - gam * vr[ii];
-        a[ii] = a[ii] - vr[ii] * wj - wi * vj;
-      }
-    }
-    // the next reflection's column (butterfly in every lane, as above)
-    {
-      const bool nxt = j == k + 1;
-      double sq[MR];
-#pragma unroll
-      for (int ii = 0; ii < MR; ++ii) {
-        const int32_t i = i0 + ii;
-        if (nxt && i < m) xbuf[i] = a[ii];
-        sq[ii] = (i >= k + 3 && i < m) ? a[ii] : 0.0;
-      }
-      const double sn = col_group_sum<H>(dot4<MR>(sq, sq));
-      if (nxt && h == 0) sig = sn;
-    }
-    __syncthreads();
-  }
-  // the last 2 x 2 block: xbuf holds column m-2, pbuf receives column m-1
-  if (m >= 2 && j == m - 1) {
-#pragma unroll
-    for (int ii = 0; ii < MR; ++ii)
-      if (i0 + ii < m) pbuf[i0 + ii] = a[ii];
-  }
-  __syncthreads();
-  if (t == 0) {
-    if (m >= 2) {
-      d[m - 2] = xbuf[m - 2];
-      e[m - 2] = xbuf[m - 1];
-      tau[m - 2] = 0.0;
-      d[m - 1] = pbuf[m - 1];
-    } else {
-      d[0] = xbuf[0];
-    }
-    tau[m - 1] = 0.0;
-  }
-}
-
 // ---- Register-distributed variant for blocks up to kRwMax wide: the
 // n x n trailing block at (ksw, ksw) of A (ld = lda) lives in registers,
 // wave w holding the RPW consecutive rows from w * RPW and lane l the
@@ -759,12 +580,13 @@ size_t tridiag_lds_bytes(int32_t m) {
 
 
 // w[j] = j-th largest eigenvalue of T, j < m, by multisection on the Sturm
-// count (LDL^T pivots of T - x I, tiny pivots replaced by -pivmin): the 64
-// lanes of a wave each count the eigenvalues below one of 64 interior points
-// of the eigenvalue's current interval, so it shrinks 65-fold per round; 9
-// rounds take the Gershgorin interval below rounding level.
-constexpr int kSect = 64;
-constexpr int kBisectRounds = 9;
+// count (LDL^T pivots of T - x I, tiny pivots replaced by -pivmin): one
+// workgroup per eigenvalue, its 256 threads each count the eigenvalues below
+// one of 256 interior points of the current interval, so it shrinks
+// 257-fold per round; 7 rounds (257^7 > 7e16) take the Gershgorin interval
+// below rounding level.
+constexpr int kSect = 256;
+constexpr int kBisectRounds = 7;
 
 __global__ __launch_bounds__(256) void k_bisect(int32_t m, const double* __restrict__ d,
                                                 const double* __restrict__ e, double* __restrict__ w) {
@@ -802,13 +624,12 @@ __global__ __launch_bounds__(256) void k_bisect(int32_t m, const double* __restr
   hi += 2.0 * u * nrm + 1e-300;
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax);
 
-  const int32_t j = (int32_t)blockIdx.x * (256 / kSect) + t / kSect;  // eigenvalue index (descending)
-  const int32_t l = t % kSect;
-  if (j >= m) return;  // whole waves leave together
-  const int32_t target = m - 1 - j;  // the target-th smallest (0-based)
+  __shared__ int kw[2][4];
+  const int32_t j = (int32_t)blockIdx.x;  // eigenvalue index (descending)
+  const int32_t target = m - 1 - j;      // the target-th smallest (0-based)
   for (int round = 0; round < kBisectRounds; ++round) {
     const double h = (hi - lo) / (double)(kSect + 1);
-    const double x = lo + h * (double)(l + 1);
+    const double x = lo + h * (double)(t + 1);
     int32_t c = 0;
     double q = 1.0;
     for (int32_t i = 0; i < m; ++i) {
@@ -816,15 +637,19 @@ __global__ __launch_bounds__(256) void k_bisect(int32_t m, const double* __restr
       if (fabs(q) < pivmin) q = -pivmin;
       c += q < 0.0;
     }
-    // the lanes whose point has at most `target` eigenvalues below it are
-    // the wave's first k lanes (the count is monotone in x)
-    const int k = __popcll(__ballot(c <= target));
+    // the threads whose point has at most `target` eigenvalues below it are
+    // the first k threads (the count is monotone in x); each wave counts
+    // its share
+    const int kc = __popcll(__ballot(c <= target));
+    if ((t & 63) == 0) kw[round & 1][t >> 6] = kc;
+    __syncthreads();
+    const int k = (kw[round & 1][0] + kw[round & 1][1]) + (kw[round & 1][2] + kw[round & 1][3]);
     const double nlo = (k == 0) ? lo : lo + h * (double)k;
     const double nhi = (k == kSect) ? hi : lo + h * (double)(k + 1);
     lo = nlo;
     hi = nhi;
   }
-  if (l == 0) w[j] = 0.5 * (lo + hi);
+  if (t == 0) w[j] = 0.5 * (lo + hi);
 }
 
 // LU with partial pivoting of T - lc I (tridiagonal, LAPACK gttrf order)
@@ -1166,13 +991,10 @@ hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* 
     return er;
   }();
   if (attr != hipSuccess) return attr;
-  // threads: H per column, whole waves
-  auto reg_threads = [m](int H) { return (unsigned)(((int64_t)m * H + 63) / 64 * 64); };
-  // (measured: the one-wave register variant wins up to m = 32)
-  if (m <= 32) {
-    hipLaunchKernelGGL((k_tridiag_reg<2, 16>), dim3(1), dim3(reg_threads(2)), 0, st, m, A, d, e, tau);
-  } else if (m <= kRwMax) {
-    if (m <= 64)
+  if (m <= kRwMax) {
+    if (m <= 32)
+      hipLaunchKernelGGL((k_tridiag_rw<1, 4>), dim3(1), dim3(kRwWaves * 64), 0, st, m, 0, m, A, d, e, tau);
+    else if (m <= 64)
       hipLaunchKernelGGL((k_tridiag_rw<1, 8>), dim3(1), dim3(kRwWaves * 64), 0, st, m, 0, m, A, d, e, tau);
     else if (m <= 96)
       hipLaunchKernelGGL((k_tridiag_rw<2, 12>), dim3(1), dim3(kRwWaves * 64), 0, st, m, 0, m, A, d, e, tau);
@@ -1199,8 +1021,7 @@ hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* 
   }
   hipError_t er = hipGetLastError();
   if (er != hipSuccess) return er;
-  hipLaunchKernelGGL(k_bisect, dim3((m + (256 / kSect) - 1) / (256 / kSect)), dim3(256),
-                     (size_t)2 * m * sizeof(double), st, m, d, e, w);
+  hipLaunchKernelGGL(k_bisect, dim3(m), dim3(kSect), (size_t)2 * m * sizeof(double), st, m, d, e, w);
   return hipGetLastError();
 }
 
