@@ -19,6 +19,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace ttice {
 namespace {
@@ -269,26 +270,34 @@ __device__ __forceinline__ double recip(double q) {
 // ---- Register-distributed variant for blocks up to kRwMax wide: the
 // n x n trailing block at (ksw, ksw) of A (ld = lda) lives in registers,
 // wave w holding the RPW consecutive rows from w * RPW and lane l the
-// columns l, l + 64 (CPL of them).  Reflection k:
-//  * the lane holding column k writes the wave's part of it to LDS (by
-//    symmetry this is x = A[k+1:, k]); one barrier;
-//  * every wave reads all of column k, one entry per lane, and forms
-//    ||x[1:]||^2 with a wave sum (the same sum in every wave), beta, tau and
-//    v_j for the lane's columns;
-//  * v of the wave's own rows comes from the same column k as broadcast
-//    16-byte reads; p = tau A v is formed as column sums of the wave's
-//    rows, one partial row per wave through LDS; one barrier;
-//  * every wave adds the partials in the order w = 0, 1, ..., forms
-//    w = p - (tau/2)(p.v) v on its columns and, through a wave-private LDS
-//    copy, on its rows, and updates its registers.
+// columns l, l + 64 (CPL of them).  One barrier per reflection: the rank-2
+// update of reflection k-1 is applied at the start of step k, and column k
+// of the updated block is formed directly as x = c - w - w_k v from column
+// k as it stood before that update (c, written to LDS by the lanes that hold
+// it at the end of step k-1; the first entry of v_{k-1} is 1).  Step k:
+//  * the per-wave partial column sums of A v_{k-1} are added in the order
+//    w = 0, 1, ..., giving p = tau A v, p.v (wave sum) and
+//    w = p - (tau/2)(p.v) v on the lane's columns; the wave's own rows of w
+//    come back from a wave-private LDS copy;
+//  * x as above, ||x[k+2:]||^2 (wave sum), beta, tau_k and v_k on the lane's
+//    columns, and through a second private copy on the wave's rows;
+//  * the registers take A -= v w^T + w v^T of reflection k-1;
+//  * p = A v_k as column sums of the wave's rows (one partial row per wave
+//    to LDS), the lanes holding column k+1 write it; one barrier.
 // A wave whose RPW rows are all finished (<= k) writes zero partials and
-// skips the product and the update, so the block's work shrinks with k.
-// Rows and columns use the same v, built from column k (a mixed row/column
-// v loses the similarity once rounding makes the block slightly
-// asymmetric).  Same outputs as k_tridiag (dsytd2 order; v_k in row ksw+k,
-// columns ksw+k+1 ..; d, e, tau from ksw).
+// skips the rest, so the block's work shrinks with k.  Rows and columns use
+// the same v, built from column k.  Same outputs as k_tridiag (dsytd2
+// order; v_k in row ksw+k, columns ksw+k+1 ..; d, e, tau from ksw).
 constexpr int kRwWaves = 8;
 constexpr int kRwMax = 128;
+
+// value of x in lane `lane` (uniform over the wave) of the wave
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
 
 template <int CPL, int RPW>
 __global__ __launch_bounds__(kRwWaves * 64) void k_tridiag_rw(int32_t n, int32_t ksw, int32_t lda,
@@ -299,12 +308,14 @@ __global__ __launch_bounds__(kRwWaves * 64) void k_tridiag_rw(int32_t n, int32_t
   typedef double dbl2 __attribute__((ext_vector_type(2)));
   constexpr int NW = kRwWaves;
   constexpr int NC = 64 * CPL;  // largest n
-  __shared__ __attribute__((aligned(16))) double xcol[2][NC];      // column k
+  __shared__ __attribute__((aligned(16))) double xcol[2][NC];      // column k before the last update
   __shared__ __attribute__((aligned(16))) double part[2][NW][NC];  // per-wave partial column sums of A v
   __shared__ __attribute__((aligned(16))) double wv[NW][NC];       // wave-private w
+  __shared__ __attribute__((aligned(16))) double vv[NW][NC];       // wave-private v
   const int l = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int32_t r0 = w * RPW;
+  const int wlast = (n - 1) / RPW;  // holds row n - 1: active in every step
   double* Ab = A + (int64_t)ksw * lda + ksw;
 
   double a[RPW][CPL];
@@ -315,77 +326,127 @@ __global__ __launch_bounds__(kRwWaves * 64) void k_tridiag_rw(int32_t n, int32_t
       const int32_t i = r0 + q, j = l + 64 * c;
       a[q][c] = (i < n && j < n) ? Ab[(int64_t)i * lda + j] : 0.0;
     }
+  // the previous reflection: v on the lane's columns and the wave's rows, tau
+  double vc[CPL], vq[RPW];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) vc[c] = 0.0;
+#pragma unroll
+  for (int q = 0; q < RPW; ++q) vq[q] = 0.0;
+  double tkp = 0.0;
 
-  for (int32_t k = 0; k + 2 < n; ++k) {
-    const int buf = k & 1;
-    const int kc = k >> 6, kl = k & 63;
-    // a wave whose rows are all <= k (or past n) has nothing left to
-    // update; its row k, if it holds it, is still read once below
-    const bool has_k = r0 + RPW - 1 >= k && r0 < n;
-    const bool act = r0 + RPW - 1 > k && r0 < n;
-    if (has_k && l == kl) {  // this lane holds column k of the wave's rows
-      dbl2* dst = (dbl2*)&xcol[buf][r0];
-      if (kc == 0) {
+  // w = p - (tau/2)(p.v) v of the previous reflection (its partial sums in
+  // part[pb]) on the lane's columns (wc) and the wave's rows (wq), for the
+  // indices >= k; zero when there is none
+  auto finish = [&](int32_t k, int pb, double (&wc)[CPL], double (&wq)[RPW]) {
+    if (tkp != 0.0) {  // uniform over the block
+      double pc[CPL];
+      double pv = 0.0;
 #pragma unroll
-        for (int u = 0; u < RPW / 2; ++u) dst[u] = dbl2{a[2 * u][0], a[2 * u + 1][0]};
-      } else {
+      for (int c = 0; c < CPL; ++c) {
+        const int32_t j = l + 64 * c;
+        double pp[NW];
 #pragma unroll
-        for (int u = 0; u < RPW / 2; ++u) dst[u] = dbl2{a[2 * u][CPL - 1], a[2 * u + 1][CPL - 1]};
+        for (int u = 0; u < NW; ++u) pp[u] = part[pb][u][j];
+        const double sp = ((pp[0] + pp[1]) + (pp[2] + pp[3])) + ((pp[4] + pp[5]) + (pp[6] + pp[7]));
+        pc[c] = (j >= k && j < n) ? tkp * sp : 0.0;
+        pv = fma(pc[c], vc[c], pv);
       }
-    }
-    __syncthreads();
-
-    double xl[CPL];
-    double s = 0.0;
+      pv = wave_sum(pv);
+      const double gam = 0.5 * tkp * pv;
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const int32_t j = l + 64 * c;
-      xl[c] = xcol[buf][j];
-      s = fma(xl[c], (j >= k + 2 && j < n) ? xl[c] : 0.0, s);
-    }
-    // column k on the wave's own rows (broadcast reads, issued with the
-    // above; scaled once beta is known)
-    double xq[RPW];
-    if (act) {
-      const dbl2* src = (const dbl2*)&xcol[buf][r0];
+      for (int c = 0; c < CPL; ++c) {
+        wc[c] = pc[c] - gam * vc[c];
+        wv[w][l + 64 * c] = wc[c];
+      }
+      // LDS operations of one wave complete in order
+      __builtin_amdgcn_wave_barrier();
+      const dbl2* src = (const dbl2*)&wv[w][r0];
 #pragma unroll
       for (int u = 0; u < RPW / 2; ++u) {
         const dbl2 t = src[u];
-        xq[2 * u] = t[0];
-        xq[2 * u + 1] = t[1];
+        wq[2 * u] = t[0];
+        wq[2 * u + 1] = t[1];
       }
-    }
-    const double sigma = wave_sum(s);
-    const double alpha = xcol[buf][k + 1];
-    double beta, tk, scale;
-    if (sigma == 0.0) {
-      tk = 0.0;
-      beta = alpha;
-      scale = 0.0;
     } else {
-      beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-      tk = (beta - alpha) * recip(beta);
-      scale = recip(alpha - beta);
-    }
-    double vc[CPL];
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      const int32_t j = l + 64 * c;
-      vc[c] = (j == k + 1) ? 1.0 : ((j > k + 1 && j < n) ? xl[c] * scale : 0.0);
-      if (w == 0 && j > k && j < n) Ab[(int64_t)k * lda + j] = vc[c];  // v_k for the back-transformation
-    }
-    if (threadIdx.x == 0) {
-      d[ksw + k] = xcol[buf][k];
-      e[ksw + k] = beta;
-      tau[ksw + k] = tk;
-    }
-    double vq[RPW];
-    if (tk != 0.0) {  // uniform over the block
-      if (act) {
+      for (int c = 0; c < CPL; ++c) wc[c] = 0.0;
 #pragma unroll
-        for (int q = 0; q < RPW; ++q) {
-          const int32_t i = r0 + q;
-          vq[q] = (i == k + 1) ? 1.0 : ((i > k + 1 && i < n) ? xq[q] * scale : 0.0);
+      for (int q = 0; q < RPW; ++q) wq[q] = 0.0;
+    }
+  };
+  // A -= v w^T + w v^T with the previous reflection
+  auto update = [&](const double (&wc)[CPL], const double (&wq)[RPW]) {
+    if (tkp != 0.0) {
+#pragma unroll
+      for (int q = 0; q < RPW; ++q)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) a[q][c] = fma(-wq[q], vc[c], fma(-vq[q], wc[c], a[q][c]));
+    }
+  };
+
+  // column 0
+  if (l == 0 && r0 < n) {
+    dbl2* dst = (dbl2*)&xcol[0][r0];
+#pragma unroll
+    for (int u = 0; u < RPW / 2; ++u) dst[u] = dbl2{a[2 * u][0], a[2 * u + 1][0]};
+  }
+  __syncthreads();
+
+  // step k; SK and SK1 are the column slots of k and k + 1 (k >> 6 and
+  // (k + 1) >> 6), fixed per range of k so that no step selects between slots
+  auto step = [&](int32_t k, auto skt, auto sk1t) __attribute__((always_inline)) {
+    constexpr int SK = decltype(skt)::value, SK1 = decltype(sk1t)::value;
+    const int buf = k & 1;
+    if (r0 + RPW - 1 > k && r0 < n) {  // the wave holds rows > k
+      const int kl = k & 63, kl1 = (k + 1) & 63;
+      double wc[CPL], wq[RPW];
+      finish(k, buf ^ 1, wc, wq);
+      // column k after the previous reflection
+      const double wk = readlane_f64(wc[SK], kl);
+      double x[CPL];
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int32_t j = l + 64 * c;
+        x[c] = fma(-wk, vc[c], xcol[buf][j] - wc[c]);
+        s = fma(x[c], (j >= k + 2 && j < n) ? x[c] : 0.0, s);
+      }
+      const double sigma = wave_sum(s);
+      const double alpha = readlane_f64(x[SK1], kl1);
+      const double dk = readlane_f64(x[SK], kl);
+      update(wc, wq);
+      double beta, tk, scale;
+      if (sigma == 0.0) {
+        tk = 0.0;
+        beta = alpha;
+        scale = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+        tk = (beta - alpha) * recip(beta);
+        scale = recip(alpha - beta);
+      }
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int32_t j = l + 64 * c;
+        vc[c] = (j == k + 1) ? 1.0 : ((j > k + 1 && j < n) ? x[c] * scale : 0.0);
+        if (w == wlast && j > k && j < n) Ab[(int64_t)k * lda + j] = vc[c];  // v_k for the back-transformation
+      }
+      if (w == wlast && l == 0) {
+        d[ksw + k] = dk;
+        e[ksw + k] = beta;
+        tau[ksw + k] = tk;
+      }
+      tkp = tk;
+      if (tk != 0.0) {  // uniform over the block
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) vv[w][l + 64 * c] = vc[c];
+        __builtin_amdgcn_wave_barrier();
+        const dbl2* src = (const dbl2*)&vv[w][r0];
+#pragma unroll
+        for (int u = 0; u < RPW / 2; ++u) {
+          const dbl2 t = src[u];
+          vq[2 * u] = t[0];
+          vq[2 * u + 1] = t[1];
         }
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
@@ -394,51 +455,33 @@ __global__ __launch_bounds__(kRwWaves * 64) void k_tridiag_rw(int32_t n, int32_t
           for (int q = 0; q < RPW; ++q) p4[q & 3] = fma(a[q][c], vq[q], p4[q & 3]);
           part[buf][w][l + 64 * c] = (p4[0] + p4[1]) + (p4[2] + p4[3]);
         }
-      } else {
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) part[buf][w][l + 64 * c] = 0.0;
       }
+      // column k + 1 as it stands now (the lane holding it, the wave's rows)
+      if (k + 3 < n && l == kl1) {
+        double* dst = &xcol[buf ^ 1][r0];
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) dst[q] = a[q][SK1];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) part[buf][w][l + 64 * c] = 0.0;
     }
     __syncthreads();
-    if (tk != 0.0) {
-      double pc[CPL];
-      double pv = 0.0;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int32_t j = l + 64 * c;
-        double pp[NW];
-#pragma unroll
-        for (int u = 0; u < NW; ++u) pp[u] = part[buf][u][j];
-        const double sp = ((pp[0] + pp[1]) + (pp[2] + pp[3])) + ((pp[4] + pp[5]) + (pp[6] + pp[7]));
-        pc[c] = (j > k && j < n) ? tk * sp : 0.0;
-        pv = fma(pc[c], vc[c], pv);
-      }
-      pv = wave_sum(pv);
-      if (act) {
-        const double gam = 0.5 * tk * pv;
-        double wc[CPL];
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-          wc[c] = pc[c] - gam * vc[c];
-          wv[w][l + 64 * c] = wc[c];
-        }
-        // the wave's own rows of w come back from its private copy (LDS
-        // operations of one wave complete in order)
-        __builtin_amdgcn_wave_barrier();
-        const dbl2* src = (const dbl2*)&wv[w][r0];
-#pragma unroll
-        for (int u = 0; u < RPW / 2; ++u) {
-          const dbl2 t = src[u];
-#pragma unroll
-          for (int c = 0; c < CPL; ++c) {
-            a[2 * u][c] = a[2 * u][c] - vq[2 * u] * wc[c] - t[0] * vc[c];
-            a[2 * u + 1][c] = a[2 * u + 1][c] - vq[2 * u + 1] * wc[c] - t[1] * vc[c];
-          }
-        }
-      }
-    }
+  };
+  typedef std::integral_constant<int, 0> S0;
+  typedef std::integral_constant<int, CPL - 1> S1;
+  const int32_t kend = n - 2;  // steps k = 0 .. n - 3
+  int32_t k = 0;
+  for (; k < kend && k < 63; ++k) step(k, S0{}, S0{});
+  for (; k < kend && k < 64; ++k) step(k, S0{}, S1{});  // k = 63 (CPL = 2)
+  for (; k < kend; ++k) step(k, S1{}, S1{});
+  // the last reflection's update, then the last 2 x 2 block (or the single
+  // entry when n = 1)
+  if (n >= 3 && r0 + RPW - 1 >= n - 2 && r0 < n) {
+    double wc[CPL], wq[RPW];
+    finish(n - 2, (n - 3) & 1, wc, wq);
+    update(wc, wq);
   }
-  // the last 2 x 2 block (or the single entry when n = 1)
 #pragma unroll
   for (int q = 0; q < RPW; ++q)
 #pragma unroll
