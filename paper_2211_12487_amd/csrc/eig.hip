@@ -299,14 +299,23 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-template <int CPL, int RPW>
-__global__ __launch_bounds__(kRwWaves * 64) void k_tridiag_rw(int32_t n, int32_t ksw, int32_t lda,
+// fixed-order pairwise sum of the per-wave partials
+template <int NW>
+__device__ __forceinline__ double wave_parts_sum(const double (&p)[NW]) {
+  static_assert(NW == 4 || NW == 8, "four or eight waves");
+  if constexpr (NW == 4)
+    return (p[0] + p[1]) + (p[2] + p[3]);
+  else
+    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+}
+
+template <int CPL, int RPW, int NW = kRwWaves>
+__global__ __launch_bounds__(NW * 64) void k_tridiag_rw(int32_t n, int32_t ksw, int32_t lda,
                                                              double* __restrict__ A, double* __restrict__ d,
                                                              double* __restrict__ e, double* __restrict__ tau) {
   static_assert(CPL == 1 || CPL == 2, "one or two columns per lane");
-  static_assert(RPW % 2 == 0 && RPW * kRwWaves <= 64 * CPL, "rows per wave: even, within the columns");
+  static_assert(RPW % 2 == 0 && RPW * NW <= 64 * CPL, "rows per wave: even, within the columns");
   typedef double dbl2 __attribute__((ext_vector_type(2)));
-  constexpr int NW = kRwWaves;
   constexpr int NC = 64 * CPL;  // largest n
   __shared__ __attribute__((aligned(16))) double xcol[2][NC];      // column k before the last update
   __shared__ __attribute__((aligned(16))) double part[2][NW][NC];  // per-wave partial column sums of A v
@@ -347,7 +356,7 @@ __global__ __launch_bounds__(kRwWaves * 64) void k_tridiag_rw(int32_t n, int32_t
         double pp[NW];
 #pragma unroll
         for (int u = 0; u < NW; ++u) pp[u] = part[pb][u][j];
-        const double sp = ((pp[0] + pp[1]) + (pp[2] + pp[3])) + ((pp[4] + pp[5]) + (pp[6] + pp[7]));
+        const double sp = wave_parts_sum<NW>(pp);
         pc[c] = (j >= k && j < n) ? tkp * sp : 0.0;
         pv = fma(pc[c], vc[c], pv);
       }
@@ -631,8 +640,68 @@ size_t tridiag_lds_bytes(int32_t m) {
 constexpr int kSect = 256;
 constexpr int kBisectRounds = 7;
 
+// The truncation rank from all m eigenvalues w (RankSelect), by one
+// workgroup: w staged in LDS (sw, m doubles), each eigenvalue's rank in
+// decreasing order counted against all others (ties by index), then the
+// suffix sums of the clamped values from the end (sl, m + 1 doubles) and the
+// first rank whose tail is within tol2.
+__device__ void select_rank_block(int32_t m, const double* w, const RankSelect& sel, double* sw, double* sl) {
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  __syncthreads();
+  for (int32_t i = t; i < m; i += blockDim.x) {
+    const double wi = w[i];
+    sw[i] = wi;
+    if (!isfinite(wi)) bad = 1;
+  }
+  __syncthreads();
+  for (int32_t i = t; i < m; i += blockDim.x) {
+    const double wi = sw[i];
+    int32_t r = 0;
+    for (int32_t j = 0; j < m; ++j) {
+      const double wj = sw[j];
+      r += (wj > wi) || (wj == wi && j < i);
+    }
+    const double li = wi > 0.0 ? wi : 0.0;
+    sel.order[r] = i;
+    sel.lam[r] = li;
+    sl[r] = li;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double acc = 0.0;
+    sel.tail[m] = 0.0;
+    for (int32_t r = m - 1; r >= 0; --r) {
+      acc = acc + sl[r];
+      sl[r] = acc;
+      sel.tail[r] = acc;
+    }
+    sl[m] = 0.0;
+    int32_t rr = m;
+    for (int32_t r = 0; r <= m; ++r)
+      if (sl[r] <= sel.tol2) {
+        rr = r;
+        break;
+      }
+    if ((int64_t)rr > sel.cap) rr = (int32_t)sel.cap;
+    const double t2 = sel.tol2 > 0.0 ? sel.tol2 : 1e-300;
+    double margin = fabs(sl[rr] - sel.tol2) / t2;
+    if (rr >= 1) margin = fmin(margin, fabs(sl[rr - 1] - sel.tol2) / t2);
+    sel.res[0] = (double)rr;
+    sel.res[1] = sl[rr];
+    sel.res[2] = margin;
+    sel.res[3] = bad ? 1.0 : 0.0;
+  }
+}
+
+// Eigenvalue blockIdx.x (decreasing order) by Sturm multisection; with a
+// RankSelect, the last workgroup to finish (arrival counter sel.cnt) then
+// selects the truncation rank from all of them and clears the counter.
+// Dynamic LDS: 2m + 1 doubles.
 __global__ __launch_bounds__(256) void k_bisect(int32_t m, const double* __restrict__ d,
-                                                const double* __restrict__ e, double* __restrict__ w) {
+                                                const double* __restrict__ e, double* __restrict__ w,
+                                                RankSelect sel) {
   HIP_DYNAMIC_SHARED(double, lds);
   __shared__ double rlo[4], rhi[4], remax[4];
   double* dS = lds;
@@ -693,6 +762,17 @@ __global__ __launch_bounds__(256) void k_bisect(int32_t m, const double* __restr
     hi = nhi;
   }
   if (t == 0) w[j] = 0.5 * (lo + hi);
+  if (sel.cnt == nullptr) return;
+  __shared__ int last;
+  if (t == 0) {
+    __threadfence();  // w[j] is visible before the arrival is counted
+    last = atomicAdd(sel.cnt, 1) == m - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  select_rank_block(m, w, sel, lds, lds + m);
+  if (t == 0) *sel.cnt = 0;
 }
 
 // LU with partial pivoting of T - lc I (tridiagonal, LAPACK gttrf order)
@@ -1020,7 +1100,8 @@ hipError_t set_lds_attr(const void* f) {
 int32_t sym_eig_max() { return kEigMax; }
 
 hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* w,
-                       double* ws) {
+                       double* ws, const RankSelect* sel) {
+  if (sel != nullptr && (m <= 0 || sel->cnt == nullptr)) return hipErrorInvalidValue;
   if (m <= 0) return hipSuccess;
   if (m > kEigMax) return hipErrorInvalidValue;
   // once per process (thread-safe static initialisation)
@@ -1064,7 +1145,8 @@ hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* 
   }
   hipError_t er = hipGetLastError();
   if (er != hipSuccess) return er;
-  hipLaunchKernelGGL(k_bisect, dim3(m), dim3(kSect), (size_t)2 * m * sizeof(double), st, m, d, e, w);
+  hipLaunchKernelGGL(k_bisect, dim3(m), dim3(kSect), (size_t)(2 * m + 1) * sizeof(double), st, m, d, e, w,
+                     sel != nullptr ? *sel : RankSelect());
   return hipGetLastError();
 }
 

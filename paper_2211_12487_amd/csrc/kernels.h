@@ -135,14 +135,33 @@ hipError_t accumulate(hipStream_t st, double* acc, const double* x, int64_t n);
 // (slice stride m*m), mirrored to be exactly symmetric.
 hipError_t gram_reduce(hipStream_t st, const double* part, int32_t S, int32_t m, double* G);
 
+// Rank selection for SVD(R, eps) from the eigenvalues w (m) of the residual's
+// Gram matrix (eq:deltasvd / eq:svdfirst): order[t] = index of the t-th
+// largest eigenvalue, lam[t] its value clamped to >= 0; tail[r] =
+// sum_{t>=r} lam[t] (m + 1 entries); r_R = smallest r with tail[r] <= tol2,
+// clipped to cap.  res[0] = r_R, res[1] = tail[r_R], res[2] = margin,
+// res[3] = 1 if any eigenvalue was not finite.  cnt: one int of device
+// memory that is zero on entry and is left zero (the arrival counter of the
+// eigenvalue workgroups).
+struct RankSelect {
+  int* cnt = nullptr;
+  double tol2 = 0.0;
+  int64_t cap = 0;
+  int32_t* order = nullptr;
+  double* lam = nullptr;
+  double* tail = nullptr;
+  double* res = nullptr;
+};
+
 // Eigenvalues of the symmetric m x m matrix A (row-major, ld = m, m <=
 // sym_eig_max()): A is reduced in place to tridiagonal form T = Q^T A Q (d, e;
 // reflectors kept in A's rows and tau; d, e, tau: m doubles each) and w
 // receives all eigenvalues in decreasing order.
 // ws: sym_eig_ws(m) doubles of device workspace, or null (then every
-// reflection runs in one workgroup).
+// reflection runs in one workgroup).  sel (optional, m >= 1): the rank
+// selection above, run by the last eigenvalue workgroup to finish.
 hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* w,
-                       double* ws);
+                       double* ws, const RankSelect* sel = nullptr);
 inline int64_t sym_eig_ws(int32_t m) { return 2 * (int64_t)m + 256; }
 inline int64_t sym_eigvecs_ws(int32_t m, int32_t r) { return (7 * (int64_t)m + 1) * r; }
 // Eigenvectors of A for its r largest eigenvalues lam[0..r) (from
@@ -152,21 +171,16 @@ hipError_t sym_eigvecs(hipStream_t st, int32_t m, int32_t r, const double* d, co
                        const double* lam, const double* A, const double* tau, double* ws, double* X);
 int32_t sym_eig_max();
 
-// Rank selection for SVD(R, eps) from the eigenvalues w (m) of the residual's
-// Gram matrix: order[t] = index of the t-th largest eigenvalue, lam[t] its
-// value clamped to >= 0; tail[r] = sum_{t>=r} lam[t]; r_R = smallest r with
-// tail[r] <= tol2, clipped to cap.  res[0] = r_R, res[1] = tail[r_R],
-// res[2] = margin, res[3] = 1 if any eigenvalue was not finite.
-hipError_t select_rank(hipStream_t st, int32_t m, const double* w, double tol2, int64_t cap,
-                       int32_t* order, double* lam, double* tail, double* res);
-
 // W (rows x r, ld = r) = V[:, order[t]] (left case)  or
 // Vs (M x r, ld = r) = V[:, order[t]] / sqrt(lam[t]) (right case, scale = true)
 hipError_t gather_columns(hipStream_t st, int32_t rows, int32_t r, const double* V, int32_t ldv,
                           const int32_t* order, const double* lam, bool scale, double* W);
-// Flip each column of W (rows x r, ld) so its largest-|.| entry (lowest row
-// index on ties) is positive.
-hipError_t sign_fix(hipStream_t st, int32_t rows, int32_t r, double* W, int64_t ld);
+// dst(:, t) = s_t W(:, t) for the r columns of W (rows x r, ld = r), s_t = +-1
+// making the column's largest-|.| entry (lowest row index on ties)
+// positive; in the same launch, zero the zrows x zcols region at zdst (ld
+// zld; none when zdst is null).
+hipError_t sign_place(hipStream_t st, int32_t rows, int32_t r, const double* W, double* dst, int64_t ldd,
+                      double* zdst, int64_t zrows, int64_t zcols, int64_t zld);
 // dst(i, j) = src(i, j) for i < rows, j < cols (both row-major)
 hipError_t copy2d(hipStream_t st, int64_t rows, int64_t cols, const double* src, int64_t lds,
                   double* dst, int64_t ldd);

@@ -447,50 +447,6 @@ __global__ void k_gram_reduce(const double* __restrict__ part, int32_t S, int32_
   G[idx] = s;
 }
 
-// ---------------------------------------------------------------------------
-// Truncation rank from the Gram eigenvalues (eq:deltasvd / eq:svdfirst)
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_select_rank(int32_t m, const double* __restrict__ w,
-                                                      double tol2, int64_t cap,
-                                                      int32_t* __restrict__ order,
-                                                      double* __restrict__ lam,
-                                                      double* __restrict__ tail,
-                                                      double* __restrict__ res) {
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int32_t i = threadIdx.x; i < m; i += blockDim.x) {
-    const double wi = w[i];
-    if (!isfinite(wi)) bad = 1;
-    int32_t r = 0;
-    for (int32_t j = 0; j < m; ++j) {
-      const double wj = w[j];
-      r += (wj > wi) || (wj == wi && j < i);
-    }
-    order[r] = i;
-    lam[r] = wi > 0.0 ? wi : 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    tail[m] = 0.0;
-    for (int32_t r = m - 1; r >= 0; --r) tail[r] = tail[r + 1] + lam[r];
-    int32_t rr = m;
-    for (int32_t r = 0; r <= m; ++r)
-      if (tail[r] <= tol2) {
-        rr = r;
-        break;
-      }
-    if ((int64_t)rr > cap) rr = (int32_t)cap;
-    const double t2 = tol2 > 0.0 ? tol2 : 1e-300;
-    double margin = fabs(tail[rr] - tol2) / t2;
-    if (rr >= 1) margin = fmin(margin, fabs(tail[rr - 1] - tol2) / t2);
-    res[0] = (double)rr;
-    res[1] = tail[rr];
-    res[2] = margin;
-    res[3] = bad ? 1.0 : 0.0;
-  }
-}
-
 __global__ void k_gather_columns(int32_t rows, int32_t r, const double* __restrict__ V, int32_t ldv,
                                  const int32_t* __restrict__ order, const double* __restrict__ lam,
                                  int32_t scale, double* __restrict__ W) {
@@ -502,14 +458,30 @@ __global__ void k_gather_columns(int32_t rows, int32_t r, const double* __restri
   W[e] = v;
 }
 
-__global__ __launch_bounds__(256) void k_sign_fix(int32_t rows, double* __restrict__ W, int64_t ld) {
+// Blocks 0 .. r-1: column t of W (rows x r, ld = r) times the sign that
+// makes its largest-|.| entry (lowest row on ties) positive, written to
+// column t of dst (ld ldd).  Blocks from r: zero the zrows x zcols region at
+// zdst (ld zld), grid-stride.
+__global__ __launch_bounds__(256) void k_sign_place(int32_t rows, int32_t r, const double* __restrict__ W,
+                                                    double* __restrict__ dst, int64_t ldd,
+                                                    double* __restrict__ zdst, int64_t zrows, int64_t zcols,
+                                                    int64_t zld) {
+  if ((int32_t)blockIdx.x >= r) {
+    const int64_t nz = zrows * zcols;
+    const int64_t stride = (int64_t)(gridDim.x - r) * blockDim.x;
+    for (int64_t e = (int64_t)(blockIdx.x - r) * blockDim.x + threadIdx.x; e < nz; e += stride) {
+      const int64_t i = e / zcols, j = e - i * zcols;
+      zdst[i * zld + j] = 0.0;
+    }
+    return;
+  }
   __shared__ double bv[256];
   __shared__ int32_t bi[256];
   const int32_t col = blockIdx.x;
   double best = -1.0;
   int32_t bidx = 0x7fffffff;
   for (int32_t i = threadIdx.x; i < rows; i += 256) {
-    const double a = fabs(W[(int64_t)i * ld + col]);
+    const double a = fabs(W[(int64_t)i * r + col]);
     if (a > best || (a == best && i < bidx)) {
       best = a;
       bidx = i;
@@ -530,10 +502,11 @@ __global__ __launch_bounds__(256) void k_sign_fix(int32_t rows, double* __restri
     __syncthreads();
   }
   const int32_t k = bi[0];
-  const bool flip = (k < rows) && (W[(int64_t)k * ld + col] < 0.0);
-  __syncthreads();
-  if (flip)
-    for (int32_t i = threadIdx.x; i < rows; i += 256) W[(int64_t)i * ld + col] = -W[(int64_t)i * ld + col];
+  const bool flip = (k < rows) && (W[(int64_t)k * r + col] < 0.0);
+  for (int32_t i = threadIdx.x; i < rows; i += 256) {
+    const double v = W[(int64_t)i * r + col];
+    dst[(int64_t)i * ldd + col] = flip ? -v : v;
+  }
 }
 
 __global__ void k_copy2d(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
@@ -702,12 +675,6 @@ hipError_t gram_reduce(hipStream_t st, const double* part, int32_t S, int32_t m,
   return hipGetLastError();
 }
 
-hipError_t select_rank(hipStream_t st, int32_t m, const double* w, double tol2, int64_t cap,
-                       int32_t* order, double* lam, double* tail, double* res) {
-  hipLaunchKernelGGL(k_select_rank, dim3(1), dim3(1024), 0, st, m, w, tol2, cap, order, lam, tail, res);
-  return hipGetLastError();
-}
-
 hipError_t gather_columns(hipStream_t st, int32_t rows, int32_t r, const double* V, int32_t ldv,
                           const int32_t* order, const double* lam, bool scale, double* W) {
   const int64_t n = (int64_t)rows * r;
@@ -717,9 +684,13 @@ hipError_t gather_columns(hipStream_t st, int32_t rows, int32_t r, const double*
   return hipGetLastError();
 }
 
-hipError_t sign_fix(hipStream_t st, int32_t rows, int32_t r, double* W, int64_t ld) {
-  if (r <= 0 || rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sign_fix, dim3(r), dim3(256), 0, st, rows, W, ld);
+hipError_t sign_place(hipStream_t st, int32_t rows, int32_t r, const double* W, double* dst, int64_t ldd,
+                      double* zdst, int64_t zrows, int64_t zcols, int64_t zld) {
+  const int64_t nz = (zdst != nullptr && zrows > 0 && zcols > 0) ? zrows * zcols : 0;
+  const int64_t zb = std::min<int64_t>(nblocks(nz, 256), 256);
+  if (r <= 0 && zb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sign_place, dim3((unsigned)(std::max(r, 0) + zb)), dim3(256), 0, st, rows, std::max(r, 0),
+                     W, dst, ldd, zdst, nz > 0 ? zrows : 0, nz > 0 ? zcols : 0, zld);
   return hipGetLastError();
 }
 

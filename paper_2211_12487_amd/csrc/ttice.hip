@@ -454,10 +454,16 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
                                          m * m, nullptr, nullptr, gws())));
         CK(gram_reduce(st, as<double>(gpart), (int32_t)Sg, (int32_t)m, as<double>(gram)));
         if (m > sym_eig_max()) return TTICE_EINVAL;  // documented size limit of the residual's SVD
-        CK(sym_eigvals(st, (int32_t)m, as<double>(gram), dd, ee, tauv, wv, dd + 4 * m));
-        const int64_t cap = rows - r;
-        CK(select_rank(st, (int32_t)m, wv, tol2, cap, as<int32_t>(order), as<double>(lam),
-                       as<double>(tail), hs));
+        // eigenvalues, then the truncation rank (eq:deltasvd) from them
+        RankSelect sel;
+        sel.cnt = as<int>(tilecnt);  // zero between kernels (the product kernels clear theirs)
+        sel.tol2 = tol2;
+        sel.cap = rows - r;
+        sel.order = as<int32_t>(order);
+        sel.lam = as<double>(lam);
+        sel.tail = as<double>(tail);
+        sel.res = hs;
+        CK(sym_eigvals(st, (int32_t)m, as<double>(gram), dd, ee, tauv, wv, dd + 4 * m, &sel));
         CKS(sync_scalars(4));
         if (hs[3] != 0.0) return TTICE_EDEVICE;
         rR = (int64_t)hs[0];
@@ -508,29 +514,36 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
                                              nullptr, gws())));
             std::swap(Wp, W2p);
           }
-          CK(sign_fix(st, (int32_t)rows, (int32_t)rR, Wp, rR));
-
-          // eq:coreexpansion: U_i <- [U_i^pad, U_R]
+          // eq:coreexpansion: U_i <- [U_i^pad, U_R] (U_R's columns sign-fixed on
+          // the way), and in the same launch the zero padding below
           CKS(grow_core(Ui, rows, r + rR, rows, r));
-          CK(copy2d(st, rows, rR, Wp, rR, Ui.p + r, Ui.ld));
+          double* zp = nullptr;
+          int64_t zr = 0, zc = 0, zl = 0;
           // eq:ukpad: zero rows for the new rank slices of the next core
           if (!last) {
             Core& Un = U[i + 1];
             const int64_t nrow_old = rk_pend[i + 1] * dims[i + 1];
             const int64_t nrow_new = (rk_pend[i + 1] + rR) * dims[i + 1];
             CKS(grow_core(Un, nrow_new, std::max<int64_t>(rk_pend[i + 2], 1), nrow_old, rk_pend[i + 2]));
-            CK(zero2d(st, nrow_new - nrow_old, Un.ld, Un.p + nrow_old * Un.ld, Un.ld));
+            zp = Un.p + nrow_old * Un.ld;
+            zr = nrow_new - nrow_old;
+            zc = Un.ld;
+            zl = Un.ld;
           } else {
             // last core: new entries of the stored tensors' columns are zero
             if (!last_out) {
               CKS(grow_core(Gt, n_total + N, r + rR, n_total + N, r));
               out = Gt.p + n_total * Gt.ld;
               fs_out = Gt.ld;
-              CK(zero2d(st, n_total, rR, Gt.p + r, Gt.ld));
+              zp = Gt.p + r;
+              zr = n_total;
+              zc = rR;
+              zl = Gt.ld;
             } else if (r + rR > last_ld) {
               return TTICE_EDEVICE;  // caller sized last_out for the maximum rank
             }
           }
+          CK(sign_place(st, (int32_t)rows, (int32_t)rR, Wp, Ui.p + r, Ui.ld, zp, zr, zc, zl));
           // New rows of the next level's data (eq:project_further with the
           // appended directions): U_R^T Z below C.
           // (U_i may have been reallocated with a new leading dimension)
