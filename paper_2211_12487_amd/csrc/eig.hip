@@ -945,6 +945,74 @@ __device__ void back_transform_chunk(int32_t m, int32_t r, int32_t klo, int32_t 
   }
 }
 
+// x from the lane CTRL names (DPP) in each of the two halves of a double
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over each aligned group of G = 8 or 16 lanes: lane pairs (l, l^1),
+// (l, l^2), then the half-row and row mirrors; every lane of a group ends
+// with the same bits (each step adds the same two values in both lanes).
+template <int G>
+__device__ __forceinline__ double group_sum(double x) {
+  static_assert(G == 8 || G == 16, "groups of 8 or 16 lanes");
+  x = x + dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x = x + dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  x = x + dpp_f64<0x141>(x);  // row_half_mirror
+  if constexpr (G == 16) x = x + dpp_f64<0x140>(x);  // row_mirror
+  return x;
+}
+
+// The same reflectors applied to 64 / G columns per wave: a group of G lanes
+// holds one column (lane p of the group: y[p + G j], YR of them), so each
+// reflector's dot product is a G-lane sum and all of a wave's columns move
+// together (for r well above the wave count).  Waves without a column skip.
+template <int G, int YR>
+__device__ void back_transform_group(int32_t m, int32_t r, int32_t klo, int32_t khi, const double* refl,
+                                     const double* __restrict__ tau, double* Y) {
+  constexpr int CPW = 64 / G;
+  const int t = threadIdx.x, l = t & 63, p = l % G, g = l / G;
+  const int w = t >> 6;
+  for (int32_t c0 = 0; c0 < r; c0 += kWaves * CPW) {
+    if (c0 + w * CPW >= r) continue;  // uniform over the wave
+    const int32_t c = c0 + w * CPW + g;
+    const bool live = c < r;
+    double* yc = Y + (int64_t)(live ? c : 0) * m;
+    double y[YR];
+#pragma unroll
+    for (int j = 0; j < YR; ++j) {
+      const int32_t a = p + G * j;
+      y[j] = (live && a < m) ? yc[a] : 0.0;
+    }
+    for (int32_t k = khi; k >= klo; --k) {
+      const double tk = tau[k];
+      const int64_t off = refl_offset(m, klo, k) - (k + 1);  // refl[off + a] = v_k[a], a > k
+      double v[YR];
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < YR; ++j) {
+        const int32_t a = p + G * j;
+        const bool in = a > k && a < m;
+        const double x = refl[off + (in ? a : k + 1)];
+        v[j] = in ? x : 0.0;
+        acc[j & 3] = fma(v[j], y[j], acc[j & 3]);
+      }
+      const double f = tk * group_sum<G>((acc[0] + acc[1]) + (acc[2] + acc[3]));
+#pragma unroll
+      for (int j = 0; j < YR; ++j) y[j] = fma(-f, v[j], y[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < YR; ++j) {
+      const int32_t a = p + G * j;
+      if (live && a < m) yc[a] = y[j];
+    }
+  }
+}
+
 // Eigenvectors of T for the r largest eigenvalues lam[0..r) (decreasing) by
 // inverse iteration, back-transformed x = Q y with the reflectors kept in A's
 // rows.  Every vector starts on its own thread (LU + three solves from a
@@ -1065,10 +1133,16 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
     // one wave per column, all reflectors of the chunk without a barrier:
     // lane l always handles the indices a = l (mod 64), so no value passes
     // between lanes through memory
-    if (m <= 128)
+    if (m <= 128 && r <= kWaves)
       back_transform_chunk<2>(m, r, klo, khi, refl, tau, Y);
-    else if (m <= 256)
+    else if (m <= 128 && r <= 4 * kWaves)
+      back_transform_group<16, 8>(m, r, klo, khi, refl, tau, Y);
+    else if (m <= 128)
+      back_transform_group<8, 16>(m, r, klo, khi, refl, tau, Y);
+    else if (m <= 256 && r <= kWaves)
       back_transform_chunk<4>(m, r, klo, khi, refl, tau, Y);
+    else if (m <= 256)
+      back_transform_group<16, 16>(m, r, klo, khi, refl, tau, Y);
     else
       for (int32_t c = t >> 6; c < r; c += kWaves) {
         double* yc = Y + (int64_t)c * m;

@@ -442,8 +442,17 @@ __global__ void k_gram_reduce(const double* __restrict__ part, int32_t S, int32_
   const int32_t p = (int32_t)(idx / m), q = (int32_t)(idx - (int64_t)p * m);
   const int32_t a = min(p, q), b = max(p, q);
   const int64_t src = (int64_t)a * m + b;
+  // slices in the order z = 0, 1, ..., eight loads in flight
   double s = 0.0;
-  for (int32_t z = 0; z < S; ++z) s += part[z * mm + src];
+  int32_t z = 0;
+  for (; z + 8 <= S; z += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(z + u) * mm + src];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; z < S; ++z) s += part[(int64_t)z * mm + src];
   G[idx] = s;
 }
 

@@ -257,7 +257,7 @@ constexpr int64_t kFusedMinCols = 8192;
 int32_t gram_kchunk(int32_t m, int64_t K) {
   const int64_t tiles = (int64_t)((m + 63) / 64) * ((m + 63) / 64);
   int64_t S = std::max<int64_t>(1, 512 / std::max<int64_t>(tiles, 1));
-  S = std::min<int64_t>(S, std::max<int64_t>(1, K / 256));
+  S = std::min<int64_t>(S, std::max<int64_t>(1, K / 64));
   int64_t chunk = (K + S - 1) / S;
   chunk = ((chunk + 15) / 16) * 16;
   return (int32_t)std::max<int64_t>(chunk, 16);

@@ -252,6 +252,18 @@ def case_eigensolver():
         assert np.abs(w - ev).max() <= 1e-13 * ev[0], m
         for c in range(X.shape[1]):
             assert min(np.linalg.norm(X[:, c] - EV[:, c]), np.linalg.norm(X[:, c] + EV[:, c])) <= 1e-10, (m, c)
+    # many kept vectors (the back-transformation with several columns per
+    # wave): separated spectrum, every vector against LAPACK's
+    for m, r in ((40, 12), (96, 40), (128, 70), (200, 40)):
+        Q, _ = np.linalg.qr(rng.standard_normal((m, m)))
+        lam = np.linspace(10.0, 1.0, m)
+        G = (Q * lam) @ Q.T
+        w, X = run(G, r)
+        assert np.abs(w - lam).max() <= 1e-13 * 10.0, m
+        for c in range(r):
+            q = Q[:, c]
+            assert min(np.linalg.norm(X[:, c] - q), np.linalg.norm(X[:, c] + q)) <= 1e-10, (m, r, c)
+        assert np.abs(X.T @ X - np.eye(r)).max() <= 1e-12, (m, r)
     # clustered spectrum: compare the kept subspace through its projector
     for m in (12, 140):
         Q, _ = np.linalg.qr(rng.standard_normal((m, m)))

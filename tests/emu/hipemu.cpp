@@ -153,15 +153,17 @@ double shfl_xor(double v, int mask) {
 }
 
 double quad_perm(double v, int ctrl) {
-  if (ctrl < 0 || ctrl >= 0x100) {
-    fprintf(stderr, "hipemu: only DPP quad permutations are emulated\n");
+  if (ctrl < 0 || (ctrl >= 0x100 && ctrl != 0x140 && ctrl != 0x141)) {
+    fprintf(stderr, "hipemu: only DPP quad permutations and row (half) mirrors are emulated\n");
     abort();
   }
   const unsigned tid = cur;
   shfl_buf[tid] = v;
   wave_barrier();
   const unsigned l = tid & 3u;
-  const unsigned src = (tid & ~3u) | ((unsigned)(ctrl >> (2 * l)) & 3u);
+  unsigned src = (tid & ~3u) | ((unsigned)(ctrl >> (2 * l)) & 3u);
+  if (ctrl == 0x140) src = (tid & ~15u) | (15u - (tid & 15u));  // row_mirror
+  if (ctrl == 0x141) src = (tid & ~7u) | (7u - (tid & 7u));     // row_half_mirror
   const double r = src < nthreads ? shfl_buf[src] : v;
   wave_barrier();
   return r;

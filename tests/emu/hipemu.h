@@ -91,8 +91,9 @@ inline int __builtin_amdgcn_readfirstlane(int x) { return x; }
 inline void __builtin_amdgcn_wave_barrier() { hipemu::wave_sync(); }
 // value of x in lane `lane` of the wave (lane uniform over the wave)
 inline int __builtin_amdgcn_readlane(int x, int lane) { return hipemu::readlane(x, lane); }
-// DPP move, quad permutations only (dpp_ctrl < 0x100): lane reads lane
-// 4*(l/4) + ((ctrl >> 2*(l%4)) & 3) of its wave
+// DPP move: quad permutations (dpp_ctrl < 0x100, lane reads lane
+// 4*(l/4) + ((ctrl >> 2*(l%4)) & 3) of its wave), row_mirror (0x140) and
+// row_half_mirror (0x141)
 inline int __builtin_amdgcn_mov_dpp(int src, int ctrl, int, int, bool) {
   return (int)hipemu::quad_perm((double)src, ctrl);
 }
