@@ -1115,7 +1115,9 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
     }
   }
   // back-transformation x = H_0 H_1 ... H_{m-3} y, reflectors klo..khi
-  // staged in LDS per chunk
+  // staged in LDS per chunk; tau goes to LDS too (dS is free from here on)
+  for (int32_t i = t; i < m; i += kTriThreads) dS[i] = tau[i];
+  const double* tauS = dS;
   int32_t khi = m - 3;
   while (khi >= 0) {
     int32_t klo = khi;
@@ -1124,30 +1126,60 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
       --klo;
       used += m - klo - 1;
     }
-    for (int32_t k = klo; k <= khi; ++k) {
-      const int64_t off = refl_offset(m, klo, k);
-      const int32_t L = m - k - 1;
-      for (int32_t i = t; i < L; i += kTriThreads) refl[off + i] = A[(int64_t)k * m + k + 1 + i];
+    if (m <= 256) {
+      // wave w stages rows klo + w, klo + w + 8, ... four at a time, lane l
+      // the entries l, l + 64, ..: all sixteen loads are issued before the
+      // first store
+      const int l = t & 63;
+      for (int32_t k0 = klo + (t >> 6); k0 <= khi; k0 += 4 * kWaves) {
+        double v[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t k = k0 + u * kWaves;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int32_t i = l + 64 * j;
+            v[u][j] = (k <= khi && i < m - k - 1) ? A[(int64_t)k * m + k + 1 + i] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t k = k0 + u * kWaves;
+          if (k > khi) continue;
+          const int64_t off = refl_offset(m, klo, k);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int32_t i = l + 64 * j;
+            if (i < m - k - 1) refl[off + i] = v[u][j];
+          }
+        }
+      }
+    } else {
+      for (int32_t k = klo; k <= khi; ++k) {
+        const int64_t off = refl_offset(m, klo, k);
+        const int32_t L = m - k - 1;
+        for (int32_t i = t; i < L; i += kTriThreads) refl[off + i] = A[(int64_t)k * m + k + 1 + i];
+      }
     }
     __syncthreads();
     // one wave per column, all reflectors of the chunk without a barrier:
     // lane l always handles the indices a = l (mod 64), so no value passes
     // between lanes through memory
     if (m <= 128 && r <= kWaves)
-      back_transform_chunk<2>(m, r, klo, khi, refl, tau, Y);
+      back_transform_chunk<2>(m, r, klo, khi, refl, tauS, Y);
     else if (m <= 128 && r <= 4 * kWaves)
-      back_transform_group<16, 8>(m, r, klo, khi, refl, tau, Y);
+      back_transform_group<16, 8>(m, r, klo, khi, refl, tauS, Y);
     else if (m <= 128)
-      back_transform_group<8, 16>(m, r, klo, khi, refl, tau, Y);
+      back_transform_group<8, 16>(m, r, klo, khi, refl, tauS, Y);
     else if (m <= 256 && r <= kWaves)
-      back_transform_chunk<4>(m, r, klo, khi, refl, tau, Y);
+      back_transform_chunk<4>(m, r, klo, khi, refl, tauS, Y);
     else if (m <= 256)
-      back_transform_group<16, 16>(m, r, klo, khi, refl, tau, Y);
+      back_transform_group<16, 16>(m, r, klo, khi, refl, tauS, Y);
     else
       for (int32_t c = t >> 6; c < r; c += kWaves) {
         double* yc = Y + (int64_t)c * m;
         for (int32_t k = khi; k >= klo; --k) {
-          const double tk = tau[k];
+          const double tk = tauS[k];
           if (tk == 0.0) continue;
           const int64_t off = refl_offset(m, klo, k) - (k + 1);  // refl[off + a] = v_k[a], a > k
           double acc = 0.0;

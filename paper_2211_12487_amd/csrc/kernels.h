@@ -181,9 +181,6 @@ hipError_t gather_columns(hipStream_t st, int32_t rows, int32_t r, const double*
 // zld; none when zdst is null).
 hipError_t sign_place(hipStream_t st, int32_t rows, int32_t r, const double* W, double* dst, int64_t ldd,
                       double* zdst, int64_t zrows, int64_t zcols, int64_t zld);
-// dst(i, j) = src(i, j) for i < rows, j < cols (both row-major)
-hipError_t copy2d(hipStream_t st, int64_t rows, int64_t cols, const double* src, int64_t lds,
-                  double* dst, int64_t ldd);
 // dst(i, j) = 0 for i < rows, j < cols
 hipError_t zero2d(hipStream_t st, int64_t rows, int64_t cols, double* dst, int64_t ldd);
 

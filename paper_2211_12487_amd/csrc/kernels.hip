@@ -518,14 +518,6 @@ __global__ __launch_bounds__(256) void k_sign_place(int32_t rows, int32_t r, con
   }
 }
 
-__global__ void k_copy2d(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds,
-                         double* __restrict__ dst, int64_t ldd) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= rows * cols) return;
-  const int64_t i = e / cols, j = e - i * cols;
-  dst[i * ldd + j] = src[i * lds + j];
-}
-
 __global__ void k_zero2d(int64_t rows, int64_t cols, double* __restrict__ dst, int64_t ldd) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= rows * cols) return;
@@ -700,14 +692,6 @@ hipError_t sign_place(hipStream_t st, int32_t rows, int32_t r, const double* W, 
   if (r <= 0 && zb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_sign_place, dim3((unsigned)(std::max(r, 0) + zb)), dim3(256), 0, st, rows, std::max(r, 0),
                      W, dst, ldd, zdst, nz > 0 ? zrows : 0, nz > 0 ? zcols : 0, zld);
-  return hipGetLastError();
-}
-
-hipError_t copy2d(hipStream_t st, int64_t rows, int64_t cols, const double* src, int64_t lds,
-                  double* dst, int64_t ldd) {
-  const int64_t n = rows * cols;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy2d, dim3(nblocks(n, 256)), dim3(256), 0, st, rows, cols, src, lds, dst, ldd);
   return hipGetLastError();
 }
 
