@@ -852,28 +852,33 @@ __device__ void tri_solve(int32_t m, const double* __restrict__ DL, const double
 // D-_i = (a_i - lc) - e_i^2 / D-_{i+1} (tiny pivots become +-pert), the
 // twist k minimising |gamma_k| with gamma_k = D+_k + D-_k - (a_k - lc), and
 // then z_k = 1, z_i = -(e_i / D+_i) z_{i+1} above k and
-// z_i = -(e_{i-1} / D-_i) z_{i-1} below it: three serial sweeps where
-// inverse iteration needs seven.  z is normalised; false when it is not
-// finite (the caller then uses inverse iteration).  dp, dm: m doubles each.
-__device__ bool twisted_vector(int32_t m, const double* __restrict__ d, const double* __restrict__ e, double lc,
-                               double pert, double* __restrict__ dp, double* __restrict__ dm,
-                               double* __restrict__ z) {
+// z_i = -(e_{i-1} / D-_i) z_{i-1} below it.  A pair of adjacent lanes
+// (role 0 and role 1) shares the work in one instruction stream on mirrored
+// indices: first the forward (dp, role 0) and backward (dm, role 1) pivots
+// ...
+__device__ void twisted_sweep(int32_t m, const double* __restrict__ d, const double* __restrict__ e, double lc,
+                              double pert, double* dp, double* dm, int role) {
   auto guard = [pert](double x) { return fabs(x) < pert ? (x < 0.0 ? -pert : pert) : x; };
-  double p = guard(d[0] - lc);
-  dp[0] = p;
-  for (int32_t i = 0; i + 1 < m; ++i) {
-    const double ei = e[i];
-    p = guard(fma(-ei * ei, recip(p), d[i + 1] - lc));
-    dp[i + 1] = p;
+  double* out = role ? dm : dp;
+  const int32_t i0 = role ? m - 1 : 0;
+  double p = guard(d[i0] - lc);
+  out[i0] = p;
+  for (int32_t s = 0; s + 1 < m; ++s) {
+    const int32_t i = role ? m - 2 - s : s + 1;
+    const double ei = e[role ? i : i - 1];
+    p = guard(fma(-ei * ei, recip(p), d[i] - lc));
+    out[i] = p;
   }
-  double q = guard(d[m - 1] - lc);
-  dm[m - 1] = q;
-  for (int32_t i = m - 2; i >= 0; --i) {
-    const double ei = e[i];
-    q = guard(fma(-ei * ei, recip(q), d[i] - lc));
-    dm[i] = q;
-  }
-  int32_t k = 0;
+}
+
+// ... then (both pivot sequences complete) the twist index k (first
+// minimum of |dp + dm - (d - lc)|, the same in both lanes) and the lane's
+// half of z: role 0 z[k] = 1 and z[k-1 .. 0], role 1 z[k+1 .. m-1].
+// Returns the half's sum of squares, and k.
+__device__ double twisted_half(int32_t m, const double* __restrict__ d, const double* __restrict__ e, double lc,
+                               const double* __restrict__ dp, const double* __restrict__ dm,
+                               double* __restrict__ z, int role, int32_t& k) {
+  k = 0;
   double best = fabs(dp[0] + dm[0] - (d[0] - lc));
   for (int32_t i = 1; i < m; ++i) {
     const double g = fabs(dp[i] + dm[i] - (d[i] - lc));
@@ -882,23 +887,20 @@ __device__ bool twisted_vector(int32_t m, const double* __restrict__ d, const do
       k = i;
     }
   }
-  double nn = 1.0, zz = 1.0;
-  z[k] = 1.0;
-  for (int32_t i = k - 1; i >= 0; --i) {
-    zz = -(e[i] * recip(dp[i])) * zz;
+  double nn = 0.0, zz = 1.0;
+  if (role == 0) {
+    z[k] = 1.0;
+    nn = 1.0;
+  }
+  const int32_t len = role ? m - 1 - k : k;
+  for (int32_t s = 0; s < len; ++s) {
+    const int32_t i = role ? k + 1 + s : k - 1 - s;
+    const double ei = e[role ? i - 1 : i];
+    zz = -(ei * recip(role ? dm[i] : dp[i])) * zz;
     z[i] = zz;
     nn = fma(zz, zz, nn);
   }
-  zz = 1.0;
-  for (int32_t i = k + 1; i < m; ++i) {
-    zz = -(e[i - 1] * recip(dm[i])) * zz;
-    z[i] = zz;
-    nn = fma(zz, zz, nn);
-  }
-  if (!(nn > 0.0 && nn < 1e300)) return false;
-  const double inv = 1.0 / sqrt(nn);
-  for (int32_t i = 0; i < m; ++i) z[i] *= inv;
-  return true;
+  return nn;
 }
 
 __device__ __forceinline__ int64_t refl_offset(int32_t m, int32_t klo, int32_t k) {
@@ -1064,28 +1066,52 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
   const double pert = fmax(u * tn, 1e-300);
   const double ortol = 1e-3 * tn;
 
-  // phase 1: every vector on its own thread; an eigenvalue isolated from
-  // both neighbours in the whole spectrum (lam holds all m, decreasing)
-  // takes the twisted factorization, the others inverse iteration
-  for (int32_t c = t; c < r; c += kTriThreads) {
+  // phase 1: every vector on a pair of adjacent lanes; an eigenvalue
+  // isolated from both neighbours in the whole spectrum (lam holds all m,
+  // decreasing) takes the twisted factorization (the two lanes run the two
+  // sweeps, then the two halves of the vector), the others inverse
+  // iteration on the pair's first lane
+  for (int32_t b0 = 0; b0 < 2 * r; b0 += kTriThreads) {  // uniform over the block
+    const int32_t c2 = b0 + t;
+    const bool act = c2 < 2 * r;
+    const int32_t c = act ? (c2 >> 1) : 0;
+    const int role = c2 & 1;
     double* base = scr + (int64_t)(6 * m + 1) * c;  // odd stride: vectors on different LDS banks
+    double* zc = Y + (int64_t)c * m;
     const double lc = lam[c];
-    const bool iso = (c == 0 || lam[c - 1] - lc > ortol) && (c + 1 >= m || lc - lam[c + 1] > ortol);
-    if (iso && twisted_vector(m, dS, eS, lc, pert, base, base + m, Y + (int64_t)c * m)) continue;
-    double *DL = base, *DD = base + m, *DU = base + 2 * m, *DU2 = base + 3 * m;
-    int32_t* piv = (int32_t*)(base + 4 * m);
-    double* y = base + 5 * m;
-    tri_factor(m, dS, eS, lc, pert, DL, DD, DU, DU2, piv);
-    // fixed, non-degenerate start vector (golden-ratio sequence in [0.5, 1.5))
-    for (int32_t i = 0; i < m; ++i) {
-      const double z = 0.6180339887498949 * (i + 1) + 0.7548776662466927 * (c + 1);
-      y[i] = 0.5 + (z - floor(z));
+    const bool iso = act && (c == 0 || lam[c - 1] - lc > ortol) && (c + 1 >= m || lc - lam[c + 1] > ortol);
+    if (iso) twisted_sweep(m, dS, eS, lc, pert, base, base + m, role);
+    // the partner lane's pivots are read below (LDS operations of one wave
+    // complete in order)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int32_t k = 0;
+    const double half = iso ? twisted_half(m, dS, eS, lc, base, base + m, zc, role, k) : 0.0;
+    const double other = __shfl_xor(half, 1);
+    const double nn = role ? other + half : half + other;  // the same bits in both lanes
+    const bool ok = iso && nn > 0.0 && nn < 1e300;
+    if (ok) {
+      const double inv = 1.0 / sqrt(nn);
+      const int32_t i0 = role ? k + 1 : 0, i1 = role ? m : k + 1;
+      for (int32_t i = i0; i < i1; ++i) zc[i] *= inv;
     }
-    for (int it = 0; it < 3; ++it) tri_solve(m, DL, DD, DU, DU2, piv, y);
-    double nn = 0.0;
-    for (int32_t i = 0; i < m; ++i) nn = fma(y[i], y[i], nn);
-    const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-    for (int32_t i = 0; i < m; ++i) Y[(int64_t)c * m + i] = y[i] * inv;
+    if (act && role == 0 && !ok) {
+      double *DL = base, *DD = base + m, *DU = base + 2 * m, *DU2 = base + 3 * m;
+      int32_t* piv = (int32_t*)(base + 4 * m);
+      double* y = base + 5 * m;
+      tri_factor(m, dS, eS, lc, pert, DL, DD, DU, DU2, piv);
+      // fixed, non-degenerate start vector (golden-ratio sequence in [0.5, 1.5))
+      for (int32_t i = 0; i < m; ++i) {
+        const double zq = 0.6180339887498949 * (i + 1) + 0.7548776662466927 * (c + 1);
+        y[i] = 0.5 + (zq - floor(zq));
+      }
+      for (int it = 0; it < 3; ++it) tri_solve(m, DL, DD, DU, DU2, piv, y);
+      double ny = 0.0;
+      for (int32_t i = 0; i < m; ++i) ny = fma(y[i], y[i], ny);
+      const double inv = ny > 0.0 ? 1.0 / sqrt(ny) : 0.0;
+      for (int32_t i = 0; i < m; ++i) zc[i] = y[i] * inv;
+    }
   }
   __syncthreads();
   // phase 2: clustered vectors, in order

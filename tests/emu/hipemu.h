@@ -89,6 +89,9 @@ inline int __builtin_amdgcn_readfirstlane(int x) { return x; }
 // every live lane of the wave reaches this point before any goes on
 // (wave-synchronous LDS exchanges)
 inline void __builtin_amdgcn_wave_barrier() { hipemu::wave_sync(); }
+// ordering of memory operations within the wave: the emulated lanes share
+// memory directly, so there is nothing to order
+inline void __builtin_amdgcn_fence(int, const char*) {}
 // value of x in lane `lane` of the wave (lane uniform over the wave)
 inline int __builtin_amdgcn_readlane(int x, int lane) { return hipemu::readlane(x, lane); }
 // DPP move: quad permutations (dpp_ctrl < 0x100, lane reads lane
