@@ -506,16 +506,23 @@ __global__ __launch_bounds__(NW * 64) void k_tridiag_rw(int32_t n, int32_t ksw, 
   }
 }
 
-// ---- Reflections of a large Gram matrix spread over many workgroups.
-// Reflection k is two launches over the trailing block (indices k+1..m-1,
-// L = m-k-1 of them), each workgroup owning a contiguous range of its rows:
-//  k_tri_mv: every workgroup forms v_k from row k (the same fixed-order sum
-//    for ||x[1:]||^2 in each, so all agree bit for bit) and computes
-//    p_i = tau_k (A v_k)_i for its rows and its share of p.v;
-//  k_tri_up: gamma = tau_k p.v / 2 from the shares (fixed order),
-//    w = p - gamma v, and A -= v w^T + w v^T on its rows; workgroup 0 stores
-//    v_k in row k of A for the back-transformation.
-// Workspace: vbuf (m), pbuf (m), part (kMaxMvBlocks) doubles.
+// ---- Reflections of a large Gram matrix spread over many workgroups, one
+// launch per reflection (k_tri_step), the rank-2 update of reflection k-1
+// folded into the launch of reflection k:
+//  * every workgroup forms w = p - gamma v of reflection k-1 (p, v and the
+//    per-workgroup shares of p.v from the previous launch; gamma =
+//    tau p.v / 2 from the shares in a fixed order), row k after that update
+//    (x = a_k - w - w_0 v, as the first entry of v is 1; kept in LDS, never
+//    stored) and from x reflection k's beta, tau and v_k (the same
+//    fixed-order sum for ||x[2:]||^2 in each workgroup, so all agree bit for
+//    bit); workgroup 0 stores v_{k-1} in row k-1 for the back-transformation;
+//  * each workgroup then takes a contiguous range of the trailing rows
+//    k+1 .. m-1, applies A -= v w^T + w v^T of reflection k-1 to them and,
+//    from the updated values still in registers, forms p_i = tau_k (A v_k)_i
+//    and its share of p.v.
+// The launch with k == kend applies the last update only, to the whole
+// trailing block from row kend.  Workspace (sym_eig_ws): vbuf[2][m],
+// pbuf[2][m], part[2][kMaxMvBlocks], alternating with the parity of k.
 constexpr int kMvThreads = 256;
 constexpr int kMaxMvBlocks = 256;
 
@@ -530,19 +537,62 @@ __device__ double block_sum_mv(double v, double* red) {
   return s;
 }
 
-__global__ __launch_bounds__(kMvThreads) void k_tri_mv(int32_t m, int32_t k, const double* __restrict__ A,
-                                                       double* __restrict__ d, double* __restrict__ e,
-                                                       double* __restrict__ tau, double* __restrict__ vbuf,
-                                                       double* __restrict__ pbuf, double* __restrict__ part) {
-  HIP_DYNAMIC_SHARED(double, v);  // L
+// dynamic LDS: 3 (m - k) + (m - k - 1) doubles
+__global__ __launch_bounds__(kMvThreads) void k_tri_step(int32_t m, int32_t k, int32_t kend, double* __restrict__ A,
+                                                         double* __restrict__ d, double* __restrict__ e,
+                                                         double* __restrict__ tau, double* __restrict__ vbuf,
+                                                         double* __restrict__ pbuf, double* __restrict__ part,
+                                                         int32_t nprev) {
+  HIP_DYNAMIC_SHARED(double, sh);
   __shared__ double red[4];
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  const int32_t L = m - k - 1;
-  const double* rowk = A + (int64_t)k * m + (k + 1);
+  const int32_t Lp = m - k;     // reflection k-1 acts on the indices k .. m-1
+  const int32_t L = m - k - 1;  // reflection k on k+1 .. m-1
+  double* vp = sh;
+  double* wp = sh + Lp;
+  double* x = sh + 2 * (int64_t)Lp;
+  double* v = sh + 3 * (int64_t)Lp;
+  const int pb = (k + 1) & 1, cb = k & 1;
+  const bool upd = k > 0;
+  const double tkp = upd ? tau[k - 1] : 0.0;
+  const bool doup = upd && tkp != 0.0;
+  if (upd) {
+    double pvp = 0.0;
+    for (int32_t g = 0; g < nprev; ++g) pvp += part[pb * kMaxMvBlocks + g];
+    const double gam = 0.5 * tkp * pvp;
+    for (int32_t j = t; j < Lp; j += kMvThreads) {
+      const double vj = vbuf[(int64_t)pb * m + j];
+      vp[j] = vj;
+      wp[j] = doup ? pbuf[(int64_t)pb * m + j] - gam * vj : 0.0;
+      if (blockIdx.x == 0) A[(int64_t)(k - 1) * m + k + j] = vj;  // v_{k-1} kept for the back-transformation
+    }
+    __syncthreads();
+  }
+  const int32_t G = (int32_t)gridDim.x;
+  if (k == kend) {
+    // the last update, rows and columns k .. m-1
+    if (!doup) return;
+    const int32_t per = (Lp + G - 1) / G;
+    const int32_t r0 = (int32_t)blockIdx.x * per, r1 = min(Lp, r0 + per);
+    for (int32_t i = r0 + wid; i < r1; i += kMvThreads / 64) {
+      double* row = A + (int64_t)(k + i) * m + k;
+      const double vi = vp[i], wi = wp[i];
+      for (int32_t j = lane; j < Lp; j += 64) row[j] = fma(-wi, vp[j], fma(-vi, wp[j], row[j]));
+    }
+    return;
+  }
+  // row k after reflection k-1 (columns k .. m-1)
+  const double* rowk = A + (int64_t)k * m + k;
+  const double w0 = doup ? wp[0] : 0.0;
+  for (int32_t q = t; q < Lp; q += kMvThreads) {
+    const double a = rowk[q];
+    x[q] = doup ? fma(-w0, vp[q], fma(-1.0, wp[q], a)) : a;
+  }
+  __syncthreads();
   double s = 0.0;
-  for (int32_t j = 1 + t; j < L; j += kMvThreads) s = fma(rowk[j], rowk[j], s);
+  for (int32_t j = 1 + t; j < L; j += kMvThreads) s = fma(x[j + 1], x[j + 1], s);
   const double sigma = block_sum_mv(s, red);
-  const double alpha = rowk[0];
+  const double alpha = x[1];
   double beta, tk, scale;
   if (sigma == 0.0) {
     tk = 0.0;
@@ -554,71 +604,52 @@ __global__ __launch_bounds__(kMvThreads) void k_tri_mv(int32_t m, int32_t k, con
     scale = 1.0 / (alpha - beta);
   }
   for (int32_t j = t; j < L; j += kMvThreads) {
-    const double vj = (j == 0) ? 1.0 : rowk[j] * scale;
+    const double vj = (j == 0) ? 1.0 : x[j + 1] * scale;
     v[j] = vj;
-    if (blockIdx.x == 0) vbuf[j] = vj;
+    if (blockIdx.x == 0) vbuf[(int64_t)cb * m + j] = vj;
   }
   if (blockIdx.x == 0 && t == 0) {
-    d[k] = A[(int64_t)k * m + k];
+    d[k] = x[0];
     e[k] = beta;
     tau[k] = tk;
   }
   __syncthreads();
-  const int32_t G = (int32_t)gridDim.x;
   const int32_t per = (L + G - 1) / G;
   const int32_t r0 = (int32_t)blockIdx.x * per, r1 = min(L, r0 + per);
   double pv = 0.0;
   for (int32_t i = r0 + wid; i < r1; i += kMvThreads / 64) {
-    const double* row = A + (int64_t)(k + 1 + i) * m + (k + 1);
+    double* row = A + (int64_t)(k + 1 + i) * m + (k + 1);  // columns k+1 .. m-1
+    const double vi = doup ? vp[i + 1] : 0.0, wi = doup ? wp[i + 1] : 0.0;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int32_t j = lane;
     for (; j + 192 < L; j += 256) {
-      acc[0] = fma(row[j], v[j], acc[0]);
-      acc[1] = fma(row[j + 64], v[j + 64], acc[1]);
-      acc[2] = fma(row[j + 128], v[j + 128], acc[2]);
-      acc[3] = fma(row[j + 192], v[j + 192], acc[3]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int32_t jj = j + 64 * u;
+        double a = row[jj];
+        if (doup) {
+          a = fma(-wi, vp[jj + 1], fma(-vi, wp[jj + 1], a));
+          row[jj] = a;
+        }
+        acc[u] = fma(a, v[jj], acc[u]);
+      }
     }
-    for (; j < L; j += 64) acc[0] = fma(row[j], v[j], acc[0]);
+    for (; j < L; j += 64) {
+      double a = row[j];
+      if (doup) {
+        a = fma(-wi, vp[j + 1], fma(-vi, wp[j + 1], a));
+        row[j] = a;
+      }
+      acc[0] = fma(a, v[j], acc[0]);
+    }
     const double pi = tk * wave_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
     if (lane == 0) {
-      pbuf[i] = pi;
+      pbuf[(int64_t)cb * m + i] = pi;
       pv = fma(pi, v[i], pv);
     }
   }
   pv = block_sum_mv(pv, red);
-  if (t == 0) part[blockIdx.x] = pv;
-}
-
-__global__ __launch_bounds__(kMvThreads) void k_tri_up(int32_t m, int32_t k, double* __restrict__ A,
-                                                       const double* __restrict__ tau,
-                                                       const double* __restrict__ vbuf,
-                                                       const double* __restrict__ pbuf,
-                                                       const double* __restrict__ part, int32_t nparts) {
-  HIP_DYNAMIC_SHARED(double, sh);  // v (L), w (L)
-  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  const int32_t L = m - k - 1;
-  const double tk = tau[k];
-  double* v = sh;
-  double* w = sh + L;
-  double pv = 0.0;
-  for (int32_t g = 0; g < nparts; ++g) pv += part[g];
-  const double gam = 0.5 * tk * pv;
-  for (int32_t j = t; j < L; j += kMvThreads) {
-    const double vj = vbuf[j];
-    v[j] = vj;
-    w[j] = tk != 0.0 ? pbuf[j] - gam * vj : 0.0;
-    if (blockIdx.x == 0) A[(int64_t)k * m + (k + 1) + j] = vj;  // v_k kept for the back-transformation
-  }
-  __syncthreads();
-  if (tk == 0.0) return;
-  const int32_t G = (int32_t)gridDim.x;
-  const int32_t per = (L + G - 1) / G;
-  const int32_t r0 = (int32_t)blockIdx.x * per, r1 = min(L, r0 + per);
-  for (int32_t i = r0 + wid; i < r1; i += kMvThreads / 64) {
-    double* row = A + (int64_t)(k + 1 + i) * m + (k + 1);
-    const double vi = v[i], wi = w[i];
-    for (int32_t j = lane; j < L; j += 64) row[j] = row[j] - vi * w[j] - wi * v[j];
-  }
+  if (t == 0) part[cb * kMaxMvBlocks + blockIdx.x] = pv;
 }
 
 int32_t mv_blocks(int32_t L) { return std::max(1, std::min(kMaxMvBlocks, (L + 15) / 16)); }
@@ -1242,8 +1273,7 @@ hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* 
     if (er == hipSuccess) er = set_lds_attr((const void*)k_bisect);
     if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_eigvecs<true>);
     if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_eigvecs<false>);
-    if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_up);
-    if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_mv);
+    if (er == hipSuccess) er = set_lds_attr((const void*)k_tri_step);
     return er;
   }();
   if (attr != hipSuccess) return attr;
@@ -1260,16 +1290,15 @@ hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* 
     // reflections whose trailing block is wider than kRwMax on many
     // workgroups, the rest in registers
     double* vbuf = ws;
-    double* pbuf = ws + m;
-    double* part = ws + 2 * (int64_t)m;
+    double* pbuf = ws + 2 * (int64_t)m;
+    double* part = ws + 4 * (int64_t)m;
     const int32_t ksw = m - kRwMax;
-    for (int32_t k = 0; k < ksw; ++k) {
+    for (int32_t k = 0; k <= ksw; ++k) {  // k == ksw: the last update only
       const int32_t L = m - k - 1;
-      const int32_t G = mv_blocks(L);
-      hipLaunchKernelGGL(k_tri_mv, dim3(G), dim3(kMvThreads), (size_t)L * sizeof(double), st, m, k, A, d, e, tau,
-                         vbuf, pbuf, part);
-      hipLaunchKernelGGL(k_tri_up, dim3(G), dim3(kMvThreads), (size_t)2 * L * sizeof(double), st, m, k, A, tau,
-                         vbuf, pbuf, part, G);
+      const int32_t G = mv_blocks(k < ksw ? L : L + 1);
+      const int32_t nprev = k > 0 ? mv_blocks(m - k) : 0;
+      hipLaunchKernelGGL(k_tri_step, dim3(G), dim3(kMvThreads), (size_t)(3 * (m - k) + L) * sizeof(double), st, m, k,
+                         ksw, A, d, e, tau, vbuf, pbuf, part, nprev);
     }
     hipLaunchKernelGGL((k_tridiag_rw<2, 16>), dim3(1), dim3(kRwWaves * 64), 0, st, kRwMax, ksw, m, A, d, e, tau);
   } else {

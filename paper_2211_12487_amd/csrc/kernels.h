@@ -162,7 +162,7 @@ struct RankSelect {
 // selection above, run by the last eigenvalue workgroup to finish.
 hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* w,
                        double* ws, const RankSelect* sel = nullptr);
-inline int64_t sym_eig_ws(int32_t m) { return 2 * (int64_t)m + 256; }
+inline int64_t sym_eig_ws(int32_t m) { return 4 * (int64_t)m + 512; }
 inline int64_t sym_eigvecs_ws(int32_t m, int32_t r) { return (7 * (int64_t)m + 1) * r; }
 // Eigenvectors of A for its r largest eigenvalues lam[0..r) (from
 // sym_eigvals, decreasing): X (m x r, row-major).  ws: sym_eigvecs_ws(m, r)
