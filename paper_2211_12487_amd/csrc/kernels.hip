@@ -381,6 +381,61 @@ __global__ __launch_bounds__(256) void k_gemm(int32_t M, int32_t N, int32_t K, i
   gemm_epilogue<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, Dz, vd, colpart, red);
 }
 
+// Products with at most four output columns and K <= 128 (the Newton-Schulz
+// and Gram-Schmidt corrections, U_R = R V, coefficient rows): one wave per
+// output row, kSkinnyRows rows per wave, lane l holding k = l and l + 64.
+// B's K x N block is loaded once per wave and kept in registers; every load
+// of the wave's rows is issued before the first product; each of the row's
+// N dot products is a wave sum (fixed order).  D = alpha A B + beta E.
+extern "C" __device__ double __ockl_wfred_add_f64(double);
+constexpr int kSkinnyRows = 4;
+constexpr int kSkinnyMaxK = 128;
+
+template <typename TB, typename TE, typename TD>
+__global__ __launch_bounds__(256) void k_gemm_skinny(int32_t M, int32_t N, int32_t K, double alpha,
+                                                     const double* __restrict__ A, View va,
+                                                     const TB* __restrict__ B, View vb, double beta,
+                                                     const TE* __restrict__ E, View ve, TD* __restrict__ D,
+                                                     View vd) {
+  const int l = threadIdx.x & 63;
+  const int32_t row0 = ((int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6)) * kSkinnyRows;
+  if (row0 >= M) return;  // uniform over the wave; no barriers below
+  double b[2][4], a[kSkinnyRows][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int32_t k = l + 64 * h;
+    const int64_t bro = row_off(vb, min(k, K - 1));
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const double x = (double)B[bro + col_off(vb, min(n, N - 1))];
+      b[h][n] = (k < K && n < N) ? x : 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kSkinnyRows; ++q) {
+    const int64_t aro = row_off(va, min(row0 + q, M - 1));
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int32_t k = l + 64 * h;
+      const double x = A[aro + col_off(va, min(k, K - 1))];
+      a[q][h] = k < K ? x : 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kSkinnyRows; ++q) {
+    const int32_t i = row0 + q;
+    if (i >= M) break;  // uniform over the wave
+    for (int n = 0; n < N; ++n) {
+      const double sn = __ockl_wfred_add_f64(fma(a[q][0], b[0][n], a[q][1] * b[1][n]));
+      if (l == 0) {
+        double v = alpha * sn;
+        if (E) v = fma(beta, (double)E[row_off(ve, i) + col_off(ve, n)], v);
+        D[row_off(vd, i) + col_off(vd, n)] = (TD)v;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Deterministic reductions
 // ---------------------------------------------------------------------------
@@ -592,6 +647,12 @@ hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk,
   // sub-blocks of 16 x 16 per tile: the largest count, that of the first
   const int64_t nsb = ((std::min<int64_t>(M, 64) + 15) / 16) * ((std::min<int64_t>(N, 64) + 15) / 16);
   const int64_t MN = (int64_t)M * N;
+  if (whole_k && !bnorm && !colpart && D && M > 0 && K > 0 && N <= 4 && K <= kSkinnyMaxK) {
+    const int64_t waves = (M + kSkinnyRows - 1) / kSkinnyRows;
+    hipLaunchKernelGGL((k_gemm_skinny<TB, TE, TD>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, M, N, K,
+                       alpha, A, va, B, vb, beta, E, ve, D, vd);
+    return hipGetLastError();
+  }
   if (whole_k && !bnorm && M > 0 && nsb <= 4 && va.cpf == kUnframed && vb.rpf == kUnframed &&
       (can_split || K >= 4 * kMfmaBatch)) {
     // small output tiles, operands linear along K, and either a K split or
