@@ -641,9 +641,11 @@ hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk,
   const int32_t gx = (N + 63) / 64, gy = gemm_row_blocks(M);
   const int64_t tiles = (int64_t)gx * gy;
   const bool whole_k = kchunk <= 0 || kchunk >= K;
-  // (a short K is not split: with tens of tiles the partials' traffic and
-  // reduction cost more than the shorter K loop saves)
-  const bool can_split = whole_k && ws.p && ws.cnt && !bnorm && M > 0 && K >= 256 && tiles <= ws.ncnt && tiles < 96;
+  // (a short K is not split when there are tens of tiles: the partials'
+  // traffic and reduction cost more than the shorter K loop saves; a single
+  // tile or a few split from K = 128)
+  const bool can_split = whole_k && ws.p && ws.cnt && !bnorm && M > 0 && (K >= 256 || (K >= 128 && tiles <= 4)) &&
+                         tiles <= ws.ncnt && tiles < 96;
   // sub-blocks of 16 x 16 per tile: the largest count, that of the first
   const int64_t nsb = ((std::min<int64_t>(M, 64) + 15) / 16) * ((std::min<int64_t>(N, 64) + 15) / 16);
   const int64_t MN = (int64_t)M * N;
