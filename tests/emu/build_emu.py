@@ -37,4 +37,5 @@ def build(outdir: str, asan: bool = True) -> str:
 
 if __name__ == "__main__":
     import sys
-    print(build(sys.argv[1] if len(sys.argv) > 1 else os.path.join(ROOT, "_work", "emu")))
+    import tempfile
+    print(build(sys.argv[1] if len(sys.argv) > 1 else tempfile.mkdtemp(prefix="ttice_emu_")))
