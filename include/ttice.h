@@ -144,8 +144,10 @@ int ttice_set_option(ttice_state* st, int32_t key, const void* val);
 /* Incorporate one increment (Algorithm 1, or Algorithm 2 per TTICE_OPT_ALGO).
  * batch: device pointer to n tensors, [n][n_1]...[n_d] C-order, element type
  * dtype (TTICE_F32 or TTICE_F64); read only.  n == 0 is a no-op.
- * info: host pointer or NULL.  Errors: EINVAL (bad args, non-finite batch),
- * ENOMEM, EDEVICE, ESTATE; the state is unchanged on error. */
+ * info: host pointer or NULL.  Errors: EINVAL (bad args, non-finite batch,
+ * or a residual whose SVD (eq:svdfirst) would exceed the eigensolver's size
+ * limit: min(r_{i-1} n_i, n * n_{i+1}...n_d) above 4096 at a core that
+ * grows), ENOMEM, EDEVICE, ESTATE; the state is unchanged on error. */
 int ttice_update(ttice_state* st, const void* batch, int64_t n, int32_t dtype,
                  struct ttice_update_info* info);
 

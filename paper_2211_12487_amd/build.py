@@ -28,13 +28,31 @@ FLAGS = [
 
 
 def build(verbose: bool = True) -> str:
+    """Compile every source to an object in parallel (one hipcc each: the
+    sources share no device code), then link the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
+    import tempfile
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     srcs = [os.path.join(HERE, s) for s in SRC]
     tmp = OUT + ".tmp"
-    cmd = [hipcc] + FLAGS + srcs + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    with tempfile.TemporaryDirectory(prefix="ttice_build_") as td:
+        objs = [os.path.join(td, os.path.basename(s) + ".o") for s in srcs]
+        cmds = [[hipcc] + [f for f in FLAGS if f != "-shared"] + ["-c", s, "-o", o] for s, o in zip(srcs, objs)]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(jobs) as ex:
+            for r in ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds):
+                if r.stdout or r.stderr:
+                    print(r.stdout + "\n".join(l for l in r.stderr.splitlines()
+                                                if "packed-fp32-ops" not in l), flush=True)
+                if r.returncode != 0:
+                    raise subprocess.CalledProcessError(r.returncode, r.args)
+        link = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.run(link, check=True)
     os.replace(tmp, OUT)
     return OUT
 

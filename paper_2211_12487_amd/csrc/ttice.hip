@@ -433,6 +433,9 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         const bool left = rows <= Ncol;
         const int64_t m = left ? rows : Ncol;
         const int64_t K = left ? Ncol : rows;
+        // documented size limit of the residual's SVD, checked before any
+        // workspace for it is allocated
+        if (m > sym_eig_max()) return TTICE_EINVAL;
         const View vR = vr;                   // rows x Ncol
         const View vRt = transposed(vr);      // Ncol x rows
         // (m <= 32: one slice, on the matrix-core product kernel)
@@ -453,7 +456,6 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
                                          (const double*)nullptr, View(), as<double>(gpart), row_major(m),
                                          m * m, nullptr, nullptr, gws())));
         CK(gram_reduce(st, as<double>(gpart), (int32_t)Sg, (int32_t)m, as<double>(gram)));
-        if (m > sym_eig_max()) return TTICE_EINVAL;  // documented size limit of the residual's SVD
         // eigenvalues, then the truncation rank (eq:deltasvd) from them
         RankSelect sel;
         sel.cnt = as<int>(tilecnt);  // zero between kernels (the product kernels clear theirs)
@@ -1099,10 +1101,16 @@ int ttice_load(const void* buf, int64_t size, ttice_state** out) {
   // the shape rules every state satisfies: r_0 = 1 and orthonormal columns
   // (r_i <= r_{i-1} n_i), frames >= 0, options in range
   if (n_total < 0 || rk[0] != 1) return TTICE_EINVAL;
+  // the dims' bounds of ttice_create first, so that r_{i-1} n_i below stays
+  // far from overflow (r_i <= prod(dims) < 2^31 by induction)
+  int64_t P = 1;
   for (int i = 0; i < d; ++i) {
     if (dims[i] < 1 || dims[i] >= ((int64_t)1 << 31)) return TTICE_EINVAL;
-    if (rk[i + 1] < 0 || rk[i + 1] > rk[i] * dims[i]) return TTICE_EINVAL;
+    P *= dims[i];
+    if (P >= ((int64_t)1 << 31)) return TTICE_EINVAL;
   }
+  for (int i = 0; i < d; ++i)
+    if (rk[i + 1] < 0 || rk[i + 1] > rk[i] * dims[i]) return TTICE_EINVAL;
   if (prec != TTICE_PREC_FP64 && prec != TTICE_PREC_FP32 && prec != TTICE_PREC_BF16X3) return TTICE_EINVAL;
   if (algo != TTICE_ALG_PLAIN && algo != TTICE_ALG_STAR) return TTICE_EINVAL;
   if (skip != TTICE_SKIP_MEAN && skip != TTICE_SKIP_BATCH && skip != TTICE_SKIP_NONE) return TTICE_EINVAL;

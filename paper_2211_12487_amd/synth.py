@@ -187,6 +187,42 @@ def fourier_field_stream(
         yield out.astype(dtype, copy=False)
 
 
+class DeviceFourierField:
+    """The field of ``fourier_field_stream`` (same seeded modes, same closed
+    form) evaluated on a torch device, for streams too large to draw on the
+    host: ``snapshots(t0, n)`` returns snapshots t0 .. t0+n-1 as a
+    (n, grid, grid, grid[, components]) tensor of ``dtype`` on ``device``,
+    computed as the host generator does (FP64 inverse FFT of the sparse
+    spectrum, then rounded to ``dtype``).  It agrees with the host generator
+    to FP64 rounding (FFT orderings differ), not bit for bit."""
+
+    def __init__(self, grid=64, components=3, n_modes=512, kmax=8, decay=2.0, seed=0, device="cuda"):
+        import torch
+        rng = np.random.default_rng(seed)
+        ks, amp, omega, phase = _fourier_modes(rng, n_modes, kmax, components)
+        kn = np.sqrt((ks.astype(np.float64) ** 2).sum(1)) ** (-decay)
+        self.grid, self.components, self.device = grid, components, device
+        self.idx = tuple(torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in (ks % grid).T)
+        self.ak = torch.from_numpy(amp * kn[:, None]).to(device)          # (modes, components)
+        self.omega = torch.from_numpy(omega).to(device)
+        self.phase = torch.from_numpy(phase).to(device)
+
+    def snapshots(self, t0, n, dtype=None):
+        import torch
+        dtype = torch.float32 if dtype is None else dtype
+        g, C = self.grid, self.components
+        out = torch.empty((n, g, g, g, C), dtype=dtype, device=self.device)
+        spec = torch.zeros((g, g, g), dtype=torch.complex128, device=self.device)
+        for b in range(n):
+            t = float(t0 + b)
+            for c in range(C):
+                spec.zero_()
+                coef = self.ak[:, c] * torch.exp(1j * (self.omega * t + self.phase[:, c]))
+                spec.index_put_(self.idx, coef, accumulate=True)
+                out[b, ..., c] = (torch.fft.ifftn(spec).real * g ** 3).to(dtype)
+        return out[..., 0] if C == 1 else out
+
+
 def tt_lowrank_stream(
     dims: Sequence[int] = (10, 15, 20),
     ranks: Sequence[int] = (2, 3, 5),

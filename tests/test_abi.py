@@ -95,3 +95,28 @@ def test_argument_validation_without_device(L):
     L.ttice_destroy(None)
     assert L.ttice_strerror(0) == b"ok"
     assert L.ttice_strerror(-2) == b"out of memory"
+
+
+def _image_header(d, dims, ranks, n_total=0):
+    import struct
+    return (b"TTICEim1" + struct.pack("<4i", d, 0, 0, 0) + struct.pack("<2d", 0.1, 1.0)
+            + struct.pack("<q", n_total) + struct.pack(f"<{d}q", *dims) + struct.pack(f"<{d + 1}q", *ranks))
+
+
+def test_load_rejects_shapes_before_any_arithmetic_on_them(L):
+    """ttice_load validates an image's dims as ttice_create does (each >= 1,
+    product below 2^31) before it multiplies ranks by dims, so a crafted
+    chain of large ranks cannot overflow the validator; every such image is
+    refused with EINVAL before any device call."""
+    h = ctypes.c_void_p()
+    cases = [
+        (3, (1 << 30, 1 << 30, 1 << 30), (1, 1 << 30, 1 << 60, 1)),   # r_2 n_3 overflows int64
+        (2, (1 << 20, 1 << 20), (1, 1 << 20, 1)),                     # product of dims >= 2^31
+        (2, (4, 0), (1, 4, 0)),                                       # a zero dim
+        (2, (4, 5), (2, 4, 1)),                                       # r_0 != 1
+        (2, (4, 5), (1, 5, 1)),                                       # r_1 > r_0 n_1
+    ]
+    for d, dims, ranks in cases:
+        img = _image_header(d, dims, ranks) + b"\0" * 64
+        assert L.ttice_load(img, len(img), ctypes.byref(h)) == -1, (dims, ranks)
+        assert not h.value
