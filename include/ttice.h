@@ -81,11 +81,22 @@ enum ttice_option {
   TTICE_OPT_STREAM = 5,    /* hipStream_t passed as (const void*)&stream; all
                               device work of later calls runs on it (default:
                               the null stream)                                 */
-  TTICE_OPT_PROFILE = 6    /* int32_t: 1 = time the kernels listed in enum
+  TTICE_OPT_PROFILE = 6,   /* int32_t: 1 = time the kernels listed in enum
                               ttice_kernel with HIP events carried by their
                               launches (start and end of the kernel itself, on
                               the library's stream; setting it resets the
                               counters); 0 = off                               */
+  TTICE_OPT_SVD = 7        /* int32_t, solver of the residual's truncated SVD
+                              (eq:svdfirst): 1 (default) = residuals whose
+                              Gram matrix is wider than 256 first try block
+                              Lanczos for the leading singular pairs (the
+                              truncation rank needs only those: the discarded
+                              energy is ||R||_F^2 minus their sum), accepted
+                              only when the residuals of its Ritz pairs
+                              certify the rank and the kept subspace, else
+                              the dense eigensolver runs; 0 = dense only;
+                              2 = as 1 for every Gram matrix wider than the
+                              Krylov basis (128)                             */
 };
 
 /* Kernels whose launches TTICE_OPT_PROFILE times. */
@@ -128,6 +139,11 @@ struct ttice_update_info {
   double achieved2;               /* sum_i tail2[i] = ||Y - Yhat||_F^2 for
                                      Algorithm 1 (Theorem 1's proof is a chain of
                                      Pythagorean equalities); -1 for Alg. 2     */
+  int32_t solver[TTICE_MAX_D];    /* truncated SVD of core i's residual: 0 none
+                                     (norm test passed or core skipped), 1 dense
+                                     eigensolver, 2 block Lanczos (TTICE_OPT_SVD) */
+  int32_t rechecked[TTICE_MAX_D]; /* 1 when core i's norm test was taken again
+                                     on an FP64 projection (reduced precision) */
 };
 
 /* Create an empty accumulation for d-way tensors of size dims[0..d-1] with

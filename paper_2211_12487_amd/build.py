@@ -8,7 +8,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = ["csrc/kernels.hip", "csrc/eig.hip", "csrc/proj.hip", "csrc/proj_lp.hip", "csrc/ttice.hip", "csrc/server.hip"]
+SRC = ["csrc/kernels.hip", "csrc/eig.hip", "csrc/proj.hip", "csrc/proj_lp.hip", "csrc/ttice.hip", "csrc/server.hip",
+       "csrc/lanczos.hip"]
 OUT = os.path.join(HERE, "libttice.so")
 ARCH = os.environ.get("TTICE_OFFLOAD_ARCH", "gfx950")
 

@@ -702,13 +702,23 @@ __device__ void select_rank_block(int32_t m, const double* w, const RankSelect& 
   __syncthreads();
   if (t == 0) {
     double acc = 0.0;
-    sel.tail[m] = 0.0;
     for (int32_t r = m - 1; r >= 0; --r) {
       acc = acc + sl[r];
       sl[r] = acc;
-      sel.tail[r] = acc;
     }
     sl[m] = 0.0;
+    // eigenvalues of a projection of the Gram matrix (Ritz values): the
+    // energy they do not account for, trace - sum, belongs to every tail
+    double rem = 0.0;
+    if (sel.trace != nullptr) {
+      const double tr = *sel.trace;
+      if (!isfinite(tr)) bad = 1;
+      rem = fmax(0.0, tr - sl[0]);
+    }
+    for (int32_t r = 0; r <= m; ++r) {
+      sl[r] += rem;
+      sel.tail[r] = sl[r];
+    }
     int32_t rr = m;
     for (int32_t r = 0; r <= m; ++r)
       if (sl[r] <= sel.tol2) {
@@ -1055,14 +1065,15 @@ __device__ void back_transform_group(int32_t m, int32_t r, int32_t klo, int32_t 
 // iteration.  The back-transformation applies the reflectors in chunks
 // staged through LDS, one wave per column.  Output X (m x r, row-major).
 // kLdsWork: the per-vector factors and Y live in LDS (else in ws, 7*m*r
-// doubles).
+// doubles).  back = 0: stop before the back-transformation (ws holds Y).
 template <bool kLdsWork>
 __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t r, const double* __restrict__ d,
                                                              const double* __restrict__ e,
                                                              const double* __restrict__ lam,
                                                              const double* __restrict__ A,
                                                              const double* __restrict__ tau,
-                                                             double* __restrict__ ws, double* __restrict__ X) {
+                                                             double* __restrict__ ws, double* __restrict__ X,
+                                                             int32_t back) {
   HIP_DYNAMIC_SHARED(double, lds);
   __shared__ double red[kWaves];
   const int t = threadIdx.x;
@@ -1171,6 +1182,9 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
       __syncthreads();
     }
   }
+  // (back == 0: the tridiagonal matrix's vectors stay in ws, column c at
+  // ws + c m, for the blocked back-transformation)
+  if (!back) return;
   // back-transformation x = H_0 H_1 ... H_{m-3} y, reflectors klo..khi
   // staged in LDS per chunk; tau goes to LDS too (dS is free from here on)
   for (int32_t i = t; i < m; i += kTriThreads) dS[i] = tau[i];
@@ -1254,6 +1268,85 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
     for (int32_t c = t & 63; c < r; c += 64) X[(int64_t)i * r + c] = Y[(int64_t)c * m + i];
 }
 
+// ---- Blocked back-transformation for wide matrices: x = H_0 H_1 ...
+// H_{m-3} y applied block by block in the compact WY form, H_{k0} ...
+// H_{k0+nb-1} = I - V T V^T (V: the nb reflectors as columns, T upper
+// triangular), so each block is three products on the tiled kernels:
+// W = V^T Y, W = T W, Y -= V W (last block first).
+constexpr int32_t kWyNb = 64;
+constexpr int32_t kWyMin = 256;  // wider matrices take this path
+
+// A(k, a) = 0 for a <= k: row k keeps only its reflector's entries (a > k),
+// so a block of rows reads as V^T with its zeros in place
+__global__ void k_zero_lower(int32_t m, double* __restrict__ A) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * m) return;
+  const int32_t k = (int32_t)(e / m), a = (int32_t)(e - (int64_t)k * m);
+  if (a <= k) A[e] = 0.0;
+}
+
+// T of block blockIdx.x (reflectors k0 .. k0 + nbc - 1, k0 = block * kWyNb,
+// nbc = min(kWyNb, nref - k0)): S = V^T V from row tiles staged in LDS
+// (thread t: row i = t / 4 of S, columns 16 (t % 4) ... + 15), then column
+// by column T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) S(0:j, j).
+// Output Tb + block * kWyNb^2 (kWyNb x kWyNb, zero outside nbc x nbc).
+// Dynamic LDS: kWyLds doubles (the row tile, S and T).
+constexpr int32_t kWyLds = kWyNb * 33 + 2 * kWyNb * (kWyNb + 1);
+__global__ __launch_bounds__(256) void k_wy_t(int32_t m, int32_t nref, const double* __restrict__ A,
+                                              const double* __restrict__ tau, double* __restrict__ Tb) {
+  HIP_DYNAMIC_SHARED(double, sh);
+  double(*Vt)[33] = reinterpret_cast<double(*)[33]>(sh);
+  double(*Ss)[kWyNb + 1] = reinterpret_cast<double(*)[kWyNb + 1]>(sh + kWyNb * 33);
+  double(*Ts)[kWyNb + 1] = reinterpret_cast<double(*)[kWyNb + 1]>(sh + kWyNb * 33 + kWyNb * (kWyNb + 1));
+  const int t = threadIdx.x;
+  const int32_t k0 = blockIdx.x * kWyNb;
+  const int32_t nbc = min(kWyNb, nref - k0);
+  const int i = t >> 2, j0 = (t & 3) * 16;
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  for (int32_t a0 = k0 + 1; a0 < m; a0 += 32) {
+    for (int q = t; q < kWyNb * 32; q += 256) {
+      const int r = q >> 5, c = q & 31;
+      const int32_t a = a0 + c;
+      Vt[r][c] = (r < nbc && a < m) ? A[(int64_t)(k0 + r) * m + a] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int c = 0; c < 32; ++c) {
+      const double vi = Vt[i][c];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] = fma(vi, Vt[j0 + u][c], acc[u]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) Ss[i][j0 + u] = acc[u];
+  for (int q = t; q < kWyNb * kWyNb; q += 256) Ts[q / kWyNb][q % kWyNb] = 0.0;
+  __syncthreads();
+  for (int32_t j = 0; j < nbc; ++j) {
+    const double tj = tau[k0 + j];
+    if (t < j) {
+      double s = 0.0;
+      for (int32_t l = t; l < j; ++l) s = fma(Ts[t][l], Ss[l][j], s);
+      Ts[t][j] = -tj * s;
+    } else if (t == j) {
+      Ts[j][j] = tj;
+    }
+    __syncthreads();
+  }
+  double* out = Tb + (int64_t)blockIdx.x * kWyNb * kWyNb;
+  for (int q = t; q < kWyNb * kWyNb; q += 256) out[q] = Ts[q / kWyNb][q % kWyNb];
+}
+
+// X (m x r, row-major) = Y (column c at Y + c m)
+__global__ void k_cols_to_rows(int32_t m, int32_t r, const double* __restrict__ Y, double* __restrict__ X) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * r) return;
+  const int32_t i = (int32_t)(e / r), c = (int32_t)(e - (int64_t)i * r);
+  X[e] = Y[(int64_t)c * m + i];
+}
+
 hipError_t set_lds_attr(const void* f) {
   return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsDoubles * sizeof(double)));
 }
@@ -1312,18 +1405,69 @@ hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* 
 }
 
 hipError_t sym_eigvecs(hipStream_t st, int32_t m, int32_t r, const double* d, const double* e,
-                       const double* lam, const double* A, const double* tau, double* ws, double* X) {
+                       const double* lam, double* A, const double* tau, double* ws, double* X, GemmWs gws) {
   if (m <= 0 || r <= 0) return hipSuccess;
-  const int64_t base_lds = 2 * (int64_t)m + sym_eigvecs_ws(m, r);
+  const int64_t base_lds = 2 * (int64_t)m + (7 * (int64_t)m + 1) * r;
   // all work in LDS when that leaves room for at least one reflector
   if (base_lds + m <= kLdsDoubles) {
     hipLaunchKernelGGL(k_tri_eigvecs<true>, dim3(1), dim3(kTriThreads), (size_t)kLdsDoubles * sizeof(double),
-                       st, m, r, d, e, lam, A, tau, ws, X);
-  } else {
-    hipLaunchKernelGGL(k_tri_eigvecs<false>, dim3(1), dim3(kTriThreads), (size_t)kLdsDoubles * sizeof(double),
-                       st, m, r, d, e, lam, A, tau, ws, X);
+                       st, m, r, d, e, lam, A, tau, ws, X, 1);
+    return hipGetLastError();
   }
+  if (m <= kWyMin) {
+    hipLaunchKernelGGL(k_tri_eigvecs<false>, dim3(1), dim3(kTriThreads), (size_t)kLdsDoubles * sizeof(double),
+                       st, m, r, d, e, lam, A, tau, ws, X, 1);
+    return hipGetLastError();
+  }
+  // vectors of the tridiagonal matrix into ws (Y, column-major), then the
+  // blocked back-transformation on the tiled products
+  hipLaunchKernelGGL(k_tri_eigvecs<false>, dim3(1), dim3(kTriThreads), (size_t)kLdsDoubles * sizeof(double), st,
+                     m, r, d, e, lam, A, tau, ws, X, 0);
+  hipError_t er = hipGetLastError();
+  if (er != hipSuccess) return er;
+  const int32_t nref = m - 2;
+  const int32_t nblk = (nref + kWyNb - 1) / kWyNb;
+  double* Y = ws;
+  double* Tb = ws + (int64_t)m * r;
+  double* W = Tb + (int64_t)nblk * kWyNb * kWyNb;
+  double* W2 = W + (int64_t)kWyNb * r;
+  hipLaunchKernelGGL(k_zero_lower, dim3((unsigned)(((int64_t)m * m + 255) / 256)), dim3(256), 0, st, m, A);
+  static const hipError_t attr = hipFuncSetAttribute((const void*)k_wy_t, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)(kWyLds * sizeof(double)));
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(k_wy_t, dim3(nblk), dim3(256), (size_t)kWyLds * sizeof(double), st, m, nref, A, tau, Tb);
+  er = hipGetLastError();
+  if (er != hipSuccess) return er;
+  View vy;  // Y rows a, columns c: Y[c m + a]
+  vy.rs = 1;
+  vy.cs = m;
+  View vcol = vy;  // V (rows a, columns j) read from A's rows
+  const View vr = row_major(r);
+  for (int32_t c = nblk - 1; c >= 0; --c) {
+    const int32_t k0 = c * kWyNb, nbc = std::min(kWyNb, nref - k0);
+    const int32_t a0 = k0 + 1, K = m - a0;
+    const double* Vb = A + (int64_t)k0 * m + a0;
+    er = gemm<double, double, double>(st, nbc, r, K, K, 1.0, Vb, row_major(m), Y + a0, vy, 0.0,
+                                      (const double*)nullptr, View(), W, vr, 0, nullptr, nullptr, gws);
+    if (er != hipSuccess) return er;
+    er = gemm<double, double, double>(st, nbc, r, nbc, nbc, 1.0, Tb + (int64_t)c * kWyNb * kWyNb, row_major(kWyNb),
+                                      W, vr, 0.0, (const double*)nullptr, View(), W2, vr, 0, nullptr, nullptr, gws);
+    if (er != hipSuccess) return er;
+    er = gemm<double, double, double>(st, K, r, nbc, nbc, -1.0, Vb, vcol, W2, vr, 1.0, Y + a0, vy, Y + a0, vy, 0,
+                                      nullptr, nullptr, gws);
+    if (er != hipSuccess) return er;
+  }
+  hipLaunchKernelGGL(k_cols_to_rows, dim3((unsigned)(((int64_t)m * r + 255) / 256)), dim3(256), 0, st, m, r, Y, X);
   return hipGetLastError();
+}
+
+int64_t sym_eigvecs_ws(int32_t m, int32_t r) {
+  int64_t w = (7 * (int64_t)m + 1) * r;
+  if (m > kWyMin) {
+    const int64_t nblk = (m - 2 + kWyNb - 1) / kWyNb;
+    w = std::max<int64_t>(w, (int64_t)m * r + nblk * kWyNb * kWyNb + 2 * (int64_t)kWyNb * r);
+  }
+  return w;
 }
 
 }  // namespace ttice

@@ -123,9 +123,13 @@ hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk,
 
 inline int32_t gemm_row_blocks(int32_t M) { return M > 0 ? (M + 63) / 64 : 1; }
 
-// out[f] = sum_{mb<MB} sum_{c<cpf} part[mb*ld + f*cpf + c], f < F.
+// out[f] = sum_{mb<MB} sum_{c<cpf} part[mb*ld + f*cpf + c], f < F, in a
+// fixed order.  scratch (F * kFrameSlicesMax doubles, or null: one block per
+// frame) holds the sums of column slices of each frame.
+constexpr int32_t kFrameSlicesMax = 64;
+int32_t frame_sum_slices(int32_t cpf, int32_t F);
 hipError_t frame_sums(hipStream_t st, const double* part, int32_t MB, int64_t ld, int32_t cpf,
-                      int32_t F, double* out);
+                      int32_t F, double* out, double* scratch);
 // out[0] = sum_{i<n} x[i] (deterministic order); out[1] = 1 if any x is not finite.
 hipError_t total_sum(hipStream_t st, const double* x, int64_t n, double* out);
 // acc[i] += x[i]
@@ -138,7 +142,7 @@ hipError_t gram_reduce(hipStream_t st, const double* part, int32_t S, int32_t m,
 // Rank selection for SVD(R, eps) from the eigenvalues w (m) of the residual's
 // Gram matrix (eq:deltasvd / eq:svdfirst): order[t] = index of the t-th
 // largest eigenvalue, lam[t] its value clamped to >= 0; tail[r] =
-// sum_{t>=r} lam[t] (m + 1 entries); r_R = smallest r with tail[r] <= tol2,
+// sum_{t>=r} lam[t] (+ the remainder below, m + 1 entries); r_R = smallest r with tail[r] <= tol2,
 // clipped to cap.  res[0] = r_R, res[1] = tail[r_R], res[2] = margin,
 // res[3] = 1 if any eigenvalue was not finite.  cnt: one int of device
 // memory that is zero on entry and is left zero (the arrival counter of the
@@ -151,6 +155,10 @@ struct RankSelect {
   double* lam = nullptr;
   double* tail = nullptr;
   double* res = nullptr;
+  // optional: the trace of the Gram matrix when the m eigenvalues are those
+  // of a projection of it (Ritz values); every tail then includes trace -
+  // sum of the m values (clamped at 0)
+  const double* trace = nullptr;
 };
 
 // Eigenvalues of the symmetric m x m matrix A (row-major, ld = m, m <=
@@ -163,14 +171,18 @@ struct RankSelect {
 hipError_t sym_eigvals(hipStream_t st, int32_t m, double* A, double* d, double* e, double* tau, double* w,
                        double* ws, const RankSelect* sel = nullptr);
 inline int64_t sym_eig_ws(int32_t m) { return 4 * (int64_t)m + 512; }
-inline int64_t sym_eigvecs_ws(int32_t m, int32_t r) { return (7 * (int64_t)m + 1) * r; }
+int64_t sym_eigvecs_ws(int32_t m, int32_t r);
 // Eigenvectors of A for its r largest eigenvalues lam[0..r) (from
 // sym_eigvals, decreasing): X (m x r, row-major).  ws: sym_eigvecs_ws(m, r)
-// doubles.
+// doubles.  For m > 256 the reflectors are applied in blocks on the tiled
+// products (K split through gws when given), and A's diagonal and the
+// entries left of it in each row (not needed by then) are zeroed.
 hipError_t sym_eigvecs(hipStream_t st, int32_t m, int32_t r, const double* d, const double* e,
-                       const double* lam, const double* A, const double* tau, double* ws, double* X);
+                       const double* lam, double* A, const double* tau, double* ws, double* X,
+                       GemmWs gws = GemmWs());
 int32_t sym_eig_max();
 
+// (order null: the identity)
 // W (rows x r, ld = r) = V[:, order[t]] (left case)  or
 // Vs (M x r, ld = r) = V[:, order[t]] / sqrt(lam[t]) (right case, scale = true)
 hipError_t gather_columns(hipStream_t st, int32_t rows, int32_t r, const double* V, int32_t ldv,
@@ -190,5 +202,26 @@ hipError_t zero2d(hipStream_t st, int64_t rows, int64_t cols, double* dst, int64
 // res[4] = |D|, res[5] = ||Y||^2; dlist = indices of D in increasing order.
 hipError_t star_decide(hipStream_t st, int32_t N, const double* e2, const double* y2, double eps,
                        int32_t* dlist, double* res);
+
+// ---- pieces of the block-Lanczos truncated SVD (lanczos.hip)
+// Q(i, j) = a fixed pseudo-random value in [-1, 1) for i < m, j < b (ld).
+hipError_t rand_fill(hipStream_t st, int64_t m, int32_t b, double* Q, int64_t ld, uint64_t seed);
+// Li = L^{-T} (b x b, ld ldl) for the Cholesky factor L of S = V^T V (b x b,
+// ld lds, b <= lz_max_block()), so V Li has orthonormal columns; a column
+// that depends on the earlier ones to working precision, or (Spre given: the
+// Gram block before orthogonalisation against earlier blocks, ld ldpre)
+// kept too little of its length, gets a zero column.
+int32_t lz_max_block();
+hipError_t chol_inv(hipStream_t st, int32_t b, const double* S, int32_t lds, const double* Spre, int32_t ldpre,
+                    double* Li, int32_t ldl);
+// T = (T + T^T) / 2 (n x n, ld)
+hipError_t symmetrize(hipStream_t st, int32_t n, double* T, int32_t ld);
+// *out = sum_{i<n} x[i]^2 in a fixed order; part: sumsq_parts(n) doubles
+int64_t sumsq_parts(int64_t n);
+hipError_t sumsq(hipStream_t st, const double* x, int64_t n, double* part, double* out);
+// eta2[j] = ||GX(:, j) - theta_j X(:, j)||^2 and theta_out[j] = theta_j for
+// j < k (X, GX: m x k, ld); the outputs may be pinned host memory
+hipError_t ritz_residuals(hipStream_t st, int32_t m, int32_t k, int32_t ld, const double* X, const double* GX,
+                          const double* theta, double* eta2, double* theta_out);
 
 }  // namespace ttice

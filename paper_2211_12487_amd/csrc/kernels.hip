@@ -452,18 +452,36 @@ __device__ double block_sum_256(double v, double* red) {
   return r;
 }
 
+// Block (s, f) sums the column slice s (of S) of frame f over the MB row
+// blocks: out[f * S + s] (with S = 1, the frame's total).  Loops run over
+// the row blocks, then columns: no index division.
 __global__ __launch_bounds__(256) void k_frame_sums(const double* __restrict__ part, int32_t MB,
-                                                     int64_t ld, int32_t cpf, double* __restrict__ out) {
+                                                     int64_t ld, int32_t cpf, int32_t cslice,
+                                                     double* __restrict__ out) {
   __shared__ double red[256];
-  const int32_t f = blockIdx.x;
-  double s = 0.0;
-  const int64_t per = (int64_t)MB * cpf;
-  for (int64_t q = threadIdx.x; q < per; q += 256) {
-    const int64_t mb = q / cpf, c = q - mb * cpf;
-    s += part[mb * ld + (int64_t)f * cpf + c];
+  const int32_t s = blockIdx.x, S = gridDim.x, f = blockIdx.y;
+  const int32_t c0 = s * cslice, c1 = min(cpf, c0 + cslice);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t mb = 0; mb < MB; ++mb) {
+    const double* p = part + (int64_t)mb * ld + (int64_t)f * cpf;
+    int32_t c = c0 + threadIdx.x;
+    for (; c + 768 < c1; c += 1024) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += p[c + 256 * u];
+    }
+    for (; c < c1; c += 256) acc[0] += p[c];
   }
-  s = block_sum_256(s, red);
-  if (threadIdx.x == 0) out[f] = s;
+  const double v = block_sum_256((acc[0] + acc[1]) + (acc[2] + acc[3]), red);
+  if (threadIdx.x == 0) out[(int64_t)f * S + s] = v;
+}
+
+// out[f] = sum of the S slice sums of frame f, in slice order
+__global__ void k_slice_sums(const double* __restrict__ sl, int32_t S, int32_t F, double* __restrict__ out) {
+  const int32_t f = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (f >= F) return;
+  double v = 0.0;
+  for (int32_t s = 0; s < S; ++s) v += sl[(int64_t)f * S + s];
+  out[f] = v;
 }
 
 __global__ __launch_bounds__(256) void k_total_sum(const double* __restrict__ x, int64_t n,
@@ -517,7 +535,7 @@ __global__ void k_gather_columns(int32_t rows, int32_t r, const double* __restri
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)rows * r) return;
   const int32_t i = (int32_t)(e / r), tcol = (int32_t)(e % r);
-  double v = V[(int64_t)i * ldv + order[tcol]];
+  double v = V[(int64_t)i * ldv + (order ? order[tcol] : tcol)];
   if (scale) v /= sqrt(lam[tcol]);
   W[e] = v;
 }
@@ -714,10 +732,22 @@ TTICE_GEMM_INST(float, float, float)
 TTICE_GEMM_INST(double, float, float)
 TTICE_GEMM_INST(float, double, float)
 
+int32_t frame_sum_slices(int32_t cpf, int32_t F) {
+  // a few hundred blocks in all, slices of at least 8192 columns
+  const int64_t by_len = ((int64_t)cpf + 8191) / 8192;
+  const int64_t by_grid = std::max<int64_t>(1, 512 / std::max(F, 1));
+  return (int32_t)std::max<int64_t>(1, std::min<int64_t>({by_len, by_grid, (int64_t)kFrameSlicesMax}));
+}
+
 hipError_t frame_sums(hipStream_t st, const double* part, int32_t MB, int64_t ld, int32_t cpf,
-                      int32_t F, double* out) {
+                      int32_t F, double* out, double* scratch) {
   if (F <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_frame_sums, dim3(F), dim3(256), 0, st, part, MB, ld, cpf, out);
+  const int32_t S = scratch ? frame_sum_slices(cpf, F) : 1;
+  const int32_t cslice = (cpf + S - 1) / S;
+  hipLaunchKernelGGL(k_frame_sums, dim3(S, F), dim3(256), 0, st, part, MB, ld, cpf, cslice, S > 1 ? scratch : out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || S == 1) return e;
+  hipLaunchKernelGGL(k_slice_sums, dim3(nblocks(F, 256)), dim3(256), 0, st, scratch, S, F, out);
   return hipGetLastError();
 }
 

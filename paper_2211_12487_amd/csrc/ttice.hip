@@ -151,6 +151,24 @@ struct ttice_state {
     return GemmWs{as<double>(splitk), (int64_t)(splitk.bytes / sizeof(double)), as<int>(tilecnt), kTileCounters};
   }
   int sync_scalars(int n);
+  // truncated SVD of the residual R (rows x Ncol, view vR, in rbuf): r_R,
+  // its discarded energy and decision margin, and for r_R > 0 the U_R
+  // candidates in W (rows x r_R, ld r_R) before re-orthogonalisation
+  int dense_svd(int64_t rows, int64_t Ncol, const View& vR, bool left, double tol2, int64_t cap, int64_t* rR,
+                double* tail2, double* margin);
+  int lanczos_svd(int level, int64_t rows, int64_t Ncol, const View& vR, bool left, double tol2, int64_t cap,
+                  int64_t* rR, double* tail2, double* margin, bool* ok);
+  int32_t lz_mode = 1;                       // 1: block Lanczos for wide Gram matrices, 0: dense only
+  int64_t last_rR[TTICE_MAX_D] = {};          // last r_R decided per core (solver choice)
+  int64_t lz_tries = 0, lz_accepted = 0;      // block-Lanczos SVDs attempted / certified
+  double* hl = nullptr;                       // pinned host copy of Ritz values and residuals
+  DevBuf lzw;
+  // slice sums of frame_sums (null when it cannot be allocated: one block
+  // per frame then)
+  DevBuf fsl;
+  double* fscratch(int64_t N) {
+    return ensure(fsl, (size_t)N * kFrameSlicesMax * sizeof(double)) == TTICE_OK ? as<double>(fsl) : nullptr;
+  }
   double lp_band(int pp, int64_t rows) const;
   int64_t lp_rechecks = 0;  // norm tests taken again in FP64 (reduced precision)
   template <typename TIn>
@@ -197,10 +215,11 @@ ttice_state::~ttice_state() {
     if (U[i].p) (void)hipFree(U[i].p);
   if (Gt.p) (void)hipFree(Gt.p);
   DevBuf* bufs[] = {&z[0], &z[1], &rbuf, &colpart, &bnorm, &fres, &fy2, &e2acc, &scal, &gpart, &gram,
-                    &tri, &order, &lam, &tail, &W, &W2, &T, &S, &dlist, &eigws, &splitk, &tilecnt};
+                    &tri, &order, &lam, &tail, &W, &W2, &T, &S, &dlist, &eigws, &splitk, &tilecnt, &lzw, &fsl};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (hs) (void)hipHostFree(hs);
+  if (hl) (void)hipHostFree(hl);
 }
 
 // Reallocate core storage to at least need_rows x need_cols, preserving the
@@ -283,6 +302,338 @@ double ttice_state::lp_band(int pp, int64_t rows) const {
   return 4.0 * g * (double)d / (eps * eps);
 }
 
+namespace {
+// Block-Lanczos truncated SVD: blocks of kLzBlock vectors, kLzSteps blocks
+// (a Krylov basis of kLzBasis vectors, whose projected matrix fits the
+// register tridiagonalisation); used for Gram matrices wider than kLzMinM.
+constexpr int32_t kLzBlock = 32;
+constexpr int32_t kLzSteps = 4;
+constexpr int32_t kLzBasis = kLzBlock * kLzSteps;
+constexpr int64_t kLzMinM = 256;
+// Acceptance of the kept Ritz pairs: the bound sum eta^2 / gap of their
+// eigenvalue error within kLzTailTol of the distance of the rank decision
+// from the tolerance, and the bound ||E||_F / gap of the kept subspace's
+// angle within kLzAngleTol (E: the residuals G x - theta x).
+constexpr double kLzTailTol = 1e-6;
+constexpr double kLzAngleTol = 1e-12;
+constexpr int kLzHost = 2 * kLzBasis + 16;  // doubles of the pinned host buffer hl
+}  // namespace
+
+int ttice_state::dense_svd(int64_t rows, int64_t Ncol, const View& vR, bool left, double tol2, int64_t cap,
+                           int64_t* rR_out, double* tail2_out, double* margin_out) {
+  hipStream_t st = stream;
+  const int64_t m = left ? rows : Ncol;
+  const int64_t K = left ? Ncol : rows;
+  const View vRt = transposed(vR);  // Ncol x rows
+  // (m <= 32: one slice, on the matrix-core product kernel)
+  const int32_t kchunk = m <= 32 ? (int32_t)K : gram_kchunk((int32_t)m, K);
+  const int64_t Sg = (K + kchunk - 1) / kchunk;
+  CKS(ensure(gpart, (size_t)Sg * m * m * sizeof(double)));
+  CKS(ensure(gram, (size_t)m * m * sizeof(double)));
+  CKS(ensure(tri, (size_t)(4 * m + sym_eig_ws((int32_t)m)) * sizeof(double)));  // d, e, tau, w, workspace
+  CKS(ensure(order, (size_t)m * sizeof(int32_t)));
+  CKS(ensure(lam, (size_t)m * sizeof(double)));
+  CKS(ensure(tail, (size_t)(m + 1) * sizeof(double)));
+  double* dd = as<double>(tri);
+  double* ee = dd + m;
+  double* tauv = dd + 2 * m;
+  double* wv = dd + 3 * m;
+  CK((gemm<double, double, double>(st, (int32_t)m, (int32_t)m, (int32_t)K, kchunk, 1.0, as<double>(rbuf),
+                                   left ? vR : vRt, as<double>(rbuf), left ? vRt : vR, 0.0, (const double*)nullptr,
+                                   View(), as<double>(gpart), row_major(m), m * m, nullptr, nullptr, gws())));
+  CK(gram_reduce(st, as<double>(gpart), (int32_t)Sg, (int32_t)m, as<double>(gram)));
+  // eigenvalues, then the truncation rank (eq:deltasvd) from them
+  RankSelect sel;
+  sel.cnt = as<int>(tilecnt);  // zero between kernels (the product kernels clear theirs)
+  sel.tol2 = tol2;
+  sel.cap = cap;
+  sel.order = as<int32_t>(order);
+  sel.lam = as<double>(lam);
+  sel.tail = as<double>(tail);
+  sel.res = hs;
+  CK(sym_eigvals(st, (int32_t)m, as<double>(gram), dd, ee, tauv, wv, dd + 4 * m, &sel));
+  CKS(sync_scalars(4));
+  if (hs[3] != 0.0) return TTICE_EDEVICE;
+  const int64_t rR = (int64_t)hs[0];
+  *rR_out = rR;
+  *tail2_out = hs[1];
+  *margin_out = hs[2];
+  if (rR == 0) return TTICE_OK;
+  CKS(ensure(W, (size_t)rows * rR * sizeof(double)));
+  CKS(ensure(W2, (size_t)rows * rR * sizeof(double)));
+  CKS(ensure(eigws, (size_t)sym_eigvecs_ws((int32_t)m, (int32_t)rR) * sizeof(double)));
+  double* Wp = as<double>(W);
+  const View vW = row_major(rR);
+  if (left) {
+    // eigenvectors of R R^T for the r_R largest eigenvalues
+    CK(sym_eigvecs(st, (int32_t)m, (int32_t)rR, dd, ee, wv, as<double>(gram), tauv, as<double>(eigws), Wp, gws()));
+  } else {
+    // U_R = R V_r Sigma_r^{-1} with V_r the eigenvectors of R^T R
+    CKS(ensure(T, (size_t)Ncol * rR * sizeof(double)));
+    CK(sym_eigvecs(st, (int32_t)m, (int32_t)rR, dd, ee, wv, as<double>(gram), tauv, as<double>(eigws),
+                   as<double>(W2), gws()));
+    CK(gather_columns(st, (int32_t)Ncol, (int32_t)rR, as<double>(W2), (int32_t)rR, as<int32_t>(order),
+                      as<double>(lam), true, as<double>(T)));
+    CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)rR, (int32_t)Ncol, (int32_t)Ncol, 1.0,
+                                     as<double>(rbuf), vR, as<double>(T), vW, 0.0, (const double*)nullptr, View(),
+                                     Wp, vW, 0, nullptr, nullptr, gws())));
+  }
+  return TTICE_OK;
+}
+
+// The leading eigenpairs of the residual's Gram matrix G (R R^T when left,
+// else R^T R; m wide, applied as two products with R, never formed) by
+// block Lanczos with full re-orthogonalisation: a pseudo-random start block,
+// Krylov blocks G Q_j orthogonalised against all earlier ones (two
+// classical Gram-Schmidt passes) and orthonormalised by two Cholesky QR
+// passes; then Rayleigh-Ritz on Q^T G Q.  The Ritz values are lower bounds
+// of the leading eigenvalues, and the energy they miss (trace - their sum,
+// the trace being ||R||_F^2) is added to every tail, so the selected r_R is
+// never below the exact one.  The result is accepted (*ok) only when the
+// residuals of the kept Ritz pairs and of the first discarded one certify
+// it (kLz*Tol); otherwise the caller runs the dense solver.
+#ifdef TTICE_EMU_DEBUG
+#define LZ_REJECT                                                          \
+  do {                                                                     \
+    fprintf(stderr, "lanczos m=%ld rejected at line %d\n", (long)m, __LINE__); \
+    return TTICE_OK;                                                       \
+  } while (0)
+#else
+#define LZ_REJECT return TTICE_OK
+#endif
+int ttice_state::lanczos_svd(int level, int64_t rows, int64_t Ncol, const View& vR, bool left, double tol2,
+                             int64_t cap, int64_t* rR_out, double* tail2_out, double* margin_out, bool* ok) {
+  hipStream_t st = stream;
+  *ok = false;
+  ++lz_tries;
+  const int64_t m = left ? rows : Ncol;
+  const int64_t mo = left ? Ncol : rows;  // the other side of R
+  const int32_t b = kLzBlock, sb = kLzBasis;
+  const double* R = as<double>(rbuf);
+  const View vRt = transposed(vR);
+  if (!hl) {
+    if (hipHostMalloc((void**)&hl, kLzHost * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      hl = nullptr;
+      return TTICE_ENOMEM;
+    }
+  }
+  // workspace: basis Q and G Q (m x sb each), two candidate blocks (m x b),
+  // the other-side products (mo x sb), small matrices, Ritz vectors X and
+  // G X (m x sb each), the trace and its partials
+  const int64_t nparts = sumsq_parts(rows * Ncol);
+  const int64_t need = 2 * m * sb + 2 * m * b + mo * sb + (int64_t)sb * b + 3 * (int64_t)sb * sb +
+                       2 * (int64_t)sb * sb + 2 * m * sb + sb + nparts + 8;
+  CKS(ensure(lzw, (size_t)need * sizeof(double)));
+  CKS(ensure(tri, (size_t)(4 * sb + sym_eig_ws(sb)) * sizeof(double)));
+  CKS(ensure(order, (size_t)sb * sizeof(int32_t)));
+  CKS(ensure(lam, (size_t)sb * sizeof(double)));
+  CKS(ensure(tail, (size_t)(sb + 1) * sizeof(double)));
+  double* Q = as<double>(lzw);       // m x sb
+  double* GQ = Q + m * sb;           // m x sb
+  double* V0 = GQ + m * sb;          // m x b
+  double* V1 = V0 + m * b;           // m x b
+  double* T1 = V1 + m * b;           // mo x sb
+  double* P = T1 + mo * sb;          // sb x b
+  double* Sb = P + (int64_t)sb * b;     // b x b (polish: r_R x r_R)
+  double* Li = Sb + (int64_t)sb * sb;   // as Sb
+  double* Spre = Li + (int64_t)sb * sb;  // b x b
+  double* Tm = Spre + (int64_t)sb * sb;  // sb x sb
+  double* Sv = Tm + (int64_t)sb * sb;  // sb x sb (eigenvectors of Tm)
+  double* X = Sv + (int64_t)sb * sb;   // m x sb
+  double* GX = X + m * sb;             // m x sb
+  double* eta2 = GX + m * sb;          // sb
+  double* parts = eta2 + sb;           // nparts
+  double* trace = parts + nparts;      // 1
+  const View q = row_major(sb), vb = row_major(b);
+  auto G = [&](const double* Xin, View vx, int32_t n, double* out, View vo) -> hipError_t {
+    // out = G Xin (m x n): the inner product with R first (mo x n into T1)
+    hipError_t e;
+    if (left) {
+      e = gemm<double, double, double>(st, (int32_t)Ncol, n, (int32_t)rows, (int32_t)rows, 1.0, R, vRt, Xin, vx,
+                                       0.0, (const double*)nullptr, View(), T1, row_major(n), 0, nullptr, nullptr,
+                                       gws());
+      if (e != hipSuccess) return e;
+      return gemm<double, double, double>(st, (int32_t)rows, n, (int32_t)Ncol, (int32_t)Ncol, 1.0, R, vR, T1,
+                                          row_major(n), 0.0, (const double*)nullptr, View(), out, vo, 0, nullptr,
+                                          nullptr, gws());
+    }
+    e = gemm<double, double, double>(st, (int32_t)rows, n, (int32_t)Ncol, (int32_t)Ncol, 1.0, R, vR, Xin, vx, 0.0,
+                                     (const double*)nullptr, View(), T1, row_major(n), 0, nullptr, nullptr, gws());
+    if (e != hipSuccess) return e;
+    return gemm<double, double, double>(st, (int32_t)Ncol, n, (int32_t)rows, (int32_t)rows, 1.0, R, vRt, T1,
+                                        row_major(n), 0.0, (const double*)nullptr, View(), out, vo, 0, nullptr,
+                                        nullptr, gws());
+  };
+  // block j of Q from the candidate block (in, view vin): orthogonalised
+  // against Q's first j blocks, then orthonormalised
+  auto orth_block = [&](int32_t j, const double* in, View vin) -> hipError_t {
+    const int32_t nq = j * b;
+    const double* cur = in;
+    View vcur = vin;
+    hipError_t e = hipSuccess;
+    if (nq > 0) {  // the candidates' Gram block before the projection
+      e = gemm<double, double, double>(st, b, b, (int32_t)m, (int32_t)m, 1.0, in, transposed(vin), in, vin, 0.0,
+                                       (const double*)nullptr, View(), Spre, vb, 0, nullptr, nullptr, gws());
+      if (e != hipSuccess) return e;
+    }
+    for (int pass = 0; pass < 2 && nq > 0; ++pass) {
+      e = gemm<double, double, double>(st, nq, b, (int32_t)m, (int32_t)m, 1.0, Q, transposed(q), cur, vcur, 0.0,
+                                       (const double*)nullptr, View(), P, vb, 0, nullptr, nullptr, gws());
+      if (e != hipSuccess) return e;
+      e = gemm<double, double, double>(st, (int32_t)m, b, nq, nq, -1.0, Q, q, P, vb, 1.0, cur, vcur, V0, vb, 0,
+                                       nullptr, nullptr, gws());
+      if (e != hipSuccess) return e;
+      cur = V0;
+      vcur = vb;
+    }
+    // two Cholesky QR passes: cur -> V1 -> block j of Q
+    for (int pass = 0; pass < 2; ++pass) {
+      e = gemm<double, double, double>(st, b, b, (int32_t)m, (int32_t)m, 1.0, cur, transposed(vcur), cur, vcur, 0.0,
+                                       (const double*)nullptr, View(), Sb, vb, 0, nullptr, nullptr, gws());
+      if (e != hipSuccess) return e;
+      e = chol_inv(st, b, Sb, b, pass == 0 && nq > 0 ? Spre : nullptr, b, Li, b);
+      if (e != hipSuccess) return e;
+      double* dst = pass == 0 ? V1 : Q + (int64_t)j * b;
+      const View vdst = pass == 0 ? vb : q;
+      e = gemm<double, double, double>(st, (int32_t)m, b, b, b, 1.0, cur, vcur, Li, vb, 0.0, (const double*)nullptr,
+                                       View(), dst, vdst, 0, nullptr, nullptr, gws());
+      if (e != hipSuccess) return e;
+      cur = V1;
+      vcur = vb;
+    }
+    return hipSuccess;
+  };
+  CK(sumsq(st, R, rows * Ncol, parts, trace));
+  double* dd = as<double>(tri);
+  double* ee = dd + sb;
+  double* tauv = dd + 2 * sb;
+  double* wv = dd + 3 * sb;
+  RankSelect sel;
+  sel.cnt = as<int>(tilecnt);
+  sel.tol2 = tol2;
+  sel.cap = cap;
+  sel.order = as<int32_t>(order);
+  sel.lam = as<double>(lam);
+  sel.tail = as<double>(tail);
+  sel.res = hs;
+  sel.trace = trace;
+  CK(rand_fill(st, m, b, V0, b, 0x9E3779B9ull + (uint64_t)level));
+  CK(orth_block(0, V0, vb));
+  for (int32_t j = 0; j < kLzSteps; ++j) {
+    CK(G(Q + (int64_t)j * b, q, b, GQ + (int64_t)j * b, q));
+    if (j + 1 < kLzSteps) CK(orth_block(j + 1, GQ + (int64_t)j * b, q));
+  }
+  // Rayleigh-Ritz: Tm = Q^T G Q (symmetrised), its eigenvalues and the rank
+  CK((gemm<double, double, double>(st, sb, sb, (int32_t)m, (int32_t)m, 1.0, Q, transposed(q), GQ, q, 0.0,
+                                   (const double*)nullptr, View(), Tm, q, 0, nullptr, nullptr, gws())));
+  CK(symmetrize(st, sb, Tm, sb));
+  CK(sym_eigvals(st, sb, Tm, dd, ee, tauv, wv, dd + 4 * sb, &sel));
+  CKS(sync_scalars(4));
+  if (hs[3] != 0.0) LZ_REJECT;  // not finite: left to the dense solver
+  const int64_t rR = (int64_t)hs[0];
+  double tail2 = hs[1], margin = hs[2];
+  if (rR >= sb) LZ_REJECT;  // the basis does not hold enough energy
+  if (rR > 0) {
+    // Ritz vectors X = Q S of the kept pairs and of the first discarded
+    // one.  The kept ones carry the rounding of the Krylov blocks (those of
+    // a wide spectrum are ill-conditioned), so one step of subspace
+    // iteration polishes them: Y = G X, orthonormalised (a well-conditioned
+    // block: its columns scale with the kept eigenvalues), and Rayleigh-Ritz
+    // on span(Y).  The first discarded pair (theta, eta) bounds the
+    // discarded eigenvalues by theta + eta.
+    const int32_t kp = (int32_t)rR, kc = kp + 1;
+    const View vc = row_major(kc), vk = row_major(kp);
+    CKS(ensure(eigws, (size_t)sym_eigvecs_ws(sb, kc) * sizeof(double)));
+    CK(sym_eigvecs(st, sb, kc, dd, ee, wv, Tm, tauv, as<double>(eigws), Sv));
+    CK((gemm<double, double, double>(st, (int32_t)m, kc, sb, sb, 1.0, Q, q, Sv, vc, 0.0, (const double*)nullptr,
+                                     View(), X, vc, 0, nullptr, nullptr, gws())));
+    CK(G(X, vc, kc, GX, vc));  // Y
+    // hl: [0, kLzBasis) eta_j^2 and [kLzBasis, 2 kLzBasis) theta_j of the
+    // polished pairs; then eta^2, theta of the first discarded pair; trace
+    double* hd = hl + 2 * kLzBasis;
+    CK(ritz_residuals(st, (int32_t)m, 1, kc, X + kp, GX + kp, wv + kp, hd, hd + 1));
+    CK(hipMemcpyAsync(hd + 2, trace, sizeof(double), hipMemcpyDeviceToHost, st));
+    // two Cholesky QR passes: Y's first r_R columns -> Q (scratch) -> X
+    const double* cur = GX;
+    View vcur = vc;
+    for (int pass = 0; pass < 2; ++pass) {
+      double* dst = pass == 0 ? Q : X;
+      CK((gemm<double, double, double>(st, kp, kp, (int32_t)m, (int32_t)m, 1.0, cur, transposed(vcur), cur, vcur,
+                                       0.0, (const double*)nullptr, View(), Sb, vk, 0, nullptr, nullptr, gws())));
+      CK(chol_inv(st, kp, Sb, kp, nullptr, 0, Li, kp));
+      CK((gemm<double, double, double>(st, (int32_t)m, kp, kp, kp, 1.0, cur, vcur, Li, vk, 0.0,
+                                       (const double*)nullptr, View(), dst, vk, 0, nullptr, nullptr, gws())));
+      cur = dst;
+      vcur = vk;
+    }
+    CK(G(X, vk, kp, GX, vk));  // G Y~
+    CK((gemm<double, double, double>(st, kp, kp, (int32_t)m, (int32_t)m, 1.0, X, transposed(vk), GX, vk, 0.0,
+                                     (const double*)nullptr, View(), Tm, vk, 0, nullptr, nullptr, gws())));
+    CK(symmetrize(st, kp, Tm, kp));
+    CK(sym_eigvals(st, kp, Tm, dd, ee, tauv, wv, dd + 4 * sb, nullptr));
+    CKS(ensure(eigws, (size_t)sym_eigvecs_ws(kp, kp) * sizeof(double)));
+    CK(sym_eigvecs(st, kp, kp, dd, ee, wv, Tm, tauv, as<double>(eigws), Sv));
+    // the polished pairs (X S, G X S) into the free basis buffers
+    CK((gemm<double, double, double>(st, (int32_t)m, kp, kp, kp, 1.0, X, vk, Sv, vk, 0.0, (const double*)nullptr,
+                                     View(), Q, vk, 0, nullptr, nullptr, gws())));
+    CK((gemm<double, double, double>(st, (int32_t)m, kp, kp, kp, 1.0, GX, vk, Sv, vk, 0.0, (const double*)nullptr,
+                                     View(), GQ, vk, 0, nullptr, nullptr, gws())));
+    CK(ritz_residuals(st, (int32_t)m, kp, kp, Q, GQ, wv, hl, hl + kLzBasis));
+    CKS(sync_scalars(0));
+    // the decision again from the polished Ritz values (lower bounds of
+    // the leading eigenvalues, so trace minus their sum bounds every tail
+    // from above): it must agree, and the error bounds of the kept
+    // eigenvalues (sum eta^2 / gap) and of the kept subspace's angle
+    // (||E||_F / gap) must not be able to move it or the result
+    const double* th = hl + kLzBasis;
+    const double trv = hd[2];
+    double esum = 0.0, s_prev = 0.0;
+    for (int32_t j = 0; j < kp; ++j) {
+      const double e2 = hl[j];
+      if (!isfinite(e2) || !isfinite(th[j])) LZ_REJECT;
+      esum += std::max(e2, 0.0);
+      if (j + 1 < kp) s_prev += std::max(th[j], 0.0);
+    }
+    const double t_r = std::max(0.0, trv - (s_prev + std::max(th[kp - 1], 0.0)));
+    const double t_rm1 = std::max(0.0, trv - s_prev);
+    const bool capped = rR == cap;
+    if (!capped && !(t_r <= tol2 && t_rm1 > tol2)) LZ_REJECT;
+    const double t2 = tol2 > 0.0 ? tol2 : 1e-300;
+    margin = std::min(fabs(t_r - tol2), fabs(t_rm1 - tol2)) / t2;
+    tail2 = t_r;
+    const double up = hd[1] + sqrt(std::max(hd[0], 0.0));
+    const double gap = th[kp - 1] - up;
+#ifdef TTICE_EMU_DEBUG
+    fprintf(stderr, "lanczos m=%ld rR=%ld th0=%g esum=%g gap=%g up=%g margin=%g tol2=%g angle=%g\n", (long)m,
+            (long)rR, th[0], esum, gap, up, margin, tol2, sqrt(esum) / gap);
+#endif
+    if (!(th[0] > 0.0) || !(gap > 0.0)) LZ_REJECT;
+    if (!capped && esum / gap > kLzTailTol * margin * tol2) LZ_REJECT;
+    if (sqrt(esum) / gap > kLzAngleTol) LZ_REJECT;
+  }
+  // (r_R = 0 is decided by the trace alone, which is exact)
+  ++lz_accepted;
+  *ok = true;
+  *rR_out = rR;
+  *tail2_out = tail2;
+  *margin_out = margin;
+  if (rR == 0) return TTICE_OK;
+  CKS(ensure(W, (size_t)rows * rR * sizeof(double)));
+  CKS(ensure(W2, (size_t)rows * rR * sizeof(double)));
+  // the polished vectors sit in Q (m x r_R), theta_j (decreasing) in wv
+  if (left) {
+    CK(gather_columns(st, (int32_t)rows, (int32_t)rR, Q, (int32_t)rR, nullptr, wv, false, as<double>(W)));
+  } else {
+    // U_R = R V_r Sigma_r^{-1}
+    CKS(ensure(T, (size_t)Ncol * rR * sizeof(double)));
+    CK(gather_columns(st, (int32_t)Ncol, (int32_t)rR, Q, (int32_t)rR, nullptr, wv, true, as<double>(T)));
+    CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)rR, (int32_t)Ncol, (int32_t)Ncol, 1.0, R, vR,
+                                     as<double>(T), row_major(rR), 0.0, (const double*)nullptr, View(),
+                                     as<double>(W), row_major(rR), 0, nullptr, nullptr, gws())));
+  }
+  return TTICE_OK;
+}
+
 template <typename TIn>
 int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, double tol_in,
                            int64_t* rk_pend, ttice_update_info* info, bool use_occ, double* last_out,
@@ -320,6 +671,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
     const double occupancy = rows > 0 ? (double)r / (double)rows : 1.0;
     const bool occ_skip = use_occ && occupancy >= tau;
     int64_t rR = 0;
+    int32_t solver = 0, rechecked = 0;
     double rho2 = std::numeric_limits<double>::quiet_NaN(), tail2 = 0.0;
     double margin = std::numeric_limits<double>::infinity();
 
@@ -384,12 +736,12 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
 
     if (i == 0 && tol2 < 0) {
       CKS(ensure(fy2, (size_t)N * sizeof(double)));
-      CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, as<double>(fy2)));
+      CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, as<double>(fy2), fscratch(N)));
       CK(total_sum(st, as<double>(fy2), N, hs + 2));
     }
 
     if (!occ_skip) {
-      CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
+      CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres), fscratch(N)));
       CK(total_sum(st, as<double>(fres), N, hs));
       CKS(sync_scalars(4));
       if (i == 0 && tol2 < 0) {
@@ -406,12 +758,13 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         // the reduced-precision energy is within its rounding band of the
         // tolerance: take the decision on the FP64 projection instead
         CK(fused_pass(kProjFP64, false));
-        CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
+        CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres), fscratch(N)));
         CK(total_sum(st, as<double>(fres), N, hs));
         CKS(sync_scalars(4));
         rho2 = hs[0];
         if (hs[1] != 0.0 || !isfinite(rho2)) return TTICE_EINVAL;
         ++lp_rechecks;
+        rechecked = 1;
       }
       rho2 = std::max(rho2, 0.0);
       tail2 = rho2;
@@ -427,71 +780,26 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
                                                  1.0, (const double*)zin, vz, as<double>(rbuf), vr, 0, nullptr,
                                                  nullptr, gws())));
         }
-        // Truncated SVD of R_cat = [R(1) ... R(N)] (eq:svdfirst) via the
-        // eigendecomposition of its Gram matrix: left (rows x rows) when
-        // rows <= N*cols, else right (N*cols x N*cols).
+        // Truncated SVD of R_cat = [R(1) ... R(N)] (eq:svdfirst) from the
+        // eigenpairs of its Gram matrix: left (rows x rows) when rows <=
+        // N*cols, else right (N*cols x N*cols).  A wide Gram matrix first
+        // goes to the block-Lanczos solver (leading eigenpairs only); the
+        // dense solver takes over when that result is not certified.
         const bool left = rows <= Ncol;
         const int64_t m = left ? rows : Ncol;
-        const int64_t K = left ? Ncol : rows;
         // documented size limit of the residual's SVD, checked before any
         // workspace for it is allocated
         if (m > sym_eig_max()) return TTICE_EINVAL;
-        const View vR = vr;                   // rows x Ncol
-        const View vRt = transposed(vr);      // Ncol x rows
-        // (m <= 32: one slice, on the matrix-core product kernel)
-        const int32_t kchunk = m <= 32 ? (int32_t)K : gram_kchunk((int32_t)m, K);
-        const int64_t Sg = (K + kchunk - 1) / kchunk;
-        CKS(ensure(gpart, (size_t)Sg * m * m * sizeof(double)));
-        CKS(ensure(gram, (size_t)m * m * sizeof(double)));
-        CKS(ensure(tri, (size_t)(4 * m + sym_eig_ws((int32_t)m)) * sizeof(double)));  // d, e, tau, w, workspace
-        CKS(ensure(order, (size_t)m * sizeof(int32_t)));
-        CKS(ensure(lam, (size_t)m * sizeof(double)));
-        CKS(ensure(tail, (size_t)(m + 1) * sizeof(double)));
-        double* dd = as<double>(tri);
-        double* ee = dd + m;
-        double* tauv = dd + 2 * m;
-        double* wv = dd + 3 * m;
-        CK((gemm<double, double, double>(st, (int32_t)m, (int32_t)m, (int32_t)K, kchunk, 1.0, as<double>(rbuf),
-                                         left ? vR : vRt, as<double>(rbuf), left ? vRt : vR, 0.0,
-                                         (const double*)nullptr, View(), as<double>(gpart), row_major(m),
-                                         m * m, nullptr, nullptr, gws())));
-        CK(gram_reduce(st, as<double>(gpart), (int32_t)Sg, (int32_t)m, as<double>(gram)));
-        // eigenvalues, then the truncation rank (eq:deltasvd) from them
-        RankSelect sel;
-        sel.cnt = as<int>(tilecnt);  // zero between kernels (the product kernels clear theirs)
-        sel.tol2 = tol2;
-        sel.cap = rows - r;
-        sel.order = as<int32_t>(order);
-        sel.lam = as<double>(lam);
-        sel.tail = as<double>(tail);
-        sel.res = hs;
-        CK(sym_eigvals(st, (int32_t)m, as<double>(gram), dd, ee, tauv, wv, dd + 4 * m, &sel));
-        CKS(sync_scalars(4));
-        if (hs[3] != 0.0) return TTICE_EDEVICE;
-        rR = (int64_t)hs[0];
-        tail2 = hs[1];
-        margin = hs[2];
+        bool have_svd = false;
+        if (lz_mode != 0 && m > (lz_mode == 2 ? (int64_t)kLzBasis : kLzMinM) && last_rR[i] < kLzBasis / 2)
+          CKS(lanczos_svd(i, rows, Ncol, vr, left, tol2, rows - r, &rR, &tail2, &margin, &have_svd));
+        if (!have_svd) CKS(dense_svd(rows, Ncol, vr, left, tol2, rows - r, &rR, &tail2, &margin));
+        last_rR[i] = rR;
+        solver = have_svd ? 2 : 1;
         if (rR > 0) {
-          CKS(ensure(W, (size_t)rows * rR * sizeof(double)));
-          CKS(ensure(W2, (size_t)rows * rR * sizeof(double)));
-          CKS(ensure(eigws, (size_t)sym_eigvecs_ws((int32_t)m, (int32_t)rR) * sizeof(double)));
           double* Wp = as<double>(W);
           double* W2p = as<double>(W2);
           const View vW = row_major(rR);
-          if (left) {
-            // eigenvectors of R R^T for the r_R largest eigenvalues
-            CK(sym_eigvecs(st, (int32_t)m, (int32_t)rR, dd, ee, wv, as<double>(gram), tauv, as<double>(eigws), Wp));
-          } else {
-            // U_R = R V_r Sigma_r^{-1} with V_r the eigenvectors of R^T R
-            CKS(ensure(T, (size_t)Ncol * rR * sizeof(double)));
-            CK(sym_eigvecs(st, (int32_t)m, (int32_t)rR, dd, ee, wv, as<double>(gram), tauv, as<double>(eigws),
-                           as<double>(W2)));
-            CK(gather_columns(st, (int32_t)Ncol, (int32_t)rR, as<double>(W2), (int32_t)rR, as<int32_t>(order),
-                              as<double>(lam), true, as<double>(T)));
-            CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)rR, (int32_t)Ncol, (int32_t)Ncol, 1.0,
-                                             as<double>(rbuf), vR, as<double>(T), vW, 0.0,
-                                             (const double*)nullptr, View(), Wp, vW, 0, nullptr, nullptr, gws())));
-          }
           // Re-orthogonalise against U (two classical Gram-Schmidt passes)
           if (r > 0) {
             CKS(ensure(T, (size_t)std::max<int64_t>(r * rR, Ncol * rR) * sizeof(double)));
@@ -570,6 +878,8 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       info->rho2[i] = rho2;
       info->tail2[i] = occ_skip ? 0.0 : tail2;
       info->margin[i] = margin;
+      info->solver[i] = solver;
+      info->rechecked[i] = rechecked;
     }
     zin = out;
     zin_is_input = false;
@@ -640,9 +950,9 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
                                            gws())));
       }
     }
-    if (bn) CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, y2_out));
+    if (bn) CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, y2_out, fscratch(N)));
     if (err2_out) {
-      CK(frame_sums(st, cp, MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres)));
+      CK(frame_sums(st, cp, MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres), fscratch(N)));
       CK(accumulate(st, err2_out, as<double>(fres), N));
     }
     zin = out;
@@ -855,6 +1165,12 @@ int ttice_set_option(ttice_state* st, int32_t key, const void* val) {
     case TTICE_OPT_STREAM:
       st->stream = *(const hipStream_t*)val;
       return TTICE_OK;
+    case TTICE_OPT_SVD: {
+      const int32_t v = *(const int32_t*)val;
+      if (v < 0 || v > 2) return TTICE_EINVAL;
+      st->lz_mode = v;
+      return TTICE_OK;
+    }
     case TTICE_OPT_PROFILE:
       st->profile = *(const int32_t*)val != 0;
       memset(&st->kstats[0], 0, sizeof(st->kstats[0]));

@@ -22,7 +22,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 ALGO = {"plain": 0, "star": 1}
 SKIP = {"mean": 0, "batch": 1, "none": 2}
-OPT_PREC, OPT_ALGO, OPT_SKIP_RULE, OPT_TAU, OPT_STREAM, OPT_PROFILE = 1, 2, 3, 4, 5, 6
+OPT_PREC, OPT_ALGO, OPT_SKIP_RULE, OPT_TAU, OPT_STREAM, OPT_PROFILE, OPT_SVD = 1, 2, 3, 4, 5, 6, 7
+SVD = {"auto": 1, "dense": 0}
 KERNEL_PROJ_L1 = 0
 F32, F64 = 0, 1
 
@@ -69,6 +70,8 @@ class UpdateInfo(ctypes.Structure):
         ("tail2", ctypes.c_double * TTICE_MAX_D),
         ("margin", ctypes.c_double * TTICE_MAX_D),
         ("achieved2", ctypes.c_double),
+        ("solver", ctypes.c_int32 * TTICE_MAX_D),
+        ("rechecked", ctypes.c_int32 * TTICE_MAX_D),
     ]
 
     def as_dict(self) -> dict:
@@ -79,6 +82,7 @@ class UpdateInfo(ctypes.Structure):
             ranks=list(self.ranks[: d + 2]), rR=list(self.r_new[:d]), rho2=list(self.rho2[:d]),
             tail2=list(self.tail2[:d]), margin=list(self.margin[:d]),
             achieved2=(self.achieved2 if self.achieved2 >= 0 else None),
+            solver=list(self.solver[:d]), rechecked=list(self.rechecked[:d]),
         )
 
 
@@ -187,7 +191,8 @@ class TTICE:
         return self
 
     def __init__(self, dims: Sequence[int], eps: float, prec: str = "fp64", algo: str = "plain",
-                 skip_rule: str = "mean", tau: float = 1.0, stream: Optional[torch.cuda.Stream] = None):
+                 skip_rule: str = "mean", tau: float = 1.0, stream: Optional[torch.cuda.Stream] = None,
+                 svd: str = "auto"):
         L = lib()
         self.dims = tuple(int(n) for n in dims)
         self.d = len(self.dims)
@@ -201,6 +206,7 @@ class TTICE:
         self.set_option(OPT_ALGO, ctypes.c_int32(ALGO[algo]))
         self.set_option(OPT_SKIP_RULE, ctypes.c_int32(SKIP[skip_rule]))
         self.set_option(OPT_TAU, ctypes.c_double(tau))
+        self.set_option(OPT_SVD, ctypes.c_int32(SVD[svd]))
         if stream is not None:
             self.set_option(OPT_STREAM, ctypes.c_void_p(stream.cuda_stream))
 

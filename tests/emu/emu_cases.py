@@ -77,6 +77,34 @@ def case_order1_order2():
     check_stream(EmuTTICE(L, (40, 90), 0.05), Oracle((40, 90), 0.05), sep(12, (40, 90), 6, 7), label="order2")
 
 
+def case_lanczos():
+    """The block-Lanczos truncated SVD (forced for every Gram matrix wider
+    than its 128-vector Krylov basis): a left Gram matrix 150 wide and a
+    right one 180 wide; ranks and reconstructions as the oracle and as the
+    dense solver of the same library, and the solver reported per core."""
+    for dims, batch, n in (((150, 12, 14), 1, 3), ((300, 10, 3), 6, 18)):
+        batches = sep(n, dims, batch, 31, terms=4)
+        g, o = EmuTTICE(L, dims, 0.02, svd=2), Oracle(dims, 0.02)
+        dense = EmuTTICE(L, dims, 0.02, svd=0)
+        used = 0
+        for Y in batches:
+            gi = g.update(Y)
+            di = dense.update(Y)
+            oi = o.update(Y)
+            used += sum(1 for s in gi["solver"] if s == 2)
+            assert all(s != 2 for s in di["solver"])
+            assert gi["ranks"] == di["ranks"] == oi["ranks"], (dims, gi["ranks"], di["ranks"], oi["ranks"])
+        assert used > 0, dims
+        rg, rd, ro = g.reconstruct(), dense.reconstruct(), o.reconstruct()
+        assert np.abs(rg - rd).max() <= 1e-10 * np.abs(rd).max(), dims
+        for b in range(ro.shape[0]):
+            assert np.linalg.norm(rg[b] - ro[b]) <= 1e-10 * np.linalg.norm(ro[b]), (dims, b)
+        for i in range(g.d):
+            U = g.core(i)
+            if U.shape[1]:
+                assert np.abs(U.T @ U - np.eye(U.shape[1])).max() <= 1e-12, (dims, i)
+
+
 def case_star():
     dims, eps = (12, 10, 6), 0.05
     g, o = EmuTTICE(L, dims, eps, algo=1), Oracle(dims, eps, algo="star")
@@ -254,7 +282,7 @@ def case_eigensolver():
             assert min(np.linalg.norm(X[:, c] - EV[:, c]), np.linalg.norm(X[:, c] + EV[:, c])) <= 1e-10, (m, c)
     # many kept vectors (the back-transformation with several columns per
     # wave): separated spectrum, every vector against LAPACK's
-    for m, r in ((40, 12), (96, 40), (128, 70), (200, 40)):
+    for m, r in ((40, 12), (96, 40), (128, 70), (200, 40), (300, 40), (331, 3)):
         Q, _ = np.linalg.qr(rng.standard_normal((m, m)))
         lam = np.linspace(10.0, 1.0, m)
         G = (Q * lam) @ Q.T

@@ -19,6 +19,7 @@ class UpdateInfo(ctypes.Structure):
         ("ranks", ctypes.c_int64 * (TTICE_MAX_D + 2)), ("r_new", ctypes.c_int64 * TTICE_MAX_D),
         ("rho2", ctypes.c_double * TTICE_MAX_D), ("tail2", ctypes.c_double * TTICE_MAX_D),
         ("margin", ctypes.c_double * TTICE_MAX_D), ("achieved2", ctypes.c_double),
+        ("solver", ctypes.c_int32 * TTICE_MAX_D), ("rechecked", ctypes.c_int32 * TTICE_MAX_D),
     ]
 
     def as_dict(self):
@@ -27,7 +28,8 @@ class UpdateInfo(ctypes.Structure):
                     normY2=self.norm_y2, eps_core=self.eps_core, eps_upd=self.eps_upd,
                     ranks=list(self.ranks[: d + 2]), rR=list(self.r_new[:d]), rho2=list(self.rho2[:d]),
                     tail2=list(self.tail2[:d]), margin=list(self.margin[:d]),
-                    achieved2=(self.achieved2 if self.achieved2 >= 0 else None))
+                    achieved2=(self.achieved2 if self.achieved2 >= 0 else None),
+                    solver=list(self.solver[:d]), rechecked=list(self.rechecked[:d]))
 
 
 class EmuError(RuntimeError):
@@ -76,7 +78,7 @@ class EmuTTICE:
 
     owner = True
 
-    def __init__(self, L, dims, eps, algo=0, prec=0, tau=None, skip_rule=None):
+    def __init__(self, L, dims, eps, algo=0, prec=0, tau=None, skip_rule=None, svd=None):
         self.L = L
         self.dims = tuple(dims)
         self.d = len(dims)
@@ -92,6 +94,8 @@ class EmuTTICE:
             self._opt(4, ctypes.c_double(tau))
         if skip_rule is not None:
             self._opt(3, ctypes.c_int32(skip_rule))
+        if svd is not None:
+            self._opt(7, ctypes.c_int32(svd))
 
     def save(self):
         n = ctypes.c_int64()
