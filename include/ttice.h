@@ -41,7 +41,9 @@ enum ttice_status {
   TTICE_EINVAL = -1,  /* bad argument, or a non-finite batch */
   TTICE_ENOMEM = -2,  /* device or host allocation failed */
   TTICE_EDEVICE = -3, /* HIP runtime / kernel launch error */
-  TTICE_ESTATE = -4   /* null or unusable state */
+  TTICE_ESTATE = -4,  /* null or unusable state */
+  TTICE_ESCRATCH = -5 /* ttice_project_noalloc: the request needs more than
+                         its fixed device scratch (32 MiB) */
 };
 
 enum ttice_dtype { TTICE_F32 = 0, TTICE_F64 = 1 };
@@ -188,6 +190,23 @@ int ttice_reconstruct(ttice_state* st, int64_t first, int64_t count, void* out,
  * (device, [n] FP64).  Errors as ttice_update. */
 int ttice_project(ttice_state* st, const void* batch, int64_t n, int32_t dtype,
                   double* coef, double* err2, double* y2);
+
+/* ttice_project without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, outputs and results as
+ * ttice_project (the same kernels); its workspace (level buffers, column
+ * energies, K-split partials and counters) lives in one fixed 32 MiB device
+ * array of the library, set up once per device when the first state is
+ * created on it and held until the process ends.  The cores must already
+ * exist (the state's own memory), and the outputs are caller buffers.
+ * The workspace needs about (2 n prod(dims) + n n_2...n_d) doubles plus
+ * the per-level column partials; a larger request returns TTICE_ESCRATCH
+ * and does nothing.  Every call on a device shares that device's array:
+ * calls that overlap on one device (any states, any host threads or
+ * streams) race and must be serialised by the caller.  Errors: as
+ * ttice_project, and TTICE_ESCRATCH. */
+int ttice_project_noalloc(ttice_state* st, const void* batch, int64_t n, int32_t dtype,
+                          double* coef, double* err2, double* y2);
 
 /* Read the profile of kernel `kernel` (enum ttice_kernel) into *out (host).
  * Errors: ESTATE, EINVAL (unknown kernel or null out). */

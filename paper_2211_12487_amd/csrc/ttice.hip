@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <limits>
+#include <mutex>
 #include <vector>
 
 #include "../../include/ttice.h"
@@ -174,9 +175,19 @@ struct ttice_state {
   template <typename TIn>
   int core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, double tol_in, int64_t* rk_pend,
                 ttice_update_info* info, bool use_occ, double* last_out, int64_t last_ld);
+  // Buffers of chain_project given by the caller instead of the state's
+  // grow-on-demand workspace (the allocation-free projection)
+  struct ChainWs {
+    double* z[2];      // level data, N * P doubles each
+    double* bnorm;     // N * cols(0)
+    double* colpart;   // max over levels of row blocks x columns
+    double* fres;      // N
+    double* fsl;       // N * kFrameSlicesMax
+    GemmWs g;
+  };
   template <typename TIn>
   int chain_project(const TIn* zin0, int64_t N, const int64_t* rks, double* coef_out, int64_t coef_ld,
-                    double* err2_out, double* y2_out, int* nonfinite);
+                    double* err2_out, double* y2_out, int* nonfinite, const ChainWs* cw = nullptr);
   template <typename TIn>
   int update_impl(const TIn* batch, int64_t N, ttice_update_info* info);
   template <typename TD>
@@ -893,11 +904,14 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
 // per-frame ||Y(b)||^2.
 template <typename TIn>
 int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, double* coef_out,
-                               int64_t coef_ld, double* err2_out, double* y2_out, int* nonfinite) {
+                               int64_t coef_ld, double* err2_out, double* y2_out, int* nonfinite,
+                               const ChainWs* cw) {
   hipStream_t st = stream;
   const void* zin = zin0;
   bool zin_is_input = true;
-  if (err2_out) CK(hipMemsetAsync(err2_out, 0, (size_t)N * sizeof(double), st));
+  const GemmWs gw = cw ? cw->g : gws();
+  double* fres_p = nullptr;
+  if (err2_out) CK(zero2d(st, 1, N, err2_out, N));
   for (int i = 0; i < d; ++i) {
     const int64_t rows = rks[i] * dims[i];
     const int64_t cols = this->cols(i);
@@ -906,22 +920,33 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
     Core& Ui = U[i];
     const bool last = (i == d - 1);
     const View vz = unfolding(cols, P);
-    double* out = last ? coef_out : as<double>(z[i % 2]);
+    double* out = last ? coef_out : (cw ? cw->z[i % 2] : as<double>(z[i % 2]));
     const int64_t fs_out = last ? coef_ld : P;
     const View vout = unfolding(cols, fs_out);
     double* bn = nullptr;
     if (i == 0 && y2_out) {
-      CKS(ensure(bnorm, (size_t)Ncol * sizeof(double)));
-      bn = as<double>(bnorm);
+      if (cw) {
+        bn = cw->bnorm;
+      } else {
+        CKS(ensure(bnorm, (size_t)Ncol * sizeof(double)));
+        bn = as<double>(bnorm);
+      }
     }
     const bool fused = proj_fits((int32_t)rows, (int32_t)r) && Ncol >= kFusedMinCols;
     const int32_t MB = fused ? 1 : gemm_row_blocks((int32_t)rows);
     double* cp = nullptr;
     if (err2_out) {
-      CKS(ensure(colpart, (size_t)MB * Ncol * sizeof(double)));
-      CKS(ensure(fres, (size_t)N * sizeof(double)));
-      cp = as<double>(colpart);
+      if (cw) {
+        cp = cw->colpart;
+        fres_p = cw->fres;
+      } else {
+        CKS(ensure(colpart, (size_t)MB * Ncol * sizeof(double)));
+        CKS(ensure(fres, (size_t)N * sizeof(double)));
+        cp = as<double>(colpart);
+        fres_p = as<double>(fres);
+      }
     }
+    double* fsl_p = cw ? cw->fsl : fscratch(N);
     if (fused) {
       if (zin_is_input)
         CK((proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p,
@@ -933,27 +958,27 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
       if (zin_is_input)
         CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
                                    transposed(row_major(Ui.ld)), (const TIn*)zin, vz, 0.0, (const TIn*)nullptr,
-                                   View(), out, vout, 0, nullptr, bn, gws())));
+                                   View(), out, vout, 0, nullptr, bn, gw)));
       else
         CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
                                          transposed(row_major(Ui.ld)), (const double*)zin, vz, 0.0,
-                                         (const double*)nullptr, View(), out, vout, 0, nullptr, bn, gws())));
+                                         (const double*)nullptr, View(), out, vout, 0, nullptr, bn, gw)));
       if (err2_out) {
         if (zin_is_input)
           CK((gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
                                         (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out, vout,
-                                        1.0, (const TIn*)zin, vz, (double*)nullptr, View(), 0, cp, nullptr, gws())));
+                                        1.0, (const TIn*)zin, vz, (double*)nullptr, View(), 0, cp, nullptr, gw)));
         else
           CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
                                            (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out,
                                            vout, 1.0, (const double*)zin, vz, (double*)nullptr, View(), 0, cp, nullptr,
-                                           gws())));
+                                           gw)));
       }
     }
-    if (bn) CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, y2_out, fscratch(N)));
+    if (bn) CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, y2_out, fsl_p));
     if (err2_out) {
-      CK(frame_sums(st, cp, MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres), fscratch(N)));
-      CK(accumulate(st, err2_out, as<double>(fres), N));
+      CK(frame_sums(st, cp, MB, Ncol, (int32_t)cols, (int32_t)N, fres_p, fsl_p));
+      CK(accumulate(st, err2_out, fres_p, N));
     }
     zin = out;
     zin_is_input = false;
@@ -1093,6 +1118,39 @@ int ttice_state::reconstruct_impl(int64_t first, int64_t count, TD* out) {
 }
 
 // ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free projection
+// (ttice_project_noalloc): one statically sized array in every device's
+// copy of the module.  Host code never uses the array's name as an address
+// (on the host it names a stand-in, not device memory): the device address
+// is taken once per device, with that device current, by
+// hipGetSymbolAddress, and only that address is handed to kernels.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on device dev (which must be current).
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return TTICE_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      (void)hipGetLastError();
+      return TTICE_EDEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TTICE_OK;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI (the only symbols the library exports)
 // ---------------------------------------------------------------------------
 #pragma GCC visibility push(default)
@@ -1117,6 +1175,11 @@ int ttice_create(int32_t d, const int64_t* dims, double eps, ttice_state** out) 
   s->eps = eps;
   s->rk[0] = 1;
   if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return TTICE_EDEVICE;
+  }
+  void* scr = nullptr;  // once per device: the allocation-free projection's scratch address
+  if (scratch_address(s->device, &scr) != TTICE_OK) {
     delete s;
     return TTICE_EDEVICE;
   }
@@ -1265,6 +1328,65 @@ int ttice_project(ttice_state* st, const void* batch, int64_t n, int32_t dtype, 
              ? st->chain_project<float>((const float*)batch, n, st->rk, coef, rd, err2, y2, y2 ? &nonfinite : nullptr)
              : st->chain_project<double>((const double*)batch, n, st->rk, coef, rd, err2, y2,
                                          y2 ? &nonfinite : nullptr);
+  }
+  if (rc == TTICE_OK && hipStreamSynchronize(st->stream) != hipSuccess) rc = TTICE_EDEVICE;
+  if (rc == TTICE_OK && nonfinite) rc = TTICE_EINVAL;
+  if (rc != TTICE_OK) (void)hipGetLastError();
+  return rc;
+}
+
+int ttice_project_noalloc(ttice_state* st, const void* batch, int64_t n, int32_t dtype, double* coef,
+                          double* err2, double* y2) {
+  if (!st) return TTICE_ESTATE;
+  if (n < 0 || (n > 0 && (!batch || !coef))) return TTICE_EINVAL;
+  if (dtype != TTICE_F32 && dtype != TTICE_F64) return TTICE_EINVAL;
+  if (n == 0) return TTICE_OK;
+  if (hipSetDevice(st->device) != hipSuccess) return TTICE_EDEVICE;
+  void* base = nullptr;
+  if (scratch_address(st->device, &base) != TTICE_OK) return TTICE_EDEVICE;
+  // carve the scratch (256-byte aligned pieces): level buffers, column
+  // energies and partials, frame sums, product counters, then the rest for
+  // K-split partials
+  const int32_t d = st->d;
+  int64_t cpmax = 1;
+  if (err2) {
+    for (int i = 0; i < d; ++i) {
+      const int64_t rows = st->rk[i] * st->dims[i], Ncol = n * st->cols(i);
+      const bool fused = proj_fits((int32_t)rows, (int32_t)st->rk[i + 1]) && Ncol >= kFusedMinCols;
+      cpmax = std::max<int64_t>(cpmax, (fused ? 1 : gemm_row_blocks((int32_t)rows)) * Ncol);
+    }
+  }
+  const double nd = (double)n;
+  const double need_d = 2.0 * nd * (double)st->P + nd * (double)st->cols(0) + (double)cpmax + nd +
+                        nd * kFrameSlicesMax + (double)(kTileCounters / 2) + 6.0 * 32.0;
+  if (need_d * sizeof(double) > (double)kScratchBytes) return TTICE_ESCRATCH;
+  double* p = (double*)base;
+  auto take = [&](int64_t count) {
+    double* q = p;
+    p += ((count + 31) / 32) * 32;
+    return q;
+  };
+  ttice_state::ChainWs cw;
+  cw.z[0] = take(n * st->P);
+  cw.z[1] = take(n * st->P);
+  cw.bnorm = take(n * st->cols(0));
+  cw.colpart = take(cpmax);
+  cw.fres = take(n);
+  cw.fsl = take(n * kFrameSlicesMax);
+  int* cnt = (int*)take(kTileCounters / 2);
+  const int64_t rest = (int64_t)(kScratchBytes / sizeof(double)) - (int64_t)(p - (double*)base);
+  cw.g = GemmWs{p, std::max<int64_t>(rest, 0), cnt, kTileCounters};
+  // the arrival counters of K-split products start at zero (a fill kernel,
+  // not a memset: callers may capture this call)
+  int rc = zero2d(st->stream, 1, kTileCounters / 2, (double*)cnt, kTileCounters / 2) == hipSuccess ? TTICE_OK
+                                                                                             : TTICE_EDEVICE;
+  int nonfinite = 0;
+  if (rc == TTICE_OK) {
+    const int64_t rd = std::max<int64_t>(st->rk[d], 1);
+    rc = (dtype == TTICE_F32) ? st->chain_project<float>((const float*)batch, n, st->rk, coef, rd, err2, y2,
+                                                         y2 ? &nonfinite : nullptr, &cw)
+                              : st->chain_project<double>((const double*)batch, n, st->rk, coef, rd, err2, y2,
+                                                          y2 ? &nonfinite : nullptr, &cw);
   }
   if (rc == TTICE_OK && hipStreamSynchronize(st->stream) != hipSuccess) rc = TTICE_EDEVICE;
   if (rc == TTICE_OK && nonfinite) rc = TTICE_EINVAL;
@@ -1499,6 +1621,7 @@ const char* ttice_strerror(int code) {
     case TTICE_ENOMEM: return "out of memory";
     case TTICE_EDEVICE: return "HIP device or launch error";
     case TTICE_ESTATE: return "invalid state";
+    case TTICE_ESCRATCH: return "request exceeds the fixed scratch of the allocation-free call";
     default: return "unknown status";
   }
 }

@@ -33,6 +33,7 @@ EXPORTS = [
     "ttice_update",
     "ttice_reconstruct",
     "ttice_project",
+    "ttice_project_noalloc",
     "ttice_reserve",
     "ttice_ranks",
     "ttice_get_core",
@@ -118,6 +119,7 @@ def lib():
     L.ttice_update.argtypes = [c_vp, c_vp, c_i64, c_i32, ctypes.POINTER(UpdateInfo)]
     L.ttice_reconstruct.argtypes = [c_vp, c_i64, c_i64, c_vp, c_i32]
     L.ttice_project.argtypes = [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp]
+    L.ttice_project_noalloc.argtypes = [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp]
     L.ttice_reserve.argtypes = [c_vp, c_i64]
     L.ttice_ranks.argtypes = [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
     L.ttice_get_core.argtypes = [c_vp, c_i32, c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
@@ -241,6 +243,23 @@ class TTICE:
                                    ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(err2.data_ptr()),
                                    ctypes.c_void_p(y2.data_ptr())), "ttice_project")
         return coef[:, :rd], err2, y2
+
+    def project_noalloc(self, Y: torch.Tensor, coef: torch.Tensor, err2: Optional[torch.Tensor] = None,
+                        y2: Optional[torch.Tensor] = None) -> None:
+        """ttice_project_noalloc into caller buffers: coef [n, max(r_d, 1)] FP64,
+        err2 / y2 [n] FP64 or None (the library allocates nothing)."""
+        if not Y.is_cuda or not Y.is_contiguous() or tuple(Y.shape[1:]) != self.dims:
+            raise ValueError("batch must be a contiguous device tensor of shape (n, *dims)")
+        n = Y.shape[0]
+        rd = max(self.ranks()[self.d], 1)
+        if coef.dtype != torch.float64 or not coef.is_contiguous() or coef.numel() < n * rd:
+            raise ValueError("coef must be a contiguous FP64 buffer of n * max(r_d, 1) values")
+        for t in (err2, y2):
+            if t is not None and (t.dtype != torch.float64 or t.numel() < n):
+                raise ValueError("err2 / y2 must be FP64 buffers of n values")
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+        _check(lib().ttice_project_noalloc(self._h, ctypes.c_void_p(Y.data_ptr()), n, _dtype_code(Y.dtype),
+                                           ptr(coef), ptr(err2), ptr(y2)), "ttice_project_noalloc")
 
     def reconstruct(self, first: int = 0, count: Optional[int] = None,
                     dtype: torch.dtype = torch.float64, device=None) -> torch.Tensor:

@@ -26,6 +26,8 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+#define __align__(n) alignas(n)
+#define HIP_SYMBOL(x) ((const void*)&(x))
 #define HIP_DYNAMIC_SHARED(type, name) type* name = (type*)hipemu::dyn_lds()
 
 struct dim3 {
@@ -164,6 +166,11 @@ hipError_t hipGetLastError();
 hipError_t hipGetDevice(int* d);
 hipError_t hipSetDevice(int d);
 hipError_t hipFuncSetAttribute(const void* f, hipFuncAttribute a, int v);
+// a __device__ variable is host memory here: its address is the symbol's
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+  *p = const_cast<void*>(sym);
+  return hipSuccess;
+}
 hipError_t hipEventCreate(hipEvent_t* e);
 hipError_t hipEventDestroy(hipEvent_t e);
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s = nullptr);
