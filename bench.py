@@ -1,15 +1,28 @@
-"""Benchmark: TT-ICE stream compression throughput on one MI355X.
+"""Benchmark: TT-ICE stream throughput on one MI355X.
 
-Workload (the video-shaped stream): 2048 FP32 frames of 240x320x3 arriving
-in increments of 32, eps = 0.1 (fixed rank-8 separable background, four
-moving Gaussian blobs, N(0, 1e-2) noise; seeded).  One step = the whole
-stream compressed from empty cores (64 ttice_update calls), with every
-increment already resident in HBM.  value = tensors/s = 2048 * steps /
-(summed wall time of the steps).
+Headline workload (the largest single-GPU configuration): the high-order
+reshaped stream.  4096 FP32 snapshots of a 256^3 scalar field (512 random
+Fourier modes with integer k in [-16, 16]^3, amplitudes |k|^-3, phases
+advancing linearly in time; seeded), each reshaped C-order to 8^8, arrive in
+increments of 8 (512 increments); eps = 0.005; TT-ICE* (Algorithm 2, mean
+skip rule) from empty cores.  Each increment (537 MB) is generated on the
+device before its update, outside the timed region, so it is resident in
+HBM when its update starts.
 
-Both arms run at the same eps and must reach the same TT-ranks: the chosen
-precision (--prec, default split-BF16 matrix-core projections; the residual
-SVD is FP64 in every arm) and the plain FP64 path.
+A step is one increment: one ttice_update call, the whole hot path over one
+batch.  Every arm runs the whole 512-increment stream; exactly K of its
+update calls (--steps, all 512 by default) are timed, at uniformly spaced
+positions of the stream, each between device synchronisations (the call is
+host-synchronous); value = 8 K / (their summed wall time).
+full_stream_tensors_per_s = 4096 / (summed wall time of all 512 calls).
+--warmup W runs the first W increments on a throwaway state first.
+
+Arms: the chosen precision (--prec, default FP32 matrix-core level
+products: the projections of the update, the TT-ICE* chain and the
+next-level data; ||Y||, the residual's SVD, the re-orthogonalisation and
+every rank decision stay FP64) and the plain FP64 path, same eps and
+algorithm.  The video-shaped stream (2048 frames of 240x320x3 in increments
+of 32, eps = 0.1, Algorithm 1) is reported beside it.
 """
 import argparse
 import json
@@ -23,25 +36,28 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = dict(name="video240", dims=(240, 320, 3), eps=0.1, frames=2048, batch=32, seed=0)
+FIELD = dict(name="field256-8way", grid=256, modes=512, kmax=16, decay=3.0, snapshots=4096, batch=8, eps=0.005,
+             seed=0, dims=(8,) * 8)
+VIDEO = dict(name="video240", dims=(240, 320, 3), eps=0.1, frames=2048, batch=32, seed=0)
 HBM_PEAK_GBS = 8000.0
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
-                    help="arithmetic of the level projections in the chosen arm (the residual SVD is FP64)")
-    ap.add_argument("--frames", type=int, default=WORKLOAD["frames"])
-    ap.add_argument("--cpu-increments", type=int, default=6,
-                    help="increments of the stream the CPU oracle baseline compresses")
+    ap.add_argument("--steps", type=int, default=512,
+                    help="timed update calls, spread uniformly over the stream (512 = all of them)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"],
+                    help="arithmetic of the level products in the chosen arm")
+    ap.add_argument("--snapshots", type=int, default=FIELD["snapshots"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-arm", action="store_true")
-    ap.add_argument("--workload", default="video240", choices=["video240", "serving", "ablation", "gel"],
-                    help="video240: the headline stream (default); serving: the many-stream mix, reported "
-                         "as arrival-to-completion latency")
+    ap.add_argument("--no-video", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--workload", default="field256", choices=["field256", "video240", "serving", "ablation", "gel"],
+                    help="field256: the headline stream (default); video240: the video-shaped stream alone; "
+                         "serving: the many-stream mix, reported as arrival-to-completion latency")
     ap.add_argument("--eps", type=float, default=None, help="ablation / gel: eps_des (default 0.1 / 0.01)")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: length of the arrival trace")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrivals per second")
@@ -53,50 +69,87 @@ def parse():
     return ap.parse_args()
 
 
-def gen_stream(frames):
+def field_source():
     from paper_2211_12487_amd import synth
-    w = WORKLOAD
-    return np.concatenate(list(synth.video_stream(frames, w["batch"], seed=w["seed"])))
+    w = FIELD
+    gen = synth.DeviceFourierField(grid=w["grid"], components=1, n_modes=w["modes"], kmax=w["kmax"],
+                                   decay=w["decay"], seed=w["seed"])
+    N, dims = w["batch"], w["dims"]
+
+    def increment(k):
+        return gen.snapshots(k * N, N).reshape((N,) + dims).contiguous()
+    return increment
 
 
-def run_stream(Yd, prec, batch, eps, dims, lat=None, kstats=None):
-    from paper_2211_12487_amd.ttice import TTICE
-    g = TTICE(dims, eps, prec=prec)
-    if kstats is not None:
-        g.profile(True)
-    info = None
-    for k in range(0, Yd.shape[0], batch):
-        t0 = time.perf_counter()
-        info = g.update(Yd[k:k + batch])
-        if lat is not None:
-            lat.append(time.perf_counter() - t0)
-    ranks = g.ranks()
-    if kstats is not None:
-        ks = g.kernel_stats()
-        for key in ks:
-            kstats[key] = kstats.get(key, 0) + ks[key]
-    g.close()
-    return ranks, info
+def timed_positions(n_inc, k):
+    """The K timed increments: all of them when K >= n_inc, else K uniformly
+    spaced positions (the centres of K equal parts of the stream)."""
+    if k >= n_inc:
+        return set(range(n_inc))
+    return {int((j + 0.5) * n_inc / k) for j in range(k)}
 
 
-def time_arm(Yd, prec, steps, warmup):
+def run_field_arm(increment, n_inc, prec, steps, warmup):
+    """One arm over the whole stream: per-increment update wall times, the
+    timed subset, final ranks, skipped increments, FP64 rechecks and the
+    level-1 projection kernel's event timings."""
     import torch
-    w = WORKLOAD
-    for _ in range(warmup):
-        run_stream(Yd, prec, w["batch"], w["eps"], w["dims"])
-    lat = []
-    kstats = {}
+    from paper_2211_12487_amd.ttice import TTICE
+    w = FIELD
+    if warmup > 0:
+        g = TTICE(w["dims"], w["eps"], prec=prec, algo="star")
+        for k in range(warmup):
+            g.update(increment(k))
+        g.close()
+    g = TTICE(w["dims"], w["eps"], prec=prec, algo="star")
+    g.profile(True)
+    pos = timed_positions(n_inc, steps)
+    lat, timed = [], []
+    skipped = rechecks = 0
+    for k in range(n_inc):
+        Y = increment(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = g.update(Y)
+        dt = time.perf_counter() - t0
+        lat.append(dt)
+        if k in pos:
+            timed.append(dt)
+        skipped += int(info["skipped"])
+        rechecks += int(info["star_rechecked"])
+        del Y
+        if k % 64 == 63:
+            print(f"  {prec}: {k + 1}/{n_inc} increments, {sum(lat):.2f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ranks = None
-    for _ in range(steps):
-        ranks, _ = run_stream(Yd, prec, w["batch"], w["eps"], w["dims"], lat, kstats)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    total = t1 - t0
-    return dict(seconds=total, tensors_per_s=Yd.shape[0] * steps / total, ranks=ranks,
+    ks = g.kernel_stats()
+    ranks = g.ranks()
+    g.close()
+    N = w["batch"]
+    return dict(value=N * len(timed) / sum(timed), timed=len(timed), timed_seconds=sum(timed),
+                full_stream_tensors_per_s=N * n_inc / sum(lat), seconds=sum(lat),
                 p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-                kstats=kstats)
+                ranks=ranks, skipped=skipped, fp64_rechecks=rechecks, kstats=ks)
+
+
+def run_video(prec):
+    """The video-shaped stream once (Algorithm 1 from empty cores): tensors/s
+    and final ranks."""
+    import torch
+    from paper_2211_12487_amd import synth
+    from paper_2211_12487_amd.ttice import TTICE
+    w = VIDEO
+    Y = torch.from_numpy(np.concatenate(list(synth.video_stream(w["frames"], w["batch"], seed=w["seed"])))).cuda()
+    for rep in range(2):  # the first pass loads and allocates
+        g = TTICE(w["dims"], w["eps"], prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(0, w["frames"], w["batch"]):
+            g.update(Y[k:k + w["batch"]])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ranks = g.ranks()
+        g.close()
+    return dict(tensors_per_s=w["frames"] / dt, seconds=dt, ranks=ranks)
 
 
 # level-1 projection kernel of each arm: (name, source file)
@@ -108,12 +161,13 @@ PROJ_KERNEL = {
 
 
 def measured_traffic(prec):
-    """HBM bytes per launch of the arm's projection kernel from the committed
-    counter summary, or None when that summary is missing or was taken on
-    another revision of the kernel's source."""
+    """HBM bytes per launch of the arm's level-1 projection kernel on the
+    headline stream from the committed counter summary, or None when that
+    summary is missing or was taken on another revision of the kernel's
+    source."""
     import hashlib
     name, src_file = PROJ_KERNEL[prec]
-    path = os.path.join(ROOT, "profiles", f"{name}_video240_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{name}_field256_traffic.txt")
     try:
         fields = dict(line.split(":", 1) for line in open(path).read().splitlines()
                       if ":" in line and not line.startswith("#"))
@@ -127,10 +181,10 @@ def measured_traffic(prec):
 
 
 def roofline(kstats, prec):
-    """Level-1 fused projection kernel (U_1^T Y, ||Y(b)||^2 and the residual
-    energy in one pass): algorithmic bytes per launch = the increment read
-    once + the r_1 coefficient rows written; duration = mean of its HIP-event
-    timed launches in the timed region."""
+    """Level-1 projection kernel (U_1^T Y and ||Y(b)||^2 in one pass over the
+    increment): algorithmic bytes per launch = the increment read once + the
+    r_1 coefficient rows written (FP64); duration = mean of its launches'
+    own start/end events over the stream."""
     n = kstats.get("launches", 0)
     if not n:
         return None
@@ -139,23 +193,33 @@ def roofline(kstats, prec):
     achieved = bytes_per_launch / avg_s / 1e9
     return dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                 traffic=measured_traffic(prec),
-                kernel=f"{PROJ_KERNEL[prec][0]} (level-1 projection + residual energy, {prec} products)",
+                kernel=f"{PROJ_KERNEL[prec][0]} (level-1 projection, {prec} products)",
                 launches=n, avg_us=avg_s * 1e6, bytes_per_launch=bytes_per_launch)
 
 
-def cpu_baseline(Y, n_inc):
-    """The FP64 NumPy oracle on the first n_inc increments of the same stream."""
+def cpu_baseline():
+    """The FP64 NumPy oracle on a bounded sample of the headline stream: its
+    first increment (8 snapshots) from empty cores, the same seeded field
+    drawn on the host."""
     from oracle import TTICE as Oracle
-    w = WORKLOAD
-    o = Oracle(w["dims"], w["eps"])
+    from paper_2211_12487_amd import synth
+    w = FIELD
+    Y = next(synth.fourier_field_stream(w["batch"], w["batch"], grid=w["grid"], components=1, n_modes=w["modes"],
+                                        kmax=w["kmax"], decay=w["decay"], seed=w["seed"]))
+    Y = Y.reshape((w["batch"],) + w["dims"])
+    o = Oracle(w["dims"], w["eps"], algo="star")
     t0 = time.perf_counter()
-    for k in range(n_inc):
-        o.update(Y[k * w["batch"]:(k + 1) * w["batch"]])
+    o.update(Y)
     dt = time.perf_counter() - t0
     cores = len(os.sched_getaffinity(0))
-    return dict(value=n_inc * w["batch"] / dt, unit="tensors/s", cores=cores, kind="oracle",
-                sample=f"first {n_inc} increments ({n_inc * w['batch']} frames) of the stream, "
-                       f"NumPy FP64 + LAPACK, BLAS threads up to {cores}", seconds=dt)
+    try:
+        from threadpoolctl import threadpool_info
+        blas = ",".join(sorted({i.get("internal_api", "?") for i in threadpool_info()}))
+    except Exception:  # pragma: no cover
+        blas = "unknown"
+    return dict(value=w["batch"] / dt, unit="tensors/s", cores=cores, kind="oracle", blas=blas,
+                sample=f"first increment ({w['batch']} snapshots, 537 MB) of the stream from empty cores, NumPy FP64 "
+                       f"+ LAPACK, BLAS threads up to {cores}", seconds=dt)
 
 
 SERVING_SHAPES = [(32, 32, 3), (64, 64, 3), (128, 128, 3), (32, 32, 32)]
@@ -387,42 +451,65 @@ def main():
     if a.workload == "gel":
         print(json.dumps(gel(a)), flush=True)
         return
-    w = WORKLOAD
-    print(f"generating {a.frames} frames", file=sys.stderr, flush=True)
-    Y = gen_stream(a.frames)
-    Yd = torch.from_numpy(Y).cuda()
-    torch.cuda.synchronize()
-    print("timing chosen arm", file=sys.stderr, flush=True)
-    chosen = time_arm(Yd, a.prec, a.steps, a.warmup)
+    if a.workload == "video240":
+        print(json.dumps(dict(chosen=run_video(a.prec), fp64=run_video("fp64"))), flush=True)
+        return
+    w = FIELD
+    n_inc = (a.snapshots + w["batch"] - 1) // w["batch"]
+    increment = field_source()
+    print(f"field256: {n_inc} increments of {w['batch']} snapshots, timing the {a.prec} arm", file=sys.stderr,
+          flush=True)
+    chosen = run_field_arm(increment, n_inc, a.prec, a.steps, a.warmup)
     if a.copy_calibration:
-        inc = Yd[:w["batch"]]
+        inc = increment(0)
         dst = torch.empty_like(inc)
         for _ in range(3):
             dst.copy_(inc)
         torch.cuda.synchronize()
         print(f"copy calibration: 3 device copies of {inc.numel() * inc.element_size()} bytes", file=sys.stderr,
               flush=True)
+        del inc, dst
     fp64 = None
     if not a.no_fp64_arm and a.prec != "fp64":
-        print("timing fp64 arm", file=sys.stderr, flush=True)
-        fp64 = time_arm(Yd, "fp64", a.steps, a.warmup)
-        assert fp64["ranks"] == chosen["ranks"], (fp64["ranks"], chosen["ranks"])
+        print("timing the fp64 arm", file=sys.stderr, flush=True)
+        fp64 = run_field_arm(increment, n_inc, "fp64", a.steps, a.warmup)
+    video = None
+    if not a.no_video:
+        print("video240: both arms", file=sys.stderr, flush=True)
+        video = dict(chosen=run_video(a.prec), fp64=run_video("fp64"))
+    serve = None
+    if not a.no_serving:
+        print("serving mix", file=sys.stderr, flush=True)
+        sa = argparse.Namespace(**vars(a))
+        sa.seconds = min(a.seconds, 5.0)
+        serve = serving(sa)
     cpu = None
     if not a.no_cpu_baseline:
-        print("timing cpu oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(Y, a.cpu_increments)
-    ms_per_step = chosen["seconds"] / a.steps * 1e3
+        print("timing the cpu oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
     out = dict(
         metric="tensors/s at fixed eps (chosen precision vs plain FP64), % HBM roofline, p99 update latency",
-        value=chosen["tensors_per_s"], unit="tensors/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
-        ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype={"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[a.prec], data="synthetic",
-        config=dict(workload=f"{w['name']}: {a.frames} frames 240x320x3 fp32, increments of {w['batch']}, "
-                             f"eps={w['eps']}, TT-ICE (Algorithm 1) from empty cores",
-                    frames=a.frames, batch=w["batch"], eps=w["eps"], prec=a.prec),
-        final_ranks=chosen["ranks"], p50_update_ms=chosen["p50_ms"], p99_update_ms=chosen["p99_ms"],
-        fp64_arm=(dict(value=fp64["tensors_per_s"], p50_update_ms=fp64["p50_ms"], p99_update_ms=fp64["p99_ms"])
-                  if fp64 else None),
+        value=chosen["value"], unit="tensors/s", n_gpus=1, steps=chosen["timed"], warmup=a.warmup,
+        ms_per_step=chosen["timed_seconds"] / chosen["timed"] * 1e3, higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype={"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[a.prec], data="synthetic",
+        config=dict(workload=f"{w['name']}: {n_inc * w['batch']} fp32 snapshots of a 256^3 field (512 Fourier modes, "
+                             f"|k|^-3, k in [-16,16]^3) reshaped to 8^8, increments of {w['batch']}, eps={w['eps']}, "
+                             f"TT-ICE* (Algorithm 2, mean rule) from empty cores",
+                    snapshots=n_inc * w["batch"], batch=w["batch"], eps=w["eps"], prec=a.prec),
+        full_stream_tensors_per_s=chosen["full_stream_tensors_per_s"], stream_seconds=chosen["seconds"],
+        final_ranks=chosen["ranks"], skipped_increments=chosen["skipped"], fp64_rechecks=chosen["fp64_rechecks"],
+        p50_update_ms=chosen["p50_ms"], p99_update_ms=chosen["p99_ms"],
+        fp64_arm=(dict(value=fp64["value"], full_stream_tensors_per_s=fp64["full_stream_tensors_per_s"],
+                       stream_seconds=fp64["seconds"], final_ranks=fp64["ranks"],
+                       skipped_increments=fp64["skipped"], p50_update_ms=fp64["p50_ms"],
+                       p99_update_ms=fp64["p99_ms"]) if fp64 else None),
+        speedup_vs_fp64=(chosen["full_stream_tensors_per_s"] / fp64["full_stream_tensors_per_s"] if fp64 else None),
+        video240=(dict(chosen_tensors_per_s=video["chosen"]["tensors_per_s"],
+                       fp64_tensors_per_s=video["fp64"]["tensors_per_s"], ranks=video["chosen"]["ranks"],
+                       fp64_ranks=video["fp64"]["ranks"]) if video else None),
+        serving=(dict(p50_ms=serve["p50_ms"], p99_ms=serve["p99_ms"], steady_p99_ms=serve["steady_p99_ms"],
+                      tensors_per_s=serve["tensors_per_s"], workload=serve["config"]["workload"])
+                 if serve else None),
         roofline=roofline(chosen["kstats"], a.prec),
         cpu_baseline=cpu,
     )

@@ -1,0 +1,57 @@
+// Matrix-core tiled products (gemm_mx.h): the FP64 instantiations and the
+// launcher behind gemm()'s route for large level contractions.
+#include "gemm_mx.h"
+
+namespace ttice {
+
+template <int P, typename TB, typename TE, typename TD>
+hipError_t launch_gemm_mx(hipStream_t st, int32_t M, int32_t N, int32_t K, double alpha, const double* A, View va,
+                          const TB* B, View vb, double beta, const TE* E, View ve, TD* D, View vd,
+                          double* colpart) {
+  constexpr size_t lds = mx::lds_bytes<P>();
+  static const hipError_t attr = hipFuncSetAttribute((const void*)mx::k_gemm_mx<P, TB, TE, TD>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  const dim3 grid((unsigned)((N + mx::BN - 1) / mx::BN), (unsigned)((M + mx::BM - 1) / mx::BM));
+  hipLaunchKernelGGL((mx::k_gemm_mx<P, TB, TE, TD>), grid, dim3(mx::kThreads), lds, st, M, N, K, alpha, A, va, B,
+                     vb, beta, E, ve, D, vd, colpart);
+  return hipGetLastError();
+}
+
+bool gemm_mx_fits(int32_t M, int32_t N, int32_t K, const View& va, const View& vb, const View& ve, const View& vd,
+                  bool has_e, bool has_d, bool bnorm) {
+  if (bnorm || M <= 0 || N <= 0 || K <= 0) return false;
+  if (va.rpf != kUnframed || va.cpf != kUnframed || vb.rpf != kUnframed) return false;
+  if ((has_e && ve.rpf != kUnframed) || (has_d && vd.rpf != kUnframed)) return false;
+  // enough output tiles to fill the device without splitting K
+  const int64_t tiles = (int64_t)((N + mx::BN - 1) / mx::BN) * ((M + mx::BM - 1) / mx::BM);
+  return tiles >= 96 && (int64_t)M * N * (int64_t)K >= ((int64_t)1 << 24);
+}
+
+template <typename TB, typename TE, typename TD>
+hipError_t gemm_mx(hipStream_t st, int prec, int32_t M, int32_t N, int32_t K, double alpha, const double* A,
+                   View va, const TB* B, View vb, double beta, const TE* E, View ve, TD* D, View vd,
+                   double* colpart) {
+  if (prec == kProjBF16x3)
+    return gemm_mx_bf3<TB, TE, TD>(st, M, N, K, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart);
+  if (prec == kProjFP32)
+    return gemm_mx_f32<TB, TE, TD>(st, M, N, K, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart);
+  return launch_gemm_mx<mx::kMxF64, TB, TE, TD>(st, M, N, K, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart);
+}
+
+#define TTICE_GEMM_MX_INST(TB, TE, TD)                                                                          \
+  template hipError_t gemm_mx<TB, TE, TD>(hipStream_t, int, int32_t, int32_t, int32_t, double, const double*,   \
+                                          View, const TB*, View, double, const TE*, View, TD*, View, double*); \
+  template hipError_t launch_gemm_mx<mx::kMxF64, TB, TE, TD>(hipStream_t, int32_t, int32_t, int32_t, double,   \
+                                                             const double*, View, const TB*, View, double,      \
+                                                             const TE*, View, TD*, View, double*);
+TTICE_GEMM_MX_INST(double, double, double)
+TTICE_GEMM_MX_INST(float, double, double)
+TTICE_GEMM_MX_INST(double, float, double)
+TTICE_GEMM_MX_INST(float, float, double)
+TTICE_GEMM_MX_INST(double, double, float)
+TTICE_GEMM_MX_INST(float, float, float)
+TTICE_GEMM_MX_INST(double, float, float)
+TTICE_GEMM_MX_INST(float, double, float)
+
+}  // namespace ttice

@@ -116,12 +116,32 @@ struct GemmWs {
 // split over K into partial sums in ws (if given and large enough) and
 // finished by a second kernel that applies alpha, beta*E and colpart; the
 // result does not depend on the split (fixed summation order per split).
+// prec (kProj*): the arithmetic of large products that fit gemm_mx; every
+// other product is FP64.
 template <typename TB, typename TE, typename TD>
 hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk, double alpha,
                 const double* A, View va, const TB* B, View vb, double beta, const TE* E, View ve,
-                TD* D, View vd, int64_t dz, double* colpart, double* bnorm, GemmWs ws = GemmWs());
+                TD* D, View vd, int64_t dz, double* colpart, double* bnorm, GemmWs ws = GemmWs(),
+                int prec = 0);
 
 inline int32_t gemm_row_blocks(int32_t M) { return M > 0 ? (M + 63) / 64 : 1; }
+
+// The matrix-core tiled product (gemm_mx.h) that gemm() takes for large
+// level contractions: FP64 (prec kProjFP64), FP32 (kProjFP32) or split
+// BF16 (kProjBF16x3).
+// gemm_mx_fits: the shape and views it supports without a K split.
+bool gemm_mx_fits(int32_t M, int32_t N, int32_t K, const View& va, const View& vb, const View& ve, const View& vd,
+                  bool has_e, bool has_d, bool bnorm);
+template <typename TB, typename TE, typename TD>
+hipError_t gemm_mx(hipStream_t st, int prec, int32_t M, int32_t N, int32_t K, double alpha, const double* A,
+                   View va, const TB* B, View vb, double beta, const TE* E, View ve, TD* D, View vd,
+                   double* colpart);
+template <typename TB, typename TE, typename TD>
+hipError_t gemm_mx_bf3(hipStream_t st, int32_t M, int32_t N, int32_t K, double alpha, const double* A, View va,
+                       const TB* B, View vb, double beta, const TE* E, View ve, TD* D, View vd, double* colpart);
+template <typename TB, typename TE, typename TD>
+hipError_t gemm_mx_f32(hipStream_t st, int32_t M, int32_t N, int32_t K, double alpha, const double* A, View va,
+                       const TB* B, View vb, double beta, const TE* E, View ve, TD* D, View vd, double* colpart);
 
 // out[f] = sum_{mb<MB} sum_{c<cpf} part[mb*ld + f*cpf + c], f < F, in a
 // fixed order.  scratch (F * kFrameSlicesMax doubles, or null: one block per
@@ -132,6 +152,10 @@ hipError_t frame_sums(hipStream_t st, const double* part, int32_t MB, int64_t ld
                       int32_t F, double* out, double* scratch);
 // out[0] = sum_{i<n} x[i] (deterministic order); out[1] = 1 if any x is not finite.
 hipError_t total_sum(hipStream_t st, const double* x, int64_t n, double* out);
+// err2[b] = max(0, y2[b] - ||c(b, 0:r)||^2) for N frames (c row b at ld):
+// the chain's residual energy by the telescoping identity (FP64 path)
+hipError_t telescope(hipStream_t st, int32_t N, int32_t r, const double* c, int64_t ld, const double* y2,
+                     double* err2);
 // acc[i] += x[i]
 hipError_t accumulate(hipStream_t st, double* acc, const double* x, int64_t n);
 
@@ -199,7 +223,9 @@ hipError_t zero2d(hipStream_t st, int64_t rows, int64_t cols, double* dst, int64
 // Algorithm 2 decision from per-frame squared errors e2[b] (old cores) and
 // norms y2[b]: res[0] = mean relative error, res[1] = batch relative error,
 // res[2] = sum e2 over D_C (frames with rel <= eps), res[3] = ||D||^2,
-// res[4] = |D|, res[5] = ||Y||^2; dlist = indices of D in increasing order.
+// res[4] = |D|, res[5] = ||Y||^2, res[6] = the smallest relative distance
+// |x / eps - 1| of the mean, the batch and every frame's relative error x;
+// dlist = indices of D in increasing order.
 hipError_t star_decide(hipStream_t st, int32_t N, const double* e2, const double* y2, double eps,
                        int32_t* dlist, double* res);
 

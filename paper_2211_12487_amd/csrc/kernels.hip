@@ -439,6 +439,7 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(int32_t M, int32_t N, int32
 // ---------------------------------------------------------------------------
 // Deterministic reductions
 // ---------------------------------------------------------------------------
+extern "C" __device__ double __ockl_wfred_add_f64(double);
 __device__ double block_sum_256(double v, double* red) {
   const int t = threadIdx.x;
   red[t] = v;
@@ -500,6 +501,21 @@ __global__ __launch_bounds__(256) void k_total_sum(const double* __restrict__ x,
     out[0] = tot;
     out[1] = nb > 0 ? 1.0 : 0.0;
   }
+}
+
+// err2[b] = max(0, y2[b] - sum_j c[b ld + j]^2), one wave per frame
+__global__ __launch_bounds__(256) void k_telescope(int32_t N, int32_t r, const double* __restrict__ c, int64_t ld,
+                                                   const double* __restrict__ y2, double* __restrict__ err2) {
+  const int32_t b = (int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6);
+  if (b >= N) return;  // uniform over the wave
+  const int l = threadIdx.x & 63;
+  double s = 0.0;
+  for (int32_t j = l; j < r; j += 64) {
+    const double v = c[(int64_t)b * ld + j];
+    s = fma(v, v, s);
+  }
+  s = __ockl_wfred_add_f64(s);
+  if (l == 0) err2[b] = fmax(0.0, y2[b] - s);
 }
 
 __global__ void k_accumulate(double* __restrict__ acc, const double* __restrict__ x, int64_t n) {
@@ -607,11 +623,12 @@ __global__ __launch_bounds__(256) void k_star_decide(int32_t N, const double* __
                                                      int32_t* __restrict__ dlist,
                                                      double* __restrict__ res) {
   __shared__ double red[256];
-  double srel = 0.0, se = 0.0, sy = 0.0, sdc = 0.0, sd = 0.0, cnt = 0.0;
+  double srel = 0.0, se = 0.0, sy = 0.0, sdc = 0.0, sd = 0.0, cnt = 0.0, near = 1e300;
   for (int32_t b = threadIdx.x; b < N; b += 256) {
     const double e = e2[b] > 0.0 ? e2[b] : 0.0;
     const double y = y2[b];
     const double rel = y > 0.0 ? sqrt(e / y) : 0.0;
+    if (y > 0.0) near = fmin(near, fabs(rel / eps - 1.0));
     srel += rel;
     se += e;
     sy += y;
@@ -628,9 +645,18 @@ __global__ __launch_bounds__(256) void k_star_decide(int32_t N, const double* __
   sdc = block_sum_256(sdc, red);
   sd = block_sum_256(sd, red);
   cnt = block_sum_256(cnt, red);
+  // the closest per-frame relative error to eps (relative distance)
+  red[threadIdx.x] = near;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  near = red[0];
   if (threadIdx.x == 0) {
     res[0] = N > 0 ? srel / N : 0.0;
     res[1] = sy > 0.0 ? sqrt(se / sy) : 0.0;
+    res[6] = fmin(near, fmin(fabs(res[0] / eps - 1.0), fabs(res[1] / eps - 1.0)));
     res[2] = sdc;
     res[3] = sd;
     res[4] = cnt;
@@ -654,8 +680,10 @@ constexpr int64_t kMfmaMaxSplit = 32;
 template <typename TB, typename TE, typename TD>
 hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk, double alpha,
                 const double* A, View va, const TB* B, View vb, double beta, const TE* E, View ve,
-                TD* D, View vd, int64_t dz, double* colpart, double* bnorm, GemmWs ws) {
+                TD* D, View vd, int64_t dz, double* colpart, double* bnorm, GemmWs ws, int prec) {
   if (N <= 0) return hipSuccess;
+  if ((kchunk <= 0 || kchunk >= K) && gemm_mx_fits(M, N, K, va, vb, ve, vd, E != nullptr, D != nullptr, bnorm))
+    return gemm_mx<TB, TE, TD>(st, prec, M, N, K, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart);
   const int32_t gx = (N + 63) / 64, gy = gemm_row_blocks(M);
   const int64_t tiles = (int64_t)gx * gy;
   const bool whole_k = kchunk <= 0 || kchunk >= K;
@@ -722,7 +750,7 @@ hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk,
 #define TTICE_GEMM_INST(TB, TE, TD)                                                                  \
   template hipError_t gemm<TB, TE, TD>(hipStream_t, int32_t, int32_t, int32_t, int32_t, double,      \
                                        const double*, View, const TB*, View, double, const TE*, View, \
-                                       TD*, View, int64_t, double*, double*, GemmWs);
+                                       TD*, View, int64_t, double*, double*, GemmWs, int);
 TTICE_GEMM_INST(double, double, double)
 TTICE_GEMM_INST(float, double, double)
 TTICE_GEMM_INST(double, float, double)
@@ -753,6 +781,13 @@ hipError_t frame_sums(hipStream_t st, const double* part, int32_t MB, int64_t ld
 
 hipError_t total_sum(hipStream_t st, const double* x, int64_t n, double* out) {
   hipLaunchKernelGGL(k_total_sum, dim3(1), dim3(256), 0, st, x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t telescope(hipStream_t st, int32_t N, int32_t r, const double* c, int64_t ld, const double* y2,
+                     double* err2) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_telescope, dim3(nblocks(N, 4)), dim3(256), 0, st, N, r, c, ld, y2, err2);
   return hipGetLastError();
 }
 

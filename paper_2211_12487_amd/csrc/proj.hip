@@ -157,11 +157,10 @@ __global__ __launch_bounds__(64 * W) void k_proj_mfma(int32_t rows, int32_t r, i
   }
 }
 
-template <typename TIn, int VEC, int RT>
-hipError_t launch_proj(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
-                       const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
-                       hipEvent_t ev0, hipEvent_t ev1) {
-  constexpr int W = RT == 4 ? 4 : 8;
+template <typename TIn, int VEC, int RT, int W>
+hipError_t launch_proj_w(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
+                         const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
+                         hipEvent_t ev0, hipEvent_t ev1) {
   constexpr size_t lds = proj::red_bytes(W, RT * VEC * 4 + VEC);
   static_assert(lds <= 80 * 1024, "reduction buffer");
   // once per process (thread-safe static initialisation)
@@ -177,6 +176,21 @@ hipError_t launch_proj(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, co
     hipLaunchKernelGGL((k_proj_mfma<TIn, VEC, RT, W>), grid, dim3(64 * W), lds, st, rows, r, Ncol, vz, Z, U, ldu, C,
                        vc, znorm2, rho2);
   return hipGetLastError();
+}
+
+// Waves per block: enough to give each a chunk of row quads, so short
+// columns (a few quads) take one or two waves and no idle ones or LDS sum.
+template <typename TIn, int VEC, int RT>
+hipError_t launch_proj(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
+                       const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
+                       hipEvent_t ev0, hipEvent_t ev1) {
+  const int32_t nq = (rows + 3) / 4;
+  if (nq <= kChunkQuads)
+    return launch_proj_w<TIn, VEC, RT, 1>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  if (nq <= 2 * kChunkQuads)
+    return launch_proj_w<TIn, VEC, RT, 2>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  return launch_proj_w<TIn, VEC, RT, RT == 4 ? 4 : 8>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0,
+                                                      ev1);
 }
 
 template <typename TIn, int VEC>

@@ -298,11 +298,10 @@ __global__ __launch_bounds__(64 * W) void k_proj_bf3(int32_t rows, int32_t r, in
   proj_store<VEC, RT, NV>(v, kq, valid, j, r, C, vc, znorm2, rho2);
 }
 
-template <int P, typename TIn, int VEC, int RT>
-hipError_t launch_lp(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz, const double* U,
-                     int64_t ldu, double* C, View vc, double* znorm2, double* rho2, hipEvent_t ev0,
-                     hipEvent_t ev1) {
-  constexpr int W = 4;  // four waves split the row blocks (measured: beats eight, whose sum costs more)
+template <int P, typename TIn, int VEC, int RT, int W>
+hipError_t launch_lp_w(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz, const double* U,
+                       int64_t ldu, double* C, View vc, double* znorm2, double* rho2, hipEvent_t ev0,
+                       hipEvent_t ev1) {
   constexpr size_t lds = red_lds_bytes<W, RT * VEC * 4 + VEC>();
   static_assert(lds <= kRedBudget, "reduction buffer");
   const void* fn = P == kProjFP32 ? (const void*)k_proj_f32<TIn, VEC, RT, W> : (const void*)k_proj_bf3<TIn, VEC, RT, W>;
@@ -317,6 +316,22 @@ hipError_t launch_lp(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, cons
     hipExtLaunchKernelGGL((k_proj_bf3<TIn, VEC, RT, W>), grid, dim3(64 * W), (uint32_t)lds, st, ev0, ev1, 0u, rows, r,
                           Ncol, vz, Z, U, ldu, C, vc, znorm2, rho2);
   return hipGetLastError();
+}
+
+// Four waves split the row blocks (measured: beats eight, whose sum costs
+// more); columns of at most one or two blocks of the kernel's row step (4
+// rows FP32, 32 rows split BF16) per wave take one or two waves.
+template <int P, typename TIn, int VEC, int RT>
+hipError_t launch_lp(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz, const double* U,
+                     int64_t ldu, double* C, View vc, double* znorm2, double* rho2, hipEvent_t ev0,
+                     hipEvent_t ev1) {
+  const int32_t step = P == kProjFP32 ? 4 * kChunkQuads : 32;
+  const int32_t nb = (rows + step - 1) / step;
+  if (nb <= 1)
+    return launch_lp_w<P, TIn, VEC, RT, 1>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  if (nb <= 2)
+    return launch_lp_w<P, TIn, VEC, RT, 2>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  return launch_lp_w<P, TIn, VEC, RT, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
 }
 
 template <int P, typename TIn, int VEC>

@@ -170,8 +170,14 @@ struct ttice_state {
   double* fscratch(int64_t N) {
     return ensure(fsl, (size_t)N * kFrameSlicesMax * sizeof(double)) == TTICE_OK ? as<double>(fsl) : nullptr;
   }
-  double lp_band(int pp, int64_t rows) const;
-  int64_t lp_rechecks = 0;  // norm tests taken again in FP64 (reduced precision)
+  // relative distance from eps within which a reduced-precision chain's
+  // relative errors do not decide Algorithm 2.  A level's residual R~ = Z~
+  // - U C~ is off by the product's rounding, about 2^-16 ||z|| (split BF16)
+  // or 2^-24 sqrt(K) ||z|| with K up to ~10^4 (FP32), relative to ||R|| ~
+  // eps ||z||: ~3e-3 or ~1e-4 at eps = 0.005 per level, a few levels
+  // adding; the bands keep a factor of about five above that
+  double star_band() const { return prec == TTICE_PREC_BF16X3 ? 0.05 : 0.002; }
+  int64_t lp_rechecks = 0;  // Algorithm 2 decisions taken again on an FP64 chain (reduced precision)
   template <typename TIn>
   int core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, double tol_in, int64_t* rk_pend,
                 ttice_update_info* info, bool use_occ, double* last_out, int64_t last_ld);
@@ -183,11 +189,16 @@ struct ttice_state {
     double* colpart;   // max over levels of row blocks x columns
     double* fres;      // N
     double* fsl;       // N * kFrameSlicesMax
+    double* y2;        // N
     GemmWs g;
   };
+  // pp (kProj*): arithmetic of the level products
   template <typename TIn>
   int chain_project(const TIn* zin0, int64_t N, const int64_t* rks, double* coef_out, int64_t coef_ld,
-                    double* err2_out, double* y2_out, int* nonfinite, const ChainWs* cw = nullptr);
+                    double* err2_out, double* y2_out, int* nonfinite, const ChainWs* cw, int pp);
+  int proj_prec() const {
+    return prec == TTICE_PREC_FP32 ? kProjFP32 : prec == TTICE_PREC_BF16X3 ? kProjBF16x3 : kProjFP64;
+  }
   template <typename TIn>
   int update_impl(const TIn* batch, int64_t N, ttice_update_info* info);
   template <typename TD>
@@ -302,17 +313,6 @@ int32_t gram_kchunk(int32_t m, int64_t K) {
 // rk_pend holds the ranks being built (starts as the committed ones).
 // The last level's coefficients go to last_out (row j = frame j, stride
 // last_ld); last_out == nullptr means "into the last core after n_total".
-// Width of the band around the tolerance, as a fraction of tol2, within
-// which a reduced-precision residual energy does not decide the norm test.
-// The energy's error is at most 2 g ||Z_i||^2, with g the relative error of
-// one coefficient (K = rows products rounded to FP32, plus 2^-15 per operand
-// for the bf16 hi + lo split), and ||Z_i||^2 <= ||Y||^2 <= d tol2 / eps^2
-// (Corollary 1; in Algorithm 2 eps_upd >= eps); a factor 2 of slack.
-double ttice_state::lp_band(int pp, int64_t rows) const {
-  const double g = (double)rows * std::ldexp(1.0, -24) + (pp == kProjBF16x3 ? std::ldexp(1.0, -14) : 0.0);
-  return 4.0 * g * (double)d / (eps * eps);
-}
-
 namespace {
 // Block-Lanczos truncated SVD: blocks of kLzBlock vectors, kLzSteps blocks
 // (a Krylov basis of kLzBasis vectors, whose projected matrix fits the
@@ -682,7 +682,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
     const double occupancy = rows > 0 ? (double)r / (double)rows : 1.0;
     const bool occ_skip = use_occ && occupancy >= tau;
     int64_t rR = 0;
-    int32_t solver = 0, rechecked = 0;
+    int32_t solver = 0;
     double rho2 = std::numeric_limits<double>::quiet_NaN(), tail2 = 0.0;
     double margin = std::numeric_limits<double>::infinity();
 
@@ -694,7 +694,11 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       bn = as<double>(bnorm);
     }
     const bool fused = proj_fits((int32_t)rows, (int32_t)r) && Ncol >= kFusedMinCols;
-    const int32_t MB = fused ? 1 : gemm_row_blocks((int32_t)rows);
+    const int pp = proj_prec();
+    // the fused FP64 pass gives the residual energies by Pythagoras (one
+    // row of partials); in reduced precision they come from the explicit
+    // residual (partials per 64-row block)
+    const int32_t MB = (fused && pp == kProjFP64) ? 1 : gemm_row_blocks((int32_t)rows);
     CKS(ensure(colpart, (size_t)MB * Ncol * sizeof(double)));
     CKS(ensure(fres, (size_t)N * sizeof(double)));
     CKS(ensure(rbuf, (size_t)std::max<int64_t>(1, rows * Ncol) * sizeof(double)));
@@ -716,33 +720,37 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       return proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz, Ui.p, Ui.ld,
                                   out, vout, bn, cp, pp, e0, e1);
     };
-    const int pp = prec == TTICE_PREC_FP32 ? kProjFP32 : prec == TTICE_PREC_BF16X3 ? kProjBF16x3 : kProjFP64;
+    // R = Z - U C with per-column energies (eq:first_resid, eq:ithresidual),
+    // FP64; written to rbuf when small enough to keep for the SVD
+    auto residual = [&]() -> hipError_t {
+      double* rout = small ? as<double>(rbuf) : nullptr;
+      have_R = small;
+      if (zin_is_input)
+        return gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r, (int32_t)std::max<int64_t>(r, 1),
+                                         -1.0, Ui.p, vU, out, vout, 1.0, (const TIn*)zin, vz, rout, vr, 0, cp, nullptr,
+                                         gws());
+      return gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r, (int32_t)std::max<int64_t>(r, 1),
+                                          -1.0, Ui.p, vU, out, vout, 1.0, (const double*)zin, vz, rout, vr, 0, cp,
+                                          nullptr, gws());
+    };
     if (fused) {
+      // (reduced precision: the fused pass's energies by cancellation would
+      // sit at the products' rounding level, so the residual is formed from
+      // the rounded coefficients in FP64: ||Z - U C~||^2 = ||R||^2 +
+      // ||C~ - C||^2, never below the true energy)
       CK(fused_pass(pp, profile && i == 0));
+      if (pp != kProjFP64 && !occ_skip) CK(residual());
     } else {
       if (zin_is_input) {
         CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
                                    vUt, (const TIn*)zin, vz, 0.0, (const TIn*)nullptr, View(), out, vout,
-                                   0, nullptr, bn, gws())));
+                                   0, nullptr, bn, gws(), pp)));
       } else {
         CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0,
                                          Ui.p, vUt, (const double*)zin, vz, 0.0, (const double*)nullptr,
-                                         View(), out, vout, 0, nullptr, bn, gws())));
+                                         View(), out, vout, 0, nullptr, bn, gws(), pp)));
       }
-      if (!occ_skip) {
-        // R = Z - U C with per-column energies (eq:first_resid, eq:ithresidual)
-        double* rout = small ? as<double>(rbuf) : nullptr;
-        have_R = small;
-        if (zin_is_input) {
-          CK((gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r, (int32_t)std::max<int64_t>(r, 1),
-                                        -1.0, Ui.p, vU, out, vout, 1.0, (const TIn*)zin, vz, rout, vr, 0, cp,
-                                        nullptr, gws())));
-        } else {
-          CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
-                                           (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, vU, out, vout, 1.0,
-                                           (const double*)zin, vz, rout, vr, 0, cp, nullptr, gws())));
-        }
-      }
+      if (!occ_skip) CK(residual());
     }
 
     if (i == 0 && tol2 < 0) {
@@ -765,18 +773,6 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       }
       rho2 = hs[0];
       if (hs[1] != 0.0 || !isfinite(rho2)) return TTICE_EINVAL;
-      if (fused && pp != kProjFP64 && fabs(rho2 - tol2) <= lp_band(pp, rows) * tol2) {
-        // the reduced-precision energy is within its rounding band of the
-        // tolerance: take the decision on the FP64 projection instead
-        CK(fused_pass(kProjFP64, false));
-        CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres), fscratch(N)));
-        CK(total_sum(st, as<double>(fres), N, hs));
-        CKS(sync_scalars(4));
-        rho2 = hs[0];
-        if (hs[1] != 0.0 || !isfinite(rho2)) return TTICE_EINVAL;
-        ++lp_rechecks;
-        rechecked = 1;
-      }
       rho2 = std::max(rho2, 0.0);
       tail2 = rho2;
 
@@ -873,12 +869,12 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
           if (zin_is_input) {
             CK((gemm<TIn, TIn, double>(st, (int32_t)rR, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0,
                                        Ui.p + r, vUt2, (const TIn*)zin, vz, 0.0, (const TIn*)nullptr, View(),
-                                       out + r * cols, vout2, 0, nullptr, nullptr, gws())));
+                                       out + r * cols, vout2, 0, nullptr, nullptr, gws(), pp)));
           } else {
             CK((gemm<double, double, double>(st, (int32_t)rR, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0,
                                              Ui.p + r, vUt2, (const double*)zin, vz, 0.0,
                                              (const double*)nullptr, View(), out + r * cols, vout2, 0,
-                                             nullptr, nullptr, gws())));
+                                             nullptr, nullptr, gws(), pp)));
           }
           rk_pend[i + 1] = r + rR;
         }
@@ -890,7 +886,6 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       info->tail2[i] = occ_skip ? 0.0 : tail2;
       info->margin[i] = margin;
       info->solver[i] = solver;
-      info->rechecked[i] = rechecked;
     }
     zin = out;
     zin_is_input = false;
@@ -900,18 +895,32 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
 
 // Push N frames through the cores with ranks rks (no update): coefficients
 // into coef_out (row b = frame b, stride coef_ld), and optionally per-frame
-// residual energy sum_i ||R_i(b)||^2 (telescoping identity of the chain) and
-// per-frame ||Y(b)||^2.
+// residual energy err2(b) = sum_i ||R_i(b)||^2 and per-frame ||Y(b)||^2.
+// Every step of the chain is an orthogonal projection, so in FP64 the
+// residual energy is the telescoping difference ||Y(b)||^2 - ||c(b)||^2; in
+// reduced precision (pp) that cancellation would sit at the products'
+// rounding level, so each level whose core is not square forms its
+// residual Z - U C explicitly (energies in FP64).
 template <typename TIn>
 int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, double* coef_out,
                                int64_t coef_ld, double* err2_out, double* y2_out, int* nonfinite,
-                               const ChainWs* cw) {
+                               const ChainWs* cw, int pp) {
   hipStream_t st = stream;
   const void* zin = zin0;
   bool zin_is_input = true;
   const GemmWs gw = cw ? cw->g : gws();
+  const bool tele = err2_out != nullptr && pp == kProjFP64;
+  double* y2p = y2_out;
+  if (err2_out && !y2p) {
+    if (cw) {
+      y2p = cw->y2;
+    } else {
+      CKS(ensure(fy2, (size_t)N * sizeof(double)));
+      y2p = as<double>(fy2);
+    }
+  }
   double* fres_p = nullptr;
-  if (err2_out) CK(zero2d(st, 1, N, err2_out, N));
+  if (err2_out && !tele) CK(zero2d(st, 1, N, err2_out, N));
   for (int i = 0; i < d; ++i) {
     const int64_t rows = rks[i] * dims[i];
     const int64_t cols = this->cols(i);
@@ -924,7 +933,7 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
     const int64_t fs_out = last ? coef_ld : P;
     const View vout = unfolding(cols, fs_out);
     double* bn = nullptr;
-    if (i == 0 && y2_out) {
+    if (i == 0 && y2p) {
       if (cw) {
         bn = cw->bnorm;
       } else {
@@ -933,9 +942,10 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
       }
     }
     const bool fused = proj_fits((int32_t)rows, (int32_t)r) && Ncol >= kFusedMinCols;
-    const int32_t MB = fused ? 1 : gemm_row_blocks((int32_t)rows);
+    const bool resid = err2_out && !tele && r < rows;
+    const int32_t MB = gemm_row_blocks((int32_t)rows);
     double* cp = nullptr;
-    if (err2_out) {
+    if (resid) {
       if (cw) {
         cp = cw->colpart;
         fres_p = cw->fres;
@@ -947,42 +957,43 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
       }
     }
     double* fsl_p = cw ? cw->fsl : fscratch(N);
+    // C = U^T Z (the next level's data, eq:project_further)
     if (fused) {
       if (zin_is_input)
-        CK((proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p,
-                              Ui.ld, out, vout, bn, cp)));
+        CK((proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p, Ui.ld, out,
+                              vout, bn, nullptr, pp)));
       else
-        CK((proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz,
-                                         Ui.p, Ui.ld, out, vout, bn, cp)));
+        CK((proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz, Ui.p, Ui.ld,
+                                 out, vout, bn, nullptr, pp)));
     } else {
       if (zin_is_input)
         CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
                                    transposed(row_major(Ui.ld)), (const TIn*)zin, vz, 0.0, (const TIn*)nullptr,
-                                   View(), out, vout, 0, nullptr, bn, gw)));
+                                   View(), out, vout, 0, nullptr, bn, gw, pp)));
       else
         CK((gemm<double, double, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
                                          transposed(row_major(Ui.ld)), (const double*)zin, vz, 0.0,
-                                         (const double*)nullptr, View(), out, vout, 0, nullptr, bn, gw)));
-      if (err2_out) {
-        if (zin_is_input)
-          CK((gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
-                                        (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out, vout,
-                                        1.0, (const TIn*)zin, vz, (double*)nullptr, View(), 0, cp, nullptr, gw)));
-        else
-          CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
-                                           (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out,
-                                           vout, 1.0, (const double*)zin, vz, (double*)nullptr, View(), 0, cp, nullptr,
-                                           gw)));
-      }
+                                         (const double*)nullptr, View(), out, vout, 0, nullptr, bn, gw, pp)));
     }
-    if (bn) CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, y2_out, fsl_p));
-    if (err2_out) {
+    // per-column energies of R = Z - U C (eq:ithresidual) in reduced precision
+    if (resid) {
+      if (zin_is_input)
+        CK((gemm<double, TIn, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r, (int32_t)std::max<int64_t>(r, 1),
+                                      -1.0, Ui.p, row_major(Ui.ld), out, vout, 1.0, (const TIn*)zin, vz,
+                                      (double*)nullptr, View(), 0, cp, nullptr, gw, pp)));
+      else
+        CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)r,
+                                         (int32_t)std::max<int64_t>(r, 1), -1.0, Ui.p, row_major(Ui.ld), out, vout,
+                                         1.0, (const double*)zin, vz, (double*)nullptr, View(), 0, cp, nullptr, gw,
+                                         pp)));
       CK(frame_sums(st, cp, MB, Ncol, (int32_t)cols, (int32_t)N, fres_p, fsl_p));
       CK(accumulate(st, err2_out, fres_p, N));
     }
+    if (bn) CK(frame_sums(st, bn, 1, Ncol, (int32_t)cols, (int32_t)N, y2p, fsl_p));
     zin = out;
     zin_is_input = false;
   }
+  if (tele) CK(telescope(st, (int32_t)N, (int32_t)rks[d], coef_out, coef_ld, y2p, err2_out));
   if (nonfinite && y2_out) {
     CK(total_sum(st, y2_out, N, hs + 2));
     CKS(sync_scalars(4));
@@ -1018,11 +1029,21 @@ int ttice_state::update_impl(const TIn* batch, int64_t N, ttice_update_info* inf
     CKS(ensure(dlist, (size_t)N * sizeof(int32_t)));
     int nonfinite = 0;
     CKS(chain_project<TIn>(batch, N, rkp, Gt.p + n_total * Gt.ld, Gt.ld, as<double>(e2acc), as<double>(fy2),
-                           &nonfinite));
+                           &nonfinite, nullptr, proj_prec()));
     if (nonfinite) return TTICE_EINVAL;
     CK(star_decide(st, (int32_t)N, as<double>(e2acc), as<double>(fy2), eps, as<int32_t>(dlist),
                    hs));
-    CKS(sync_scalars(6));
+    CKS(sync_scalars(7));
+    if (proj_prec() != kProjFP64 && hs[6] <= star_band()) {
+      // a relative error within the reduced arithmetic's band of eps: the
+      // decisions (skip, the subset D) are taken on the FP64 chain instead
+      CKS(chain_project<TIn>(batch, N, rkp, Gt.p + n_total * Gt.ld, Gt.ld, as<double>(e2acc), as<double>(fy2),
+                             nullptr, nullptr, kProjFP64));
+      CK(star_decide(st, (int32_t)N, as<double>(e2acc), as<double>(fy2), eps, as<int32_t>(dlist), hs));
+      CKS(sync_scalars(7));
+      ++lp_rechecks;
+      if (info) info->star_rechecked = 1;
+    }
     const double mean_rel = hs[0], batch_rel = hs[1], sdc = hs[2], nd2 = hs[3];
     const int64_t nD = (int64_t)hs[4];
     const double ny2 = hs[5];
@@ -1066,7 +1087,8 @@ int ttice_state::update_impl(const TIn* batch, int64_t N, ttice_update_info* inf
       const int64_t r_old = rk[d], r_new = rkp[d];
       CKS(grow_core(Gt, n_total + N, std::max<int64_t>(r_new, 1), n_total, r_old));
       if (r_new > r_old) CK(zero2d(st, n_total, r_new - r_old, Gt.p + r_old, Gt.ld));
-      CKS(chain_project<TIn>(batch, N, rkp, Gt.p + n_total * Gt.ld, Gt.ld, nullptr, nullptr, nullptr));
+      CKS(chain_project<TIn>(batch, N, rkp, Gt.p + n_total * Gt.ld, Gt.ld, nullptr, nullptr, nullptr, nullptr,
+                             proj_prec()));
     }
   }
   CK(hipStreamSynchronize(st));
@@ -1324,10 +1346,10 @@ int ttice_project(ttice_state* st, const void* batch, int64_t n, int32_t dtype, 
   int nonfinite = 0;
   if (rc == TTICE_OK) {
     const int64_t rd = std::max<int64_t>(st->rk[st->d], 1);
-    rc = (dtype == TTICE_F32)
-             ? st->chain_project<float>((const float*)batch, n, st->rk, coef, rd, err2, y2, y2 ? &nonfinite : nullptr)
-             : st->chain_project<double>((const double*)batch, n, st->rk, coef, rd, err2, y2,
-                                         y2 ? &nonfinite : nullptr);
+    rc = (dtype == TTICE_F32) ? st->chain_project<float>((const float*)batch, n, st->rk, coef, rd, err2, y2,
+                                                         y2 ? &nonfinite : nullptr, nullptr, st->proj_prec())
+                              : st->chain_project<double>((const double*)batch, n, st->rk, coef, rd, err2, y2,
+                                                          y2 ? &nonfinite : nullptr, nullptr, st->proj_prec());
   }
   if (rc == TTICE_OK && hipStreamSynchronize(st->stream) != hipSuccess) rc = TTICE_EDEVICE;
   if (rc == TTICE_OK && nonfinite) rc = TTICE_EINVAL;
@@ -1352,13 +1374,12 @@ int ttice_project_noalloc(ttice_state* st, const void* batch, int64_t n, int32_t
   if (err2) {
     for (int i = 0; i < d; ++i) {
       const int64_t rows = st->rk[i] * st->dims[i], Ncol = n * st->cols(i);
-      const bool fused = proj_fits((int32_t)rows, (int32_t)st->rk[i + 1]) && Ncol >= kFusedMinCols;
-      cpmax = std::max<int64_t>(cpmax, (fused ? 1 : gemm_row_blocks((int32_t)rows)) * Ncol);
+      cpmax = std::max<int64_t>(cpmax, (int64_t)gemm_row_blocks((int32_t)rows) * Ncol);
     }
   }
   const double nd = (double)n;
-  const double need_d = 2.0 * nd * (double)st->P + nd * (double)st->cols(0) + (double)cpmax + nd +
-                        nd * kFrameSlicesMax + (double)(kTileCounters / 2) + 6.0 * 32.0;
+  const double need_d = 2.0 * nd * (double)st->P + nd * (double)st->cols(0) + (double)cpmax + 2.0 * nd +
+                        nd * kFrameSlicesMax + (double)(kTileCounters / 2) + 7.0 * 32.0;
   if (need_d * sizeof(double) > (double)kScratchBytes) return TTICE_ESCRATCH;
   double* p = (double*)base;
   auto take = [&](int64_t count) {
@@ -1373,6 +1394,7 @@ int ttice_project_noalloc(ttice_state* st, const void* batch, int64_t n, int32_t
   cw.colpart = take(cpmax);
   cw.fres = take(n);
   cw.fsl = take(n * kFrameSlicesMax);
+  cw.y2 = take(n);
   int* cnt = (int*)take(kTileCounters / 2);
   const int64_t rest = (int64_t)(kScratchBytes / sizeof(double)) - (int64_t)(p - (double*)base);
   cw.g = GemmWs{p, std::max<int64_t>(rest, 0), cnt, kTileCounters};
@@ -1384,9 +1406,9 @@ int ttice_project_noalloc(ttice_state* st, const void* batch, int64_t n, int32_t
   if (rc == TTICE_OK) {
     const int64_t rd = std::max<int64_t>(st->rk[d], 1);
     rc = (dtype == TTICE_F32) ? st->chain_project<float>((const float*)batch, n, st->rk, coef, rd, err2, y2,
-                                                         y2 ? &nonfinite : nullptr, &cw)
+                                                         y2 ? &nonfinite : nullptr, &cw, st->proj_prec())
                               : st->chain_project<double>((const double*)batch, n, st->rk, coef, rd, err2, y2,
-                                                          y2 ? &nonfinite : nullptr, &cw);
+                                                          y2 ? &nonfinite : nullptr, &cw, st->proj_prec());
   }
   if (rc == TTICE_OK && hipStreamSynchronize(st->stream) != hipSuccess) rc = TTICE_EDEVICE;
   if (rc == TTICE_OK && nonfinite) rc = TTICE_EINVAL;

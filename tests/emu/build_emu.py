@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 SRCS = [os.path.join(ROOT, "paper_2211_12487_amd", "csrc", f) for f in ("kernels.hip", "eig.hip", "proj.hip", "ttice.hip", "server.hip",
-                                                                          "lanczos.hip")]
+                                                                          "lanczos.hip", "gemm_mx.hip")]
 
 
 def asan_runtime() -> str:
@@ -27,7 +27,8 @@ def build(outdir: str, asan: bool = True) -> str:
         cmd += ["-fsanitize=address", "-fno-omit-frame-pointer"]
     objs = []
     for src in SRCS + [os.path.join(HERE, "hipemu.cpp"), os.path.join(HERE, "eig_probe.cpp"),
-                          os.path.join(HERE, "proj_probe.cpp"), os.path.join(HERE, "proj_lp_stub.cpp")]:
+                          os.path.join(HERE, "proj_probe.cpp"), os.path.join(HERE, "proj_lp_stub.cpp"),
+                          os.path.join(HERE, "gemm_probe.cpp"), os.path.join(HERE, "gemm_mx_lp_stub.cpp")]:
         obj = os.path.join(outdir, os.path.basename(src) + ".o")
         lang = ["-x", "c++"] if src.endswith(".hip") else []
         subprocess.run(cmd + ["-c"] + lang + [src, "-o", obj], check=True)

@@ -310,6 +310,35 @@ def case_eigensolver():
     assert np.abs(w - ev).max() <= 1e-13 * ev[0]
 
 
+def case_gemm_mx():
+    """The matrix-core tiled product (FP64) on its own, against NumPy:
+    ragged sizes off the 128 x 64 tile and the 32-deep K tile, A given
+    row-major or transposed, framed B columns, beta E, and the column
+    energies per 64-row block."""
+    import ctypes
+    vp, c_int, c_dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.hipemu_gemm_mx.argtypes = [c_int, c_int, c_int, c_dbl, vp, c_int, vp, c_int, ctypes.c_long, c_dbl, vp, vp, vp]
+    rng = np.random.default_rng(12)
+    for M, N, K, nf, a_trans, beta in ((130, 70, 45, 1, 0, 0.0), (200, 96, 33, 3, 1, -1.0), (64, 64, 32, 2, 0, 0.5),
+                                       (7, 5, 3, 1, 1, 1.0)):
+        A = rng.standard_normal((M, K))
+        cpf = N // nf
+        fs = K * cpf + 7
+        Bf = rng.standard_normal(nf * fs)
+        B = np.concatenate([Bf[f * fs:f * fs + K * cpf].reshape(K, cpf) for f in range(nf)], axis=1)
+        E = rng.standard_normal((M, N))
+        D = np.zeros((M, N))
+        MB = (M + 63) // 64
+        cp = np.zeros((MB, N))
+        Ain = np.ascontiguousarray(A.T) if a_trans else A
+        assert L.hipemu_gemm_mx(M, N, K, 0.75, Ain.ctypes.data, a_trans, Bf.ctypes.data, nf, fs, beta,
+                                E.ctypes.data, D.ctypes.data, cp.ctypes.data) == 0
+        ref = 0.75 * A @ B + beta * E
+        assert np.abs(D - ref).max() <= 1e-12 * np.abs(ref).max(), (M, N, K)
+        cref = np.array([(ref[64 * b:64 * (b + 1)] ** 2).sum(0) for b in range(MB)])
+        assert np.abs(cp - cref).max() <= 1e-12 * np.abs(cref).max(), (M, N, K)
+
+
 def case_proj_kernel():
     """The fused column-projection kernel on its own, against NumPy FP64:
     every vector width (4, 2, 1 columns per lane, and 1 for a misaligned

@@ -2,15 +2,17 @@
 cores, and split BF16: hi + lo bf16 operands with three products and FP32
 accumulation), through the C ABI.
 
-These modes change only the fused level projection (the HBM-bound pass);
-the residual SVD, re-orthogonalisation and all decisions stay FP64, and a
-norm test whose reduced-precision energy lands near the tolerance is taken
-again in FP64.  Bars: equal TT-ranks wherever the oracle's decision margins
-clear the reduced-precision floor, reconstructions within 1e-5 relative,
-achieved error <= eps per increment, orthonormal cores to 1e-12.  The
-shapes put more than 8192 columns at level 1 (the fused path) and reach
-every kernel variant: 4, 2 and 1 columns per lane, FP64 and FP32 input, and
-level-1 ranks in each 16-wide tile count (<= 16, <= 32, <= 64)."""
+These modes change the level projections C = U^T Z (the one-pass projection
+of narrow cores and the large matrix-core products); the norm test's
+residual is formed in FP64 from the rounded coefficients (never below the
+exact energy), and the residual SVD, re-orthogonalisation and all rank
+decisions stay FP64.  Bars: equal TT-ranks wherever the oracle's decision
+margins clear the reduced-precision floor, reconstructions within 1e-5
+relative (FP32) or 3e-4 (split BF16, see RTOL), achieved error <= eps per
+increment, orthonormal cores to 1e-12.  The shapes put more than 8192
+columns at level 1 (the fused path) and reach every kernel variant: 4, 2
+and 1 columns per lane, FP64 and FP32 input, and level-1 ranks in each
+16-wide tile count (<= 16, <= 32, <= 64)."""
 import numpy as np
 import pytest
 
@@ -24,7 +26,13 @@ from gpu_helpers import MARGIN_REDUCED, compare_stream, full_reconstruction_erro
 pytestmark = pytest.mark.gpu
 
 PRECS = ["fp32", "bf16x3"]
-RTOL = 1e-5
+# Reconstruction bars against the FP64 oracle: 1e-5 for FP32 (operands to
+# 2^-24, the reduced path's bar).  Split BF16 keeps 16 significant bits of
+# each operand (hi + lo): coefficient j is off by up to 2^-16 ||z|| even for
+# data in the cores' span, so the r coefficients of a column by up to
+# sqrt(r) 2^-16 ||z||, 1.2e-4 relative at the largest level-1 rank here
+# (r = 64): 3e-4 (a factor 2.5 above).
+RTOL = {"fp32": 1e-5, "bf16x3": 3e-4}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -43,11 +51,11 @@ def make(dims, eps, **kw):
 
 def check(dims, eps, batches, prec, label):
     g, o = make(dims, eps, prec=prec), Oracle(dims, eps)
-    infos, ok = compare_stream(g, o, batches, RTOL, MARGIN_REDUCED, label=label)
+    infos, ok = compare_stream(g, o, batches, RTOL[prec], MARGIN_REDUCED, label=label)
     assert ok, label
     for gi, oi in infos:
         assert gi["achieved2"] <= eps ** 2 * gi["normY2"] * (1 + 1e-6), (label, gi["achieved2"])
-    full_reconstruction_error(g, o, RTOL)
+    full_reconstruction_error(g, o, RTOL[prec])
     assert orthogonality(g) <= 1e-12
     g.close()
 
