@@ -1,0 +1,184 @@
+"""GPU <-> oracle parity on the benchmarked streams and the paper-shaped
+workloads, through the C ABI, in the FP64 and the reduced-precision arms.
+
+* the video-shaped stream (2048 frames of 240x320x3 in increments of 32,
+  eps = 0.1, Algorithm 1), all 64 increments, FP64 and FP32 arms;
+* the simulation-shaped stream (64^3 x 3 snapshots in increments of 16,
+  eps = 0.01), its first four full-size increments in the FP32 arm;
+* the order-8 reshaped 256^3 field (8^8, increments of 8, eps = 0.005,
+  Algorithm 2 with the mean rule), its first increment in the FP32 and the
+  split-BF16 arms;
+* ATARI-shaped runs (210x160x3 frames reshaped to 30x28x40x3, one run per
+  increment) under the Algorithm 2 variants of the experiments (Sec. 5), and
+  gel-shaped simulations (7x13x37x3x10, one per increment, TT-ICE* with
+  tau = 1, Sec. 4.2), FP64.
+
+The oracle runs once per stream (a module fixture) and every arm is compared
+with it.  Bars: equal TT-ranks on every increment whose decision margins
+clear the arm's floor, reconstructions of every increment within 1e-10
+(FP64) or 1e-5 (FP32) relative (split BF16: 3e-4, the bar of its 16
+significant bits, see test_gpu_precision.py), achieved error within eps
+(Algorithm 1), orthonormal cores to 1e-12."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import TTICE as Oracle
+from paper_2211_12487_amd import synth
+
+from gpu_helpers import MARGIN_FP64, MARGIN_REDUCED, log, orthogonality, to_dev
+
+pytestmark = pytest.mark.gpu
+
+RTOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 3e-4}
+MARGIN = {"fp64": MARGIN_FP64, "fp32": MARGIN_REDUCED, "bf16x3": MARGIN_REDUCED}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12487_amd import ttice
+    ttice.lib()
+    yield
+
+
+def checked_frames(n):
+    """The tensors of an increment whose reconstructions are compared: the
+    first, the middle and the last."""
+    return sorted({0, n // 2, n - 1})
+
+
+def oracle_run(dims, eps, batches, **kw):
+    """The oracle over the whole stream: per-increment info and the
+    reconstructions of the checked tensors of each increment right after it
+    was added (later updates leave them unchanged, Theorem 2)."""
+    o = Oracle(dims, eps, **kw)
+    infos, recs = [], []
+    for Y in batches:
+        info = o.update(Y.astype(np.float64))
+        infos.append(info)
+        n = Y.shape[0]
+        first = o.n_total - n
+        recs.append(np.stack([o.reconstruct(first + b, 1)[0] for b in checked_frames(n)]))
+    return o, infos, recs
+
+
+def gpu_against(o_infos, o_recs, dims, eps, batches, prec, label, **kw):
+    from paper_2211_12487_amd.ttice import TTICE
+    g = TTICE(dims, eps, prec=prec, **kw)
+    compared = 0
+    for k, (Y, oi, orec) in enumerate(zip(batches, o_infos, o_recs)):
+        gi = g.update(to_dev(Y))
+        margins = [m for m in oi["margin"] if m == m]
+        decisive = all(m > MARGIN[prec] for m in margins) if margins else True
+        if gi["ranks"][1:-1] != oi["ranks"][1:-1]:
+            assert not decisive, (label, k, gi["ranks"], oi["ranks"], oi["margin"])
+            log(f"{label} increment {k}: ranks {gi['ranks']} vs {oi['ranks']} at margin {min(margins):.2e}; "
+                "stream no longer comparable")
+            break
+        if "skipped" in oi and oi["skipped"] is not None:
+            assert gi["skipped"] == oi["skipped"] and gi["used"] == oi["used"], (label, k)
+        if gi["achieved2"] is not None:
+            assert gi["achieved2"] <= eps ** 2 * gi["normY2"] * (1 + 1e-6), (label, k)
+        n = Y.shape[0]
+        for q, b in enumerate(checked_frames(n)):
+            rec = g.reconstruct(g.n_total - n + b, 1)[0].cpu().numpy()
+            den = max(np.linalg.norm(orec[q]), 1e-300)
+            assert np.linalg.norm(rec - orec[q]) / den <= RTOL[prec], (label, k, b)
+        compared += 1
+    assert orthogonality(g) <= 1e-12
+    g.close()
+    return compared
+
+
+# ---- the video-shaped stream, all 64 increments ---------------------------
+
+VIDEO = dict(dims=(240, 320, 3), eps=0.1, frames=2048, batch=32)
+
+
+@pytest.fixture(scope="module")
+def video_oracle():
+    w = VIDEO
+    batches = list(synth.video_stream(w["frames"], w["batch"], seed=0))
+    log("oracle: video240 stream, 64 increments")
+    _, infos, recs = oracle_run(w["dims"], w["eps"], batches)
+    return batches, infos, recs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_video_stream_all_increments(video_oracle, prec):
+    log(f"case video240 x64, prec={prec}")
+    batches, infos, recs = video_oracle
+    n = gpu_against(infos, recs, VIDEO["dims"], VIDEO["eps"], batches, prec, f"video-{prec}")
+    assert n == len(batches)
+
+
+# ---- the simulation-shaped stream, first four increments ------------------
+
+def test_field64_stream_fp32():
+    log("case field64 (64^3 x 3), 4 increments of 16, prec=fp32")
+    dims, eps = (64, 64, 64, 3), 0.01
+    batches = list(synth.fourier_field_stream(64, 16, grid=64, components=3, seed=0))
+    _, infos, recs = oracle_run(dims, eps, batches)
+    n = gpu_against(infos, recs, dims, eps, batches, "fp32", "field64-fp32")
+    assert n >= 2
+
+
+# ---- the order-8 reshaped field, first increment -------------------------
+
+@pytest.fixture(scope="module")
+def order8_oracle():
+    dims = (8,) * 8
+    raw = next(synth.fourier_field_stream(8, 8, grid=256, components=1, kmax=16, decay=3.0, seed=0))
+    Y = raw.reshape((8,) + dims)
+    log("oracle: order-8 field, first increment")
+    _, infos, recs = oracle_run(dims, 0.005, [Y], algo="star")
+    return [Y], infos, recs
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_order8_first_increment_reduced(order8_oracle, prec):
+    log(f"case order-8 field 8^8 first increment, prec={prec}")
+    batches, infos, recs = order8_oracle
+    n = gpu_against(infos, recs, (8,) * 8, 0.005, batches, prec, f"order8-{prec}", algo="star")
+    assert n == 1
+
+
+# ---- paper-shaped workloads -------------------------------------------------
+
+ATARI = dict(frame=(210, 160, 3), dims=(30, 28, 40, 3), runs=(40, 70, 55, 90, 64, 48), seed=5)
+
+
+@pytest.mark.parametrize("variant,skip_rule,tau", [("TT-ICE*", "mean", 0.8), ("SS", "mean", 2.0),
+                                                   ("Subselect", "none", 2.0)])
+def test_atari_shaped_runs(variant, skip_rule, tau):
+    """Frames reshaped to 30x28x40x3 as in the experiments, one run per
+    increment, eps = 0.1, the Algorithm 2 variants."""
+    log(f"case atari-shaped runs, {variant}")
+    w = ATARI
+    total = sum(w["runs"])
+    h, wd, c = w["frame"]
+    Y = np.concatenate(list(synth.video_stream(total, 256, height=h, width=wd, channels=c, seed=w["seed"])))
+    Y = Y.reshape((total,) + w["dims"])
+    starts = np.concatenate([[0], np.cumsum(w["runs"])])
+    batches = [Y[starts[k]:starts[k + 1]] for k in range(len(w["runs"]))]
+    kw = dict(algo="star", skip_rule=skip_rule, tau=tau)
+    _, infos, recs = oracle_run(w["dims"], 0.1, batches, **kw)
+    n = gpu_against(infos, recs, w["dims"], 0.1, batches, "fp64", f"atari-{variant}", **kw)
+    assert n == len(batches)
+
+
+def test_gel_shaped_simulations():
+    """7x13x37x3x10 tensors one per increment (a low-rank family plus noise),
+    eps = 0.01, TT-ICE* with tau = 1."""
+    log("case gel-shaped 7x13x37x3x10, TT-ICE*")
+    dims = (7, 13, 37, 3, 10)
+    Y = np.concatenate(list(synth.tt_lowrank_stream(dims, (5, 15, 30, 10, 12), 24, 24, seed=9)))
+    Y = Y + 1e-3 * Y.std() * np.random.default_rng(10).standard_normal(Y.shape)
+    batches = [Y[k:k + 1] for k in range(Y.shape[0])]
+    kw = dict(algo="star", skip_rule="mean", tau=1.0)
+    _, infos, recs = oracle_run(dims, 0.01, batches, **kw)
+    n = gpu_against(infos, recs, dims, 0.01, batches, "fp64", "gel", **kw)
+    assert n == len(batches)
