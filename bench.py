@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrivals per second")
     ap.add_argument("--streams", type=int, default=256, help="serving: number of streams")
     ap.add_argument("--workers", type=int, default=32, help="serving: worker threads of the server")
+    ap.add_argument("--serving-prec", default="fp32", choices=["fp64", "fp32", "bf16x3"],
+                    help="serving: the streams' precision")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy one increment device-to-device (a plain copy kernel of known "
                          "size whose FETCH_SIZE / WRITE_SIZE counters calibrate the projection kernel's)")
@@ -236,32 +238,30 @@ def serving(a):
     it is submitted to the server.  Latency = completion - scheduled arrival
     (the driver's polling adds up to one loop period)."""
     import torch
+    from paper_2211_12487_amd import synth
     from paper_2211_12487_amd.ttice import Server
     rng = np.random.default_rng(0)
     srv = Server(workers=a.workers, budget_bytes=200 << 30)
     kinds = [(SERVING_SHAPES[int(rng.integers(len(SERVING_SHAPES)))], SERVING_EPS[int(rng.integers(3))])
              for _ in range(a.streams)]
-    sids = [srv.add_stream(dims, eps, max_batch=64) for dims, eps in kinds]
     n_req = int(rng.poisson(a.rate * a.seconds))
     times = np.sort(rng.uniform(0.0, a.seconds, n_req))
     who = rng.integers(0, a.streams, n_req)
     sizes = rng.integers(1, 65, n_req)
+    # each stream declares its capacity (the tensors it will receive), which
+    # bounds its reservation
+    total = np.bincount(who, weights=sizes, minlength=a.streams).astype(np.int64)
+    sids = [srv.add_stream(dims, eps, prec=a.serving_prec, max_batch=64, max_tensors=max(64, int(total[s])))
+            for s, (dims, eps) in enumerate(kinds)]
+    if srv.stats()["waiting_streams"]:
+        raise RuntimeError("serving: the budget does not hold every stream")
     gen = torch.cuda.Stream()
     g = torch.Generator(device="cuda")
     g.manual_seed(0)
 
     def make(dims, n):
         with torch.cuda.stream(gen):
-            parts = []
-            for ax, nn in enumerate(dims):
-                t = torch.arange(nn, device="cuda", dtype=torch.float32) / max(nn - 1, 1)
-                w = torch.rand((n, 5, 1), device="cuda", generator=g) * 3.0
-                ph = torch.rand((n, 5, 1), device="cuda", generator=g) * (2 * math.pi)
-                parts.append(torch.cos(math.pi * w * t + ph))
-            wt = torch.randn((n, 5), device="cuda", generator=g)
-            Y = (wt[:, :, None, None, None] * parts[0][:, :, :, None, None] * parts[1][:, :, None, :, None]
-                 * parts[2][:, :, None, None, :]).sum(1)
-            Y += 1e-3 * torch.randn(Y.shape, device="cuda", generator=g)
+            Y = synth.device_separable(dims, n, g)
         gen.synchronize()
         return Y
 
@@ -304,20 +304,22 @@ def serving(a):
         if not busy:
             time.sleep(50e-6)
     wall = time.perf_counter() - t0
+    counters = srv.stats()
     srv.close()
     lat_ms = np.array(lat) * 1e3
     steady = lat_ms[np.array(arrivals) >= min(1.0, a.seconds / 2)]  # after the streams' first increments
     return dict(
         metric="serving arrival-to-completion latency p99", value=float(np.percentile(lat_ms, 99)), unit="ms",
         n_gpus=1, steps=1, warmup=0, ms_per_step=wall * 1e3, higher_is_better=False, scaling="weak",
-        vs_baseline=None, dtype="f64", data="synthetic",
+        vs_baseline=None, dtype={"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[a.serving_prec], data="synthetic",
         config=dict(workload=f"serving: {a.streams} streams of {SERVING_SHAPES}, eps in {SERVING_EPS}, "
                              f"increments of 1..64 tensors, Poisson {a.rate:.0f}/s for {a.seconds:.0f} s, "
-                             f"{a.workers} workers"),
+                             f"{a.workers} workers, {a.serving_prec}"),
         p50_ms=float(np.percentile(lat_ms, 50)), p99_ms=float(np.percentile(lat_ms, 99)),
         max_ms=float(lat_ms.max()), submit_lag_p99_ms=float(np.percentile(np.array(lag) * 1e3, 99)),
         steady_p50_ms=float(np.percentile(steady, 50)), steady_p99_ms=float(np.percentile(steady, 99)),
-        increments=len(lat), tensors_per_s=tensors / wall,
+        increments=len(lat), tensors_per_s=tensors / wall, grouped_launches=counters["groups"],
+        grouped_increments=counters["grouped_increments"],
         offered_tensors_per_s=float(sizes.sum()) / a.seconds)
 
 
@@ -508,7 +510,9 @@ def main():
                        fp64_tensors_per_s=video["fp64"]["tensors_per_s"], ranks=video["chosen"]["ranks"],
                        fp64_ranks=video["fp64"]["ranks"]) if video else None),
         serving=(dict(p50_ms=serve["p50_ms"], p99_ms=serve["p99_ms"], steady_p99_ms=serve["steady_p99_ms"],
-                      tensors_per_s=serve["tensors_per_s"], workload=serve["config"]["workload"])
+                      tensors_per_s=serve["tensors_per_s"], grouped_launches=serve["grouped_launches"],
+                      grouped_increments=serve["grouped_increments"], increments=serve["increments"],
+                      workload=serve["config"]["workload"])
                  if serve else None),
         roofline=roofline(chosen["kstats"], a.prec),
         cpu_baseline=cpu,

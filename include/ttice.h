@@ -271,39 +271,57 @@ const char* ttice_strerror(int code);
  * a time (Algorithm 1, or Algorithm 2 per the stream's options); increments
  * of different streams run concurrently on different workers, so the small,
  * latency-bound launches of one stream's update overlap with other streams'
- * on the device.  A free worker always takes the stream that has waited
- * longest (continuous, work-conserving scheduling).  Every stream's result
- * is independent of the mix it ran in: the library's reductions have a
- * fixed order, so a stream alone and the same stream among others give
+ * on the device.  A free worker first continues an update whose level-1
+ * projection has been made, else takes the stream that has waited longest
+ * (continuous, work-conserving scheduling).
+ *
+ * Grouped launches: when several Algorithm 1 streams are waiting, the worker
+ * that takes them makes the level-1 projection of all their increments
+ * (eq:first_resid: U_1^T Z, ||z||^2 and the residual energies, the pass over
+ * every element of every tensor) in one launch per launch shape, up to 16
+ * streams per launch, in each stream's precision; each update then continues
+ * on any worker.  A served stream's level 1 always takes that projection
+ * with one column per lane, alone or grouped, and every reduction has a
+ * fixed order, so a stream alone and the same stream in a mix give
  * bit-identical cores.
  *
  * Admission: each stream reserves a projected footprint for increments of
- * up to max_batch tensors (level buffers, residual, Gram and eigen
- * workspace, and cores at the rank bound min(n_1..n_i, n_{i+1}..n_d), but
- * not the last core, which grows by one row per stored tensor); a stream
- * whose reservation would exceed the server's budget is refused.
+ * up to max_batch tensors and at most max_tensors tensors in all (level
+ * buffers, residual, Gram and eigen workspace, and every core at its rank
+ * bound with capacity doubling, the last core at max_tensors rows).  A
+ * stream whose reservation exceeds the budget left waits, in order of
+ * arrival, and is admitted when ttice_server_remove_stream frees enough;
+ * its increments queue meanwhile.  A reservation above the whole budget is
+ * refused.
  *
- * Ownership: a submitted batch (device pointer) must stay valid and
- * unchanged until its ticket completes.  Tickets are released once their
- * completion has been reported by ttice_server_wait or ttice_server_poll. */
+ * Ordering and ownership: a submitted batch (device pointer) is read after
+ * all work queued on the producer stream named at submission, and must stay
+ * valid and unchanged until its ticket completes.  Tickets are released once
+ * their completion has been reported by ttice_server_wait or
+ * ttice_server_poll. */
 typedef struct ttice_server ttice_server;
 
-/* workers in [1, 64]; budget_bytes > 0.  Errors: EINVAL, ENOMEM, EDEVICE. */
+/* workers in [1, 64]; budget_bytes > 0; the server runs on the current
+ * device.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int ttice_server_create(int32_t workers, int64_t budget_bytes, ttice_server** out);
 
 /* New stream of order-d tensors (ttice_create's arguments) with precision
  * prec (enum ttice_prec) and algorithm algo (enum ttice_algo), for
- * increments of at most max_batch tensors; *stream_id receives its id.
- * Errors: EINVAL, ENOMEM (state allocation, or the reservation exceeds the
- * remaining budget), ESTATE. */
+ * increments of at most max_batch tensors and at most max_tensors tensors in
+ * all (max_tensors >= max_batch); *stream_id receives its id.  The stream is
+ * admitted now or waits for budget (above).  Errors: EINVAL, ENOMEM (state
+ * allocation, or a reservation above the whole budget), ESTATE. */
 int ttice_server_add_stream(ttice_server* srv, int32_t d, const int64_t* dims, double eps, int32_t prec,
-                            int32_t algo, int64_t max_batch, int32_t* stream_id);
+                            int32_t algo, int64_t max_batch, int64_t max_tensors, int32_t* stream_id);
 
-/* Queue an increment (ttice_update's batch, n, dtype) on a stream; *ticket
- * receives its id.  Errors: EINVAL (unknown stream, n < 0 or > max_batch,
- * bad dtype, null batch with n > 0), ESTATE. */
+/* Queue an increment (ttice_update's batch, n, dtype) on a stream, ordered
+ * after the work queued so far on `producer` (a hipStream_t of the server's
+ * device; NULL: the null stream); *ticket receives its id.  Errors: EINVAL
+ * (unknown stream, n < 0 or > max_batch, max_tensors exceeded, bad dtype,
+ * null batch with n > 0, invalid producer), EDEVICE, ESTATE; a stream whose
+ * admission failed returns that status. */
 int ttice_server_submit(ttice_server* srv, int32_t stream_id, const void* batch, int64_t n, int32_t dtype,
-                        int64_t* ticket);
+                        void* producer, int64_t* ticket);
 
 /* *done = 1 when the ticket has completed; then *status receives
  * ttice_update's return code, info (host, may be NULL) its report, and the
@@ -316,17 +334,26 @@ int ttice_server_wait(ttice_server* srv, int64_t ticket, int32_t* status, struct
 
 /* Borrow a stream's state for the read-only calls (ttice_ranks,
  * ttice_reconstruct, ttice_get_core, ttice_project) once its queue has
- * drained; the server keeps ownership.  Errors: EINVAL, ESTATE (stream busy
- * or with queued increments). */
+ * drained; the server keeps ownership.  Errors: EINVAL, ESTATE (stream busy,
+ * with queued increments, or not admitted). */
 int ttice_server_stream_state(ttice_server* srv, int32_t stream_id, ttice_state** st);
 
-/* Destroy an idle stream and return its reservation.  Errors: EINVAL,
- * ESTATE (busy or queued). */
+/* Destroy an idle stream (admitted or waiting) and return its reservation,
+ * then admit waiting streams that fit.  Errors: EINVAL, ESTATE (busy,
+ * queued, or being admitted). */
 int ttice_server_remove_stream(ttice_server* srv, int32_t stream_id);
 
-/* Reserved bytes, budget and queued-or-running increments (each may be
- * NULL).  Errors: ESTATE. */
-int ttice_server_stats(ttice_server* srv, int64_t* reserved_bytes, int64_t* budget_bytes, int64_t* pending);
+struct ttice_server_counters {
+  int64_t reserved_bytes;      /* reservations of admitted streams */
+  int64_t budget_bytes;
+  int64_t pending;             /* increments queued or running */
+  int64_t waiting_streams;     /* streams waiting for admission */
+  int64_t groups;              /* grouped level-1 launches made */
+  int64_t grouped_increments;  /* increments whose level-1 projection ran in one */
+};
+
+/* The server's counters into *out (host).  Errors: EINVAL, ESTATE. */
+int ttice_server_stats(ttice_server* srv, struct ttice_server_counters* out);
 
 /* Stop the workers after the increments already running (queued ones are
  * completed with status ESTATE), then destroy every stream.  No other call

@@ -86,10 +86,44 @@ bool proj_fits(int32_t rows, int32_t r);
 // as its own start and end timestamps (the dispatch packet's, so they time
 // the kernel alone).
 constexpr int kProjFP64 = 0, kProjFP32 = 1, kProjBF16x3 = 2;
+// vmax caps the columns per lane (1, 2 or 4; the widest the alignment allows
+// up to vmax is taken).
 template <typename TIn>
 hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
                         const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
-                        int prec = kProjFP64, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                        int prec = kProjFP64, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
+                        int vmax = 4);
+
+// Several independent projections (one per stream of a server) in one
+// launch: descriptor q is proj_columns' arguments for one column per lane,
+// and its column blocks are blocks start[q] .. start[q + 1] - 1 of the grid.
+// Every descriptor of a group shares the input type, the arithmetic and the
+// launch shape (proj_shape), so each block computes bit for bit what the
+// same block of that projection's own launch (vmax = 1) computes.
+struct ProjDesc {
+  int32_t rows = 0, r = 0, Ncol = 0;
+  View vz, vc;
+  const void* Z = nullptr;
+  const double* U = nullptr;
+  int64_t ldu = 0;
+  double* C = nullptr;
+  double* znorm2 = nullptr;
+  double* rho2 = nullptr;
+};
+constexpr int kGroupMax = 16;  // descriptors per launch (kernel arguments stay under 4 KB)
+struct ProjGroup {
+  int32_t n = 0;
+  int32_t start[kGroupMax + 1] = {};
+  ProjDesc d[kGroupMax];
+};
+// Launch shape of a projection with one column per lane, 8 * (waves per
+// block) + (16-wide column tiles of U): equal for two projections exactly
+// when they can share a grouped launch (given the same input type and prec).
+int32_t proj_shape(int prec, int32_t rows, int32_t r);
+template <typename TIn>
+hipError_t proj_group(hipStream_t st, int prec, const ProjGroup& g);
+template <typename TIn>
+hipError_t proj_group_lp(hipStream_t st, int prec, const ProjGroup& g);
 // The reduced-precision launches behind proj_columns (vec = columns per lane,
 // already checked for alignment).
 template <typename TIn>

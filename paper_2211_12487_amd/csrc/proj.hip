@@ -37,17 +37,18 @@ using proj::store_vec;
 using proj::Vec;
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// the kernel body for column block blk
 template <typename TIn, int VEC, int RT, int W>
-__global__ __launch_bounds__(64 * W) void k_proj_mfma(int32_t rows, int32_t r, int32_t Ncol, View vz,
-                                                      const TIn* __restrict__ Z, const double* __restrict__ U,
-                                                      int64_t ldu, double* __restrict__ C, View vc,
-                                                      double* __restrict__ znorm2, double* __restrict__ rho2) {
+__device__ __forceinline__ void proj_mfma_body(int32_t blk, int32_t rows, int32_t r, int32_t Ncol, View vz,
+                                               const TIn* __restrict__ Z, const double* __restrict__ U, int64_t ldu,
+                                               double* __restrict__ C, View vc, double* __restrict__ znorm2,
+                                               double* __restrict__ rho2) {
   constexpr int NV = RT * VEC * 4 + VEC;  // doubles per lane: D tiles + ||z||^2 partials
   HIP_DYNAMIC_SHARED(double, red);        // (W / 2) x NV x 64
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int kq = lane >> 4, n = lane & 15;
-  const int32_t j = (int32_t)blockIdx.x * (16 * VEC) + VEC * n;  // first of this lane's VEC columns
+  const int32_t j = blk * (16 * VEC) + VEC * n;  // first of this lane's VEC columns
   const bool valid = j < Ncol;
   // lanes past the last column read column 0 and are never stored
   const int64_t coff = valid ? col_off(vz, j) : 0;
@@ -158,6 +159,26 @@ __global__ __launch_bounds__(64 * W) void k_proj_mfma(int32_t rows, int32_t r, i
 }
 
 template <typename TIn, int VEC, int RT, int W>
+__global__ __launch_bounds__(64 * W) void k_proj_mfma(int32_t rows, int32_t r, int32_t Ncol, View vz,
+                                                      const TIn* __restrict__ Z, const double* __restrict__ U,
+                                                      int64_t ldu, double* __restrict__ C, View vc,
+                                                      double* __restrict__ znorm2, double* __restrict__ rho2) {
+  proj_mfma_body<TIn, VEC, RT, W>((int32_t)blockIdx.x, rows, r, Ncol, vz, Z, U, ldu, C, vc, znorm2, rho2);
+}
+
+// Several projections in one launch (one column per lane): block b belongs
+// to the descriptor q with g.start[q] <= b < g.start[q + 1], and computes
+// exactly what the single launch's block b - g.start[q] computes.
+template <typename TIn, int RT, int W>
+__global__ __launch_bounds__(64 * W) void k_proj_mfma_group(ProjGroup g) {
+  int q = 0;
+  while (q + 1 < g.n && (int32_t)blockIdx.x >= g.start[q + 1]) ++q;
+  const ProjDesc& p = g.d[q];
+  proj_mfma_body<TIn, 1, RT, W>((int32_t)blockIdx.x - g.start[q], p.rows, p.r, p.Ncol, p.vz, (const TIn*)p.Z, p.U,
+                                p.ldu, p.C, p.vc, p.znorm2, p.rho2);
+}
+
+template <typename TIn, int VEC, int RT, int W>
 hipError_t launch_proj_w(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
                          const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
                          hipEvent_t ev0, hipEvent_t ev1) {
@@ -209,14 +230,14 @@ bool proj_fits(int32_t rows, int32_t r) { return r <= 64 && rows > 0; }
 template <typename TIn>
 hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
                         const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2, int prec,
-                        hipEvent_t ev0, hipEvent_t ev1) {
+                        hipEvent_t ev0, hipEvent_t ev1, int vmax) {
   if (Ncol <= 0) return hipSuccess;
   if (vz.rpf != kUnframed || vc.rpf != kUnframed || r > 64 || rows <= 0) return hipErrorInvalidValue;
   // the widest instantiation reads 16 * 4 doubles of every row of U
   static_assert(kProjTail >= 64, "core allocations must cover the widest row read");
   int vec = 1;
   for (int v : {4, 2}) {
-    if ((Ncol % v) == 0 && aligned_cols(vz, Z, sizeof(TIn), v) && (!C || aligned_cols(vc, C, sizeof(double), v))) {
+    if (v <= vmax && (Ncol % v) == 0 && aligned_cols(vz, Z, sizeof(TIn), v) && (!C || aligned_cols(vc, C, sizeof(double), v))) {
       vec = v;
       break;
     }
@@ -229,8 +250,61 @@ hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, c
 }
 
 template hipError_t proj_columns<float>(hipStream_t, int32_t, int32_t, int32_t, const float*, View, const double*,
-                                        int64_t, double*, View, double*, double*, int, hipEvent_t, hipEvent_t);
+                                        int64_t, double*, View, double*, double*, int, hipEvent_t, hipEvent_t, int);
 template hipError_t proj_columns<double>(hipStream_t, int32_t, int32_t, int32_t, const double*, View, const double*,
-                                         int64_t, double*, View, double*, double*, int, hipEvent_t, hipEvent_t);
+                                         int64_t, double*, View, double*, double*, int, hipEvent_t, hipEvent_t, int);
+
+// ---- grouped launches (one column per lane, the single launch's shape)
+int32_t proj_shape(int prec, int32_t rows, int32_t r) {
+  const int32_t rt = r <= 16 ? 1 : r <= 32 ? 2 : 4;
+  int32_t w;
+  if (prec == kProjFP64) {
+    const int32_t nq = (rows + 3) / 4;
+    w = nq <= kChunkQuads ? 1 : nq <= 2 * kChunkQuads ? 2 : (rt == 4 ? 4 : 8);
+  } else {
+    const int32_t step = prec == kProjFP32 ? 4 * kChunkQuads : 32;
+    const int32_t nb = (rows + step - 1) / step;
+    w = nb <= 1 ? 1 : nb <= 2 ? 2 : 4;
+  }
+  return 8 * w + rt;
+}
+
+namespace {
+template <typename TIn, int RT, int W>
+hipError_t launch_group_w(hipStream_t st, const ProjGroup& g) {
+  constexpr size_t lds = proj::red_bytes(W, RT * 4 + 1);
+  static const hipError_t attr = hipFuncSetAttribute((const void*)k_proj_mfma_group<TIn, RT, W>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL((k_proj_mfma_group<TIn, RT, W>), dim3((unsigned)g.start[g.n]), dim3(64 * W), lds, st, g);
+  return hipGetLastError();
+}
+template <typename TIn, int RT>
+hipError_t launch_group_rt(hipStream_t st, const ProjGroup& g, int32_t w) {
+  if (w == 1) return launch_group_w<TIn, RT, 1>(st, g);
+  if (w == 2) return launch_group_w<TIn, RT, 2>(st, g);
+  if (w == 4) return launch_group_w<TIn, RT, 4>(st, g);
+  return launch_group_w<TIn, RT, 8>(st, g);
+}
+}  // namespace
+
+template <typename TIn>
+hipError_t proj_group(hipStream_t st, int prec, const ProjGroup& g) {
+  if (g.n < 1 || g.n > kGroupMax || g.start[0] != 0) return hipErrorInvalidValue;
+  const int32_t shape = proj_shape(prec, g.d[0].rows, g.d[0].r);
+  for (int q = 0; q < g.n; ++q) {
+    const ProjDesc& p = g.d[q];
+    if (p.rows <= 0 || p.r < 0 || p.r > 64 || p.Ncol <= 0 || p.vz.rpf != kUnframed || p.vc.rpf != kUnframed ||
+        proj_shape(prec, p.rows, p.r) != shape || g.start[q + 1] - g.start[q] != (p.Ncol + 15) / 16)
+      return hipErrorInvalidValue;
+  }
+  if (prec != kProjFP64) return proj_group_lp<TIn>(st, prec, g);
+  const int32_t w = shape / 8, rt = shape % 8;
+  if (rt == 1) return launch_group_rt<TIn, 1>(st, g, w);
+  if (rt == 2) return launch_group_rt<TIn, 2>(st, g, w);
+  return launch_group_rt<TIn, 4>(st, g, w);
+}
+template hipError_t proj_group<float>(hipStream_t, int, const ProjGroup&);
+template hipError_t proj_group<double>(hipStream_t, int, const ProjGroup&);
 
 }  // namespace ttice

@@ -143,16 +143,16 @@ __device__ __forceinline__ void proj_store(const double (&v)[NV], int kq, bool v
 
 // ---- FP32 matrix cores: row quads, as the FP64 kernel
 template <typename TIn, int VEC, int RT, int W>
-__global__ __launch_bounds__(64 * W) void k_proj_f32(int32_t rows, int32_t r, int32_t Ncol, View vz,
-                                                     const TIn* __restrict__ Z, const double* __restrict__ U,
-                                                     int64_t ldu, double* __restrict__ C, View vc,
-                                                     double* __restrict__ znorm2, double* __restrict__ rho2) {
+__device__ __forceinline__ void f32_body(int32_t blk, int32_t rows, int32_t r, int32_t Ncol, View vz,
+                                         const TIn* __restrict__ Z, const double* __restrict__ U, int64_t ldu,
+                                         double* __restrict__ C, View vc, double* __restrict__ znorm2,
+                                         double* __restrict__ rho2) {
   constexpr int NV = RT * VEC * 4 + VEC;
   HIP_DYNAMIC_SHARED(double, red);
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int kq = lane >> 4, n = lane & 15;
-  const int32_t j = (int32_t)blockIdx.x * (16 * VEC) + VEC * n;
+  const int32_t j = blk * (16 * VEC) + VEC * n;
   const bool valid = j < Ncol;
   const int64_t coff = valid ? col_off(vz, j) : 0;
   const int64_t rs = vz.rs;
@@ -211,16 +211,16 @@ __global__ __launch_bounds__(64 * W) void k_proj_f32(int32_t rows, int32_t r, in
 constexpr int kOcts = 2;  // 32-row blocks whose loads are issued together
 
 template <typename TIn, int VEC, int RT, int W>
-__global__ __launch_bounds__(64 * W) void k_proj_bf3(int32_t rows, int32_t r, int32_t Ncol, View vz,
-                                                     const TIn* __restrict__ Z, const double* __restrict__ U,
-                                                     int64_t ldu, double* __restrict__ C, View vc,
-                                                     double* __restrict__ znorm2, double* __restrict__ rho2) {
+__device__ __forceinline__ void bf3_body(int32_t blk, int32_t rows, int32_t r, int32_t Ncol, View vz,
+                                         const TIn* __restrict__ Z, const double* __restrict__ U, int64_t ldu,
+                                         double* __restrict__ C, View vc, double* __restrict__ znorm2,
+                                         double* __restrict__ rho2) {
   constexpr int NV = RT * VEC * 4 + VEC;
   HIP_DYNAMIC_SHARED(double, red);
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int kq = lane >> 4, n = lane & 15;
-  const int32_t j = (int32_t)blockIdx.x * (16 * VEC) + VEC * n;
+  const int32_t j = blk * (16 * VEC) + VEC * n;
   const bool valid = j < Ncol;
   const int64_t coff = valid ? col_off(vz, j) : 0;
   const int64_t rs = vz.rs;
@@ -298,6 +298,34 @@ __global__ __launch_bounds__(64 * W) void k_proj_bf3(int32_t rows, int32_t r, in
   proj_store<VEC, RT, NV>(v, kq, valid, j, r, C, vc, znorm2, rho2);
 }
 
+template <typename TIn, int VEC, int RT, int W>
+__global__ __launch_bounds__(64 * W) void k_proj_f32(int32_t rows, int32_t r, int32_t Ncol, View vz,
+                                                     const TIn* __restrict__ Z, const double* __restrict__ U,
+                                                     int64_t ldu, double* __restrict__ C, View vc,
+                                                     double* __restrict__ znorm2, double* __restrict__ rho2) {
+  f32_body<TIn, VEC, RT, W>((int32_t)blockIdx.x, rows, r, Ncol, vz, Z, U, ldu, C, vc, znorm2, rho2);
+}
+template <typename TIn, int VEC, int RT, int W>
+__global__ __launch_bounds__(64 * W) void k_proj_bf3(int32_t rows, int32_t r, int32_t Ncol, View vz,
+                                                     const TIn* __restrict__ Z, const double* __restrict__ U,
+                                                     int64_t ldu, double* __restrict__ C, View vc,
+                                                     double* __restrict__ znorm2, double* __restrict__ rho2) {
+  bf3_body<TIn, VEC, RT, W>((int32_t)blockIdx.x, rows, r, Ncol, vz, Z, U, ldu, C, vc, znorm2, rho2);
+}
+
+// Several projections in one launch (one column per lane; see ProjGroup)
+template <int P, typename TIn, int RT, int W>
+__global__ __launch_bounds__(64 * W) void k_proj_lp_group(ProjGroup g) {
+  int q = 0;
+  while (q + 1 < g.n && (int32_t)blockIdx.x >= g.start[q + 1]) ++q;
+  const ProjDesc& p = g.d[q];
+  const int32_t blk = (int32_t)blockIdx.x - g.start[q];
+  if constexpr (P == kProjFP32)
+    f32_body<TIn, 1, RT, W>(blk, p.rows, p.r, p.Ncol, p.vz, (const TIn*)p.Z, p.U, p.ldu, p.C, p.vc, p.znorm2, p.rho2);
+  else
+    bf3_body<TIn, 1, RT, W>(blk, p.rows, p.r, p.Ncol, p.vz, (const TIn*)p.Z, p.U, p.ldu, p.C, p.vc, p.znorm2, p.rho2);
+}
+
 template <int P, typename TIn, int VEC, int RT, int W>
 hipError_t launch_lp_w(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz, const double* U,
                        int64_t ldu, double* C, View vc, double* znorm2, double* rho2, hipEvent_t ev0,
@@ -352,6 +380,30 @@ hipError_t launch_lp_vec(hipStream_t st, int vec, int32_t rows, int32_t r, int32
   return launch_lp_rt<P, TIn, 1>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
 }
 
+template <int P, typename TIn, int RT, int W>
+hipError_t launch_lp_group_w(hipStream_t st, const ProjGroup& g) {
+  constexpr size_t lds = red_lds_bytes<W, RT * 4 + 1>();
+  static_assert(lds <= kRedBudget, "reduction buffer");
+  static const hipError_t attr = hipFuncSetAttribute((const void*)k_proj_lp_group<P, TIn, RT, W>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL((k_proj_lp_group<P, TIn, RT, W>), dim3((unsigned)g.start[g.n]), dim3(64 * W), lds, st, g);
+  return hipGetLastError();
+}
+template <int P, typename TIn, int RT>
+hipError_t launch_lp_group_rt(hipStream_t st, const ProjGroup& g, int32_t w) {
+  if (w == 1) return launch_lp_group_w<P, TIn, RT, 1>(st, g);
+  if (w == 2) return launch_lp_group_w<P, TIn, RT, 2>(st, g);
+  return launch_lp_group_w<P, TIn, RT, 4>(st, g);
+}
+template <int P, typename TIn>
+hipError_t launch_lp_group(hipStream_t st, const ProjGroup& g, int32_t shape) {
+  const int32_t w = shape / 8, rt = shape % 8;
+  if (rt == 1) return launch_lp_group_rt<P, TIn, 1>(st, g, w);
+  if (rt == 2) return launch_lp_group_rt<P, TIn, 2>(st, g, w);
+  return launch_lp_group_rt<P, TIn, 4>(st, g, w);
+}
+
 }  // namespace
 
 template <typename TIn>
@@ -371,5 +423,16 @@ template hipError_t proj_columns_lp<float>(hipStream_t, int, int, int32_t, int32
 template hipError_t proj_columns_lp<double>(hipStream_t, int, int, int32_t, int32_t, int32_t, const double*, View,
                                             const double*, int64_t, double*, View, double*, double*, hipEvent_t,
                                             hipEvent_t);
+
+// (descriptors validated by proj_group)
+template <typename TIn>
+hipError_t proj_group_lp(hipStream_t st, int prec, const ProjGroup& g) {
+  const int32_t shape = proj_shape(prec, g.d[0].rows, g.d[0].r);
+  if (prec == kProjFP32) return launch_lp_group<kProjFP32, TIn>(st, g, shape);
+  if (prec == kProjBF16x3) return launch_lp_group<kProjBF16x3, TIn>(st, g, shape);
+  return hipErrorInvalidValue;
+}
+template hipError_t proj_group_lp<float>(hipStream_t, int, const ProjGroup&);
+template hipError_t proj_group_lp<double>(hipStream_t, int, const ProjGroup&);
 
 }  // namespace ttice

@@ -28,10 +28,29 @@
 
 #include "../../include/ttice.h"
 #include "kernels.h"
+#include "serve.h"
 
 using namespace ttice;
 
 namespace {
+
+// internal results of a capturing update (never returned by the C ABI)
+constexpr int kL1Captured = 1000, kL1Plain = 1001;
+
+// Projections that may share a grouped launch have equal keys: the launch
+// shape, the arithmetic and the input type.
+int32_t serve_key(int prec, int32_t rows, int32_t r, bool f32) {
+  return (proj_shape(prec, rows, r) * 3 + prec) * 2 + (f32 ? 1 : 0);
+}
+
+bool same_view(const View& a, const View& b) {
+  return a.rpf == b.rpf && a.cpf == b.cpf && a.rfs == b.rfs && a.rs == b.rs && a.cfs == b.cfs && a.cs == b.cs &&
+         a.cfidx == b.cfidx;
+}
+bool same_desc(const ProjDesc& a, const ProjDesc& b) {
+  return a.rows == b.rows && a.r == b.r && a.Ncol == b.Ncol && same_view(a.vz, b.vz) && same_view(a.vc, b.vc) &&
+         a.Z == b.Z && a.U == b.U && a.ldu == b.ldu && a.C == b.C && a.znorm2 == b.znorm2 && a.rho2 == b.rho2;
+}
 
 struct DevBuf {
   void* p = nullptr;
@@ -44,6 +63,9 @@ struct Core {
   double* p = nullptr;
   int64_t cap_rows = 0;
   int64_t ld = 0;
+  // capacity growth stops at these (the core's rank bounds, when known)
+  int64_t max_rows = std::numeric_limits<int64_t>::max();
+  int64_t max_cols = std::numeric_limits<int64_t>::max();
 };
 
 int status_of(hipError_t e) {
@@ -178,6 +200,17 @@ struct ttice_state {
   // adding; the bands keep a factor of about five above that
   double star_band() const { return prec == TTICE_PREC_BF16X3 ? 0.05 : 0.002; }
   int64_t lp_rechecks = 0;  // Algorithm 2 decisions taken again on an FP64 chain (reduced precision)
+  // Serving (server.hip): a served state's level 1 (Algorithm 1) always
+  // takes the fused projection with one column per lane, the form a grouped
+  // launch over several streams computes bit for bit.  l1_mode 1 stops an
+  // update just before that launch and records its arguments in l1_desc
+  // (kL1Captured), or stops before any level-1 work when the launch does not
+  // apply (kL1Plain); l1_mode 2 runs an update whose level-1 launch has
+  // already been made from l1_desc.
+  bool served = false;
+  int l1_mode = 0;
+  ProjDesc l1_desc;
+  int32_t l1_key = -1;
   template <typename TIn>
   int core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, double tol_in, int64_t* rk_pend,
                 ttice_update_info* info, bool use_occ, double* last_out, int64_t last_ld);
@@ -253,6 +286,8 @@ int ttice_state::grow_core(Core& c, int64_t need_rows, int64_t need_cols, int64_
   if (need_rows > c.cap_rows) nr = std::max<int64_t>(need_rows, 2 * c.cap_rows);
   int64_t nl = std::max<int64_t>(need_cols, c.ld);
   if (need_cols > c.ld) nl = std::max<int64_t>(need_cols, 2 * c.ld);
+  nr = std::min<int64_t>(nr, std::max<int64_t>(need_rows, c.max_rows));
+  nl = std::min<int64_t>(nl, std::max<int64_t>(need_cols, c.max_cols));
   nr = std::max<int64_t>(nr, 1);
   nl = std::max<int64_t>(nl, 1);
   double* p = nullptr;
@@ -693,7 +728,11 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       CKS(ensure(bnorm, (size_t)Ncol * sizeof(double)));
       bn = as<double>(bnorm);
     }
-    const bool fused = proj_fits((int32_t)rows, (int32_t)r) && Ncol >= kFusedMinCols;
+    // a served state's level 1 (Algorithm 1) is always fused, one column per lane
+    const bool l1_served = served && i == 0 && fidx == nullptr && !profile && proj_fits((int32_t)rows, (int32_t)r);
+    if (i == 0 && l1_mode == 1 && !l1_served) return kL1Plain;
+    if (i == 0 && l1_mode == 2 && !l1_served) return TTICE_EDEVICE;  // the captured launch does not apply
+    const bool fused = proj_fits((int32_t)rows, (int32_t)r) && (Ncol >= kFusedMinCols || l1_served);
     const int pp = proj_prec();
     // the fused FP64 pass gives the residual energies by Pythagoras (one
     // row of partials); in reduced precision they come from the explicit
@@ -714,11 +753,12 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         if (prof_begin(&e0, &e1) != TTICE_OK) return hipErrorOutOfMemory;
         ev_bytes.push_back((double)N * P * sizeof(TIn) + (double)r * Ncol * sizeof(double));
       }
+      const int vmax = l1_served ? 1 : 4;
       if (zin_is_input)
         return proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p, Ui.ld, out,
-                                 vout, bn, cp, pp, e0, e1);
+                                 vout, bn, cp, pp, e0, e1, vmax);
       return proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz, Ui.p, Ui.ld,
-                                  out, vout, bn, cp, pp, e0, e1);
+                                  out, vout, bn, cp, pp, e0, e1, vmax);
     };
     // R = Z - U C with per-column energies (eq:first_resid, eq:ithresidual),
     // FP64; written to rbuf when small enough to keep for the SVD
@@ -738,7 +778,29 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       // sit at the products' rounding level, so the residual is formed from
       // the rounded coefficients in FP64: ||Z - U C~||^2 = ||R||^2 +
       // ||C~ - C||^2, never below the true energy)
-      CK(fused_pass(pp, profile && i == 0));
+      if (l1_served && l1_mode != 0) {
+        ProjDesc dsc;
+        dsc.rows = (int32_t)rows;
+        dsc.r = (int32_t)r;
+        dsc.Ncol = (int32_t)Ncol;
+        dsc.vz = vz;
+        dsc.vc = vout;
+        dsc.Z = zin;
+        dsc.U = Ui.p;
+        dsc.ldu = Ui.ld;
+        dsc.C = out;
+        dsc.znorm2 = bn;
+        dsc.rho2 = cp;
+        if (l1_mode == 1) {
+          l1_desc = dsc;
+          l1_key = serve_key(pp, (int32_t)rows, (int32_t)r, sizeof(TIn) == sizeof(float));
+          return kL1Captured;
+        }
+        // the launch made from the captured arguments must be this one
+        if (!same_desc(dsc, l1_desc)) return TTICE_EDEVICE;
+      } else {
+        CK(fused_pass(pp, profile && i == 0));
+      }
       if (pp != kProjFP64 && !occ_skip) CK(residual());
     } else {
       if (zin_is_input) {
@@ -1289,11 +1351,22 @@ int ttice_reserve(ttice_state* st, int64_t max_batch) {
   return TTICE_OK;
 }
 
-int ttice_update(ttice_state* st, const void* batch, int64_t n, int32_t dtype, ttice_update_info* info) {
+}  // extern "C"
+#pragma GCC visibility pop
+
+namespace {
+// ttice_update with the state's level-1 mode set to l1_mode for its duration
+int update_entry(ttice_state* st, const void* batch, int64_t n, int32_t dtype, ttice_update_info* info,
+                 int l1_mode) {
   if (!st) return TTICE_ESTATE;
   if (n < 0 || (n > 0 && !batch)) return TTICE_EINVAL;
   if (dtype != TTICE_F32 && dtype != TTICE_F64) return TTICE_EINVAL;
   if (n * st->P >= ((int64_t)1 << 31)) return TTICE_EINVAL;  // 32-bit column indices
+  struct ModeScope {
+    ttice_state* s;
+    ~ModeScope() { s->l1_mode = 0; }
+  } scope{st};
+  st->l1_mode = l1_mode;
   ttice_update_info local;
   ttice_update_info* inf = info ? info : &local;
   memset(inf, 0, sizeof(*inf));
@@ -1306,6 +1379,7 @@ int ttice_update(ttice_state* st, const void* batch, int64_t n, int32_t dtype, t
     if (hipSetDevice(st->device) != hipSuccess) return TTICE_EDEVICE;
     rc = (dtype == TTICE_F32) ? st->update_impl<float>((const float*)batch, n, inf)
                               : st->update_impl<double>((const double*)batch, n, inf);
+    if (rc == kL1Captured || rc == kL1Plain) return rc;  // nothing launched but allocations and padding
     if (rc != TTICE_OK) {
       (void)hipStreamSynchronize(st->stream);
       (void)hipGetLastError();
@@ -1318,6 +1392,67 @@ int ttice_update(ttice_state* st, const void* batch, int64_t n, int32_t dtype, t
   inf->ranks[st->d + 1] = 1;
   return rc;
 }
+}  // namespace
+
+#pragma GCC visibility push(default)
+extern "C" {
+int ttice_update(ttice_state* st, const void* batch, int64_t n, int32_t dtype, ttice_update_info* info) {
+  return update_entry(st, batch, n, dtype, info, 0);
+}
+}  // extern "C"
+#pragma GCC visibility pop
+
+// ---- serving hooks (server.hip; internal to the library)
+namespace ttice {
+
+void serve_mark(ttice_state* st) { st->served = true; }
+
+void serve_limit(ttice_state* st, int64_t max_tensors) {
+  int64_t rb[TTICE_MAX_D + 1];
+  serve_rank_bounds(st->d, st->dims, max_tensors, rb);
+  for (int i = 0; i < st->d; ++i) {
+    st->U[i].max_rows = rb[i] * st->dims[i];
+    st->U[i].max_cols = rb[i + 1];
+  }
+  st->Gt.max_rows = max_tensors;
+  st->Gt.max_cols = rb[st->d];
+}
+
+void serve_rank_bounds(int32_t d, const int64_t* dims, int64_t T, int64_t* rb) {
+  // r_i <= min(n_1 ... n_i, n_{i+1} ... n_d T): the ranks of the unfoldings of
+  // the (d + 1)-way array of all T tensors; r_d <= min(prod(dims), T)
+  double left = 1.0, P = 1.0;
+  for (int i = 0; i < d; ++i) P *= (double)dims[i];
+  rb[0] = 1;
+  for (int i = 0; i < d; ++i) {
+    left *= (double)dims[i];
+    const double b = std::min(left, P / left * (double)T);
+    rb[i + 1] = (int64_t)std::min(b, 9.0e18);
+  }
+}
+
+int serve_capture(ttice_state* st, const void* batch, int64_t n, int32_t dtype, ProjDesc* desc, int32_t* key) {
+  if (!st || st->algo != TTICE_ALG_PLAIN || st->d < 2 || n <= 0) return 0;
+  if (update_entry(st, batch, n, dtype, nullptr, 1) != kL1Captured) return 0;  // errors: ttice_update reports them
+  *desc = st->l1_desc;
+  *key = st->l1_key;
+  return 1;
+}
+
+int serve_update_after(ttice_state* st, const void* batch, int64_t n, int32_t dtype, ttice_update_info* info) {
+  return update_entry(st, batch, n, dtype, info, 2);
+}
+
+hipError_t serve_group_launch(hipStream_t s, int32_t key, const ProjGroup& g) {
+  const bool f32 = (key & 1) != 0;
+  const int prec = (key >> 1) % 3;
+  return f32 ? proj_group<float>(s, prec, g) : proj_group<double>(s, prec, g);
+}
+
+}  // namespace ttice
+
+#pragma GCC visibility push(default)
+extern "C" {
 
 int ttice_reconstruct(ttice_state* st, int64_t first, int64_t count, void* out, int32_t dtype) {
   if (!st) return TTICE_ESTATE;

@@ -35,6 +35,7 @@ __all__ = [
     "smooth_separable_stream",
     "video_stream",
     "fourier_field_stream",
+    "device_separable",
     "tt_lowrank_stream",
     "serving_trace",
     "CONFIGS",
@@ -221,6 +222,27 @@ class DeviceFourierField:
                 spec.index_put_(self.idx, coef, accumulate=True)
                 out[b, ..., c] = (torch.fft.ifftn(spec).real * g ** 3).to(dtype)
         return out[..., 0] if C == 1 else out
+
+
+def device_separable(dims, n, generator, terms=5, noise=1e-3, dtype=None):
+    """``n`` tensors of shape ``dims`` (3-way) drawn on the generator's torch
+    device: each a sum of ``terms`` separable products of cosine profiles
+    cos(pi w t + phi) (w ~ U[0, 3), phi ~ U[0, 2 pi), t on [0, 1]) with N(0,1)
+    weights, plus N(0, noise^2); the serving mix's tensors."""
+    import torch
+    dtype = torch.float32 if dtype is None else dtype
+    dev = generator.device
+    parts = []
+    for nn in dims:
+        t = torch.arange(nn, device=dev, dtype=torch.float32) / max(nn - 1, 1)
+        w = torch.rand((n, terms, 1), device=dev, generator=generator) * 3.0
+        ph = torch.rand((n, terms, 1), device=dev, generator=generator) * (2 * math.pi)
+        parts.append(torch.cos(math.pi * w * t + ph))
+    wt = torch.randn((n, terms), device=dev, generator=generator)
+    Y = (wt[:, :, None, None, None] * parts[0][:, :, :, None, None] * parts[1][:, :, None, :, None]
+         * parts[2][:, :, None, None, :]).sum(1)
+    Y += noise * torch.randn(Y.shape, device=dev, generator=generator)
+    return Y.to(dtype)
 
 
 def tt_lowrank_stream(

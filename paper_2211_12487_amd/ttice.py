@@ -55,6 +55,11 @@ EXPORTS = [
 ]
 
 
+class ServerCounters(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in ("reserved_bytes", "budget_bytes", "pending", "waiting_streams",
+                                                    "groups", "grouped_increments")]
+
+
 class UpdateInfo(ctypes.Structure):
     _fields_ = [
         ("d", ctypes.c_int32),
@@ -133,15 +138,15 @@ def lib():
     L.ttice_strerror.argtypes = [ctypes.c_int]
     L.ttice_strerror.restype = ctypes.c_char_p
     L.ttice_server_create.argtypes = [c_i32, c_i64, ctypes.POINTER(c_vp)]
-    L.ttice_server_add_stream.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i64), c_dbl, c_i32, c_i32, c_i64,
+    L.ttice_server_add_stream.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i64), c_dbl, c_i32, c_i32, c_i64, c_i64,
                                           ctypes.POINTER(c_i32)]
-    L.ttice_server_submit.argtypes = [c_vp, c_i32, c_vp, c_i64, c_i32, ctypes.POINTER(c_i64)]
+    L.ttice_server_submit.argtypes = [c_vp, c_i32, c_vp, c_i64, c_i32, c_vp, ctypes.POINTER(c_i64)]
     L.ttice_server_poll.argtypes = [c_vp, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
                                     ctypes.POINTER(UpdateInfo)]
     L.ttice_server_wait.argtypes = [c_vp, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(UpdateInfo)]
     L.ttice_server_stream_state.argtypes = [c_vp, c_i32, ctypes.POINTER(c_vp)]
     L.ttice_server_remove_stream.argtypes = [c_vp, c_i32]
-    L.ttice_server_stats.argtypes = [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
+    L.ttice_server_stats.argtypes = [c_vp, ctypes.POINTER(ServerCounters)]
     L.ttice_server_destroy.argtypes = [c_vp]
     L.ttice_server_destroy.restype = None
     for name in ("ttice_create", "ttice_set_option", "ttice_update", "ttice_reconstruct",
@@ -219,6 +224,9 @@ class TTICE:
     def _batch(self, Y: torch.Tensor) -> torch.Tensor:
         if not Y.is_cuda:
             raise ValueError("batch must be a device tensor")
+        if self.stream is None:
+            # the library's work is ordered after the caller's on torch's current stream
+            self.set_option(OPT_STREAM, ctypes.c_void_p(torch.cuda.current_stream(Y.device).cuda_stream))
         if tuple(Y.shape) == self.dims:
             Y = Y.unsqueeze(0)
         if tuple(Y.shape[1:]) != self.dims:
@@ -360,12 +368,14 @@ class Server:
         self._inflight = {}  # ticket -> batch tensor kept alive until completion
 
     def add_stream(self, dims: Sequence[int], eps: float, prec: str = "fp64", algo: str = "plain",
-                   max_batch: int = 64) -> int:
+                   max_batch: int = 64, max_tensors: int = 4096) -> int:
+        """A new stream (admitted now, or once removed streams free budget)."""
         dims = tuple(int(n) for n in dims)
         arr = (ctypes.c_int64 * len(dims))(*dims)
         sid = ctypes.c_int32()
         _check(lib().ttice_server_add_stream(self._h, len(dims), arr, float(eps), PREC[prec], ALGO[algo],
-                                             int(max_batch), ctypes.byref(sid)), "ttice_server_add_stream")
+                                             int(max_batch), int(max_tensors), ctypes.byref(sid)),
+               "ttice_server_add_stream")
         self._streams[sid.value] = (dims, float(eps))
         return sid.value
 
@@ -379,8 +389,10 @@ class Server:
             raise ValueError(f"batch shape {tuple(Y.shape)} does not match dims {dims}")
         Y = Y.contiguous()
         t = ctypes.c_int64()
+        # the update reads Y after the work queued so far on torch's current stream
+        producer = ctypes.c_void_p(torch.cuda.current_stream(Y.device).cuda_stream)
         _check(lib().ttice_server_submit(self._h, int(sid), ctypes.c_void_p(Y.data_ptr()), Y.shape[0],
-                                         _dtype_code(Y.dtype), ctypes.byref(t)), "ttice_server_submit")
+                                         _dtype_code(Y.dtype), producer, ctypes.byref(t)), "ttice_server_submit")
         self._inflight[t.value] = Y
         return t.value
 
@@ -414,10 +426,9 @@ class Server:
         self._streams.pop(sid, None)
 
     def stats(self) -> dict:
-        r, b, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        _check(lib().ttice_server_stats(self._h, ctypes.byref(r), ctypes.byref(b), ctypes.byref(p)),
-               "ttice_server_stats")
-        return dict(reserved_bytes=r.value, budget_bytes=b.value, pending=p.value)
+        c = ServerCounters()
+        _check(lib().ttice_server_stats(self._h, ctypes.byref(c)), "ttice_server_stats")
+        return {name: getattr(c, name) for name, _ in ServerCounters._fields_}
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 sys.path.insert(0, HERE)
 
-from emu_ttice import EmuError, EmuTTICE, UpdateInfo, load  # noqa: E402
+from emu_ttice import EmuError, EmuTTICE, ServerCounters, UpdateInfo, load  # noqa: E402
 from oracle import TTICE as Oracle  # noqa: E402
 from paper_2211_12487_amd import synth  # noqa: E402
 
@@ -382,25 +382,35 @@ def case_proj_kernel():
                     assert np.abs(rh[b * cols:(b + 1) * cols] - res).max() <= 1e-12 * z2.max()
 
 
-def case_server():
-    """The serving layer (one worker thread: the emulation runs one launch at
-    a time): per-stream FIFO order, tickets and statuses, an error that
-    leaves its stream usable, admission against the byte budget, removal,
-    and alone-vs-mix: every stream's cores and reconstructions are
-    bit-identical to the same stream run on its own."""
+def _server_run(specs, data, workers, budget):
+    """Runs every stream's increments through one server (all submitted
+    before any is waited for); returns the server and the stream ids."""
     import ctypes
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     srv = vp()
-    assert L.ttice_server_create(1, 1 << 30, ctypes.byref(srv)) == 0
-    specs = [((16, 16, 3), 0.05, 0), ((12, 9, 4), 0.02, 0), ((8, 8, 8), 0.05, 1)]
-    sids, data = [], []
-    for k, (dims, eps, algo) in enumerate(specs):
+    assert L.ttice_server_create(workers, budget, ctypes.byref(srv)) == 0
+    sids = []
+    for dims, eps, algo in specs:
         sid = i32()
         arr = (ctypes.c_int64 * len(dims))(*dims)
-        assert L.ttice_server_add_stream(srv, len(dims), arr, eps, 0, algo, 4, ctypes.byref(sid)) == 0
+        assert L.ttice_server_add_stream(srv, len(dims), arr, eps, 0, algo, 4, 64, ctypes.byref(sid)) == 0
         sids.append(sid.value)
-        data.append(list(synth.smooth_separable_stream(10, dims, 3, 1e-3, 1 + k, 40 + k, dtype=np.float64)))
-    # interleave the increments of the three streams; one bad batch on stream 1
+    return srv, sids
+
+
+def case_server():
+    """The serving layer (one worker thread: the emulation runs one launch at
+    a time): per-stream FIFO order, tickets and statuses, an error that
+    leaves its stream usable, grouped level-1 launches, queued admission
+    against the byte budget, removal, and alone-vs-mix: every stream's cores
+    and reconstructions are bit-identical to the same stream served alone."""
+    import ctypes
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    specs = [((16, 16, 3), 0.05, 0), ((12, 9, 4), 0.02, 0), ((8, 8, 8), 0.05, 1), ((16, 16, 3), 0.1, 0)]
+    data = [list(synth.smooth_separable_stream(10, dims, 3, 1e-3, 1 + k, 40 + k, dtype=np.float64))
+            for k, (dims, _, _) in enumerate(specs)]
+    srv, sids = _server_run(specs, data, 1, 1 << 30)
+    # interleave the increments of the streams; one bad batch on stream 1
     bad = np.full((2,) + specs[1][0], np.nan)
     tickets = []  # (stream index, increment index or -1, ticket)
     keep = []
@@ -410,11 +420,11 @@ def case_server():
                 Y = np.ascontiguousarray(data[k][j])
                 keep.append(Y)
                 t = i64()
-                assert L.ttice_server_submit(srv, sid, Y.ctypes.data, Y.shape[0], 1, ctypes.byref(t)) == 0
+                assert L.ttice_server_submit(srv, sid, Y.ctypes.data, Y.shape[0], 1, None, ctypes.byref(t)) == 0
                 tickets.append((k, j, t.value))
             if k == 1 and j == 2:
                 t = i64()
-                assert L.ttice_server_submit(srv, sid, bad.ctypes.data, 2, 1, ctypes.byref(t)) == 0
+                assert L.ttice_server_submit(srv, sid, bad.ctypes.data, 2, 1, None, ctypes.byref(t)) == 0
                 tickets.append((k, -1, t.value))
     for k, j, t in tickets:
         status, info = i32(), UpdateInfo()
@@ -422,34 +432,118 @@ def case_server():
         assert status.value == (-1 if j < 0 else 0), (k, j, status.value)
         done = i32()
         assert L.ttice_server_poll(srv, t, ctypes.byref(done), None, None) == -1  # released
+    c = ServerCounters()
+    assert L.ttice_server_stats(srv, ctypes.byref(c)) == 0
+    assert c.pending == 0 and 0 < c.reserved_bytes <= c.budget_bytes and c.waiting_streams == 0
+    # the worker found several Algorithm 1 streams waiting after its first update
+    assert c.groups > 0 and c.grouped_increments > c.groups, (c.groups, c.grouped_increments)
     for k, sid in enumerate(sids):
         h = vp()
         assert L.ttice_server_stream_state(srv, sid, ctypes.byref(h)) == 0
         mixed = EmuTTICE.borrowed(L, h, specs[k][0])
-        alone = EmuTTICE(L, specs[k][0], specs[k][1], algo=specs[k][2])
-        for Y in data[k]:
-            alone.update(Y)
+        # the same stream served alone (its bad batch included)
+        alone_srv, (asid,) = _server_run([specs[k]], [data[k]], 1, 1 << 30)
+        for j, Y in enumerate(data[k]):
+            Y = np.ascontiguousarray(Y)
+            t, status = i64(), i32()
+            assert L.ttice_server_submit(alone_srv, asid, Y.ctypes.data, Y.shape[0], 1, None, ctypes.byref(t)) == 0
+            assert L.ttice_server_wait(alone_srv, t.value, ctypes.byref(status), None) == 0 and status.value == 0
+        ha = vp()
+        assert L.ttice_server_stream_state(alone_srv, asid, ctypes.byref(ha)) == 0
+        alone = EmuTTICE.borrowed(L, ha, specs[k][0])
         assert mixed.ranks() == alone.ranks(), k
         assert np.array_equal(mixed.reconstruct(), alone.reconstruct()), k
         for i in range(len(specs[k][0]) + 1):
             assert np.array_equal(mixed.core(i), alone.core(i)), (k, i)
-        alone.close()
-    reserved, budget, pending = i64(), i64(), i64()
-    assert L.ttice_server_stats(srv, ctypes.byref(reserved), ctypes.byref(budget), ctypes.byref(pending)) == 0
-    assert pending.value == 0 and 0 < reserved.value <= budget.value
-    # admission: a stream whose reservation exceeds what is left is refused
+        L.ttice_server_destroy(alone_srv)
+    # a reservation above the whole budget is refused
     big = (ctypes.c_int64 * 3)(512, 512, 512)
     sid = i32()
-    assert L.ttice_server_add_stream(srv, 3, big, 0.1, 0, 0, 64, ctypes.byref(sid)) == -2
+    assert L.ttice_server_add_stream(srv, 3, big, 0.1, 0, 0, 64, 64, ctypes.byref(sid)) == -2
+    assert L.ttice_server_add_stream(srv, 3, big, 0.1, 0, 0, 64, 32, ctypes.byref(sid)) == -1  # max_tensors < max_batch
     # removal returns the reservation; the id is then unknown
-    before = reserved.value
+    before = c.reserved_bytes
     assert L.ttice_server_remove_stream(srv, sids[0]) == 0
-    assert L.ttice_server_stats(srv, ctypes.byref(reserved), None, None) == 0
-    assert reserved.value < before
+    assert L.ttice_server_stats(srv, ctypes.byref(c)) == 0
+    assert c.reserved_bytes < before
     t = i64()
     Y = keep[0]
-    assert L.ttice_server_submit(srv, sids[0], Y.ctypes.data, Y.shape[0], 1, ctypes.byref(t)) == -1
-    assert L.ttice_server_submit(srv, sids[1], None, 5, 1, ctypes.byref(t)) == -1  # null batch / over max_batch
+    assert L.ttice_server_submit(srv, sids[0], Y.ctypes.data, Y.shape[0], 1, None, ctypes.byref(t)) == -1
+    assert L.ttice_server_submit(srv, sids[1], None, 5, 1, None, ctypes.byref(t)) == -1  # null batch / over max_batch
+    # the tensor limit: stream 3 has taken 10 of its 64 tensors
+    zeros = np.zeros((4,) + specs[3][0])
+    for _ in range(13):
+        assert L.ttice_server_submit(srv, sids[3], zeros.ctypes.data, 4, 1, None, ctypes.byref(t)) == 0
+        assert L.ttice_server_wait(srv, t.value, None, None) == 0
+    assert L.ttice_server_submit(srv, sids[3], zeros.ctypes.data, 3, 1, None, ctypes.byref(t)) == -1  # 65 > 64
+    assert L.ttice_server_submit(srv, sids[3], zeros.ctypes.data, 2, 1, None, ctypes.byref(t)) == 0
+    assert L.ttice_server_wait(srv, t.value, None, None) == 0
+    L.ttice_server_destroy(srv)
+
+
+def case_server_admission():
+    """Queued admission: with a budget that holds two streams, a third waits
+    (its increments queue) and is admitted when a stream is removed; its
+    results equal the same stream served alone."""
+    import ctypes
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    dims, eps = (16, 16, 3), 0.05
+    arr = (ctypes.c_int64 * 3)(*dims)
+    # the footprint of one stream, measured on a server of ample budget
+    probe, sid = vp(), i32()
+    assert L.ttice_server_create(1, 1 << 40, ctypes.byref(probe)) == 0
+    assert L.ttice_server_add_stream(probe, 3, arr, eps, 0, 0, 4, 64, ctypes.byref(sid)) == 0
+    c = ServerCounters()
+    assert L.ttice_server_stats(probe, ctypes.byref(c)) == 0
+    one = c.reserved_bytes
+    L.ttice_server_destroy(probe)
+    srv = vp()
+    assert L.ttice_server_create(1, 2 * one + one // 2, ctypes.byref(srv)) == 0
+    sids = []
+    for _ in range(3):
+        assert L.ttice_server_add_stream(srv, 3, arr, eps, 0, 0, 4, 64, ctypes.byref(sid)) == 0
+        sids.append(sid.value)
+    assert L.ttice_server_stats(srv, ctypes.byref(c)) == 0
+    assert c.waiting_streams == 1 and c.reserved_bytes == 2 * one, (c.waiting_streams, c.reserved_bytes, one)
+    h = vp()
+    assert L.ttice_server_stream_state(srv, sids[2], ctypes.byref(h)) == -4  # not admitted (ESTATE)
+    data = list(synth.smooth_separable_stream(6, dims, 3, 1e-3, 2, 77, dtype=np.float64))
+    keep, tickets = [], []
+    for Y in data:
+        Y = np.ascontiguousarray(Y)
+        keep.append(Y)
+        t = i64()
+        assert L.ttice_server_submit(srv, sids[2], Y.ctypes.data, Y.shape[0], 1, None, ctypes.byref(t)) == 0
+        tickets.append(t.value)
+    done = i32()
+    assert L.ttice_server_poll(srv, tickets[0], ctypes.byref(done), None, None) == 0 and done.value == 0
+    assert L.ttice_server_stats(srv, ctypes.byref(c)) == 0
+    assert c.pending == len(data)
+    assert L.ttice_server_remove_stream(srv, sids[0]) == 0  # frees one stream's budget: the third is admitted
+    status = i32()
+    for t in tickets:
+        assert L.ttice_server_wait(srv, t, ctypes.byref(status), None) == 0 and status.value == 0
+    assert L.ttice_server_stats(srv, ctypes.byref(c)) == 0
+    assert c.waiting_streams == 0 and c.reserved_bytes == 2 * one and c.pending == 0
+    assert L.ttice_server_stream_state(srv, sids[2], ctypes.byref(h)) == 0
+    served = EmuTTICE.borrowed(L, h, dims)
+    alone_srv, (asid,) = _server_run([(dims, eps, 0)], [data], 1, 1 << 40)
+    for Y in keep:
+        t = i64()
+        assert L.ttice_server_submit(alone_srv, asid, Y.ctypes.data, Y.shape[0], 1, None, ctypes.byref(t)) == 0
+        assert L.ttice_server_wait(alone_srv, t.value, ctypes.byref(status), None) == 0 and status.value == 0
+    ha = vp()
+    assert L.ttice_server_stream_state(alone_srv, asid, ctypes.byref(ha)) == 0
+    alone = EmuTTICE.borrowed(L, ha, dims)
+    assert served.ranks() == alone.ranks()
+    for i in range(len(dims) + 1):
+        assert np.array_equal(served.core(i), alone.core(i)), i
+    L.ttice_server_destroy(alone_srv)
+    # a waiting stream with nothing queued can be removed
+    assert L.ttice_server_add_stream(srv, 3, arr, eps, 0, 0, 4, 64, ctypes.byref(sid)) == 0
+    assert L.ttice_server_stats(srv, ctypes.byref(c)) == 0 and c.waiting_streams == 1
+    assert L.ttice_server_remove_stream(srv, sid.value) == 0
+    assert L.ttice_server_stats(srv, ctypes.byref(c)) == 0 and c.waiting_streams == 0
     L.ttice_server_destroy(srv)
 
 

@@ -11,6 +11,11 @@ import numpy as np
 TTICE_MAX_D = 16
 
 
+class ServerCounters(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in ("reserved_bytes", "budget_bytes", "pending", "waiting_streams",
+                                                    "groups", "grouped_increments")]
+
+
 class UpdateInfo(ctypes.Structure):
     _fields_ = [
         ("d", ctypes.c_int32), ("skipped", ctypes.c_int32), ("n", ctypes.c_int64),
@@ -58,13 +63,13 @@ def load(path):
     L.hipemu_fail_alloc_after.argtypes = [ctypes.c_longlong]
     L.hipemu_fail_alloc_after.restype = None
     L.ttice_server_create.argtypes = [i32, i64, ctypes.POINTER(vp)]
-    L.ttice_server_add_stream.argtypes = [vp, i32, ctypes.POINTER(i64), dbl, i32, i32, i64, ctypes.POINTER(i32)]
-    L.ttice_server_submit.argtypes = [vp, i32, vp, i64, i32, ctypes.POINTER(i64)]
+    L.ttice_server_add_stream.argtypes = [vp, i32, ctypes.POINTER(i64), dbl, i32, i32, i64, i64, ctypes.POINTER(i32)]
+    L.ttice_server_submit.argtypes = [vp, i32, vp, i64, i32, vp, ctypes.POINTER(i64)]
     L.ttice_server_poll.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(UpdateInfo)]
     L.ttice_server_wait.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(UpdateInfo)]
     L.ttice_server_stream_state.argtypes = [vp, i32, ctypes.POINTER(vp)]
     L.ttice_server_remove_stream.argtypes = [vp, i32]
-    L.ttice_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.ttice_server_stats.argtypes = [vp, ctypes.POINTER(ServerCounters)]
     L.ttice_server_destroy.argtypes = [vp]
     L.ttice_server_destroy.restype = None
     return L

@@ -325,6 +325,9 @@ hipError_t hipEventCreate(hipEvent_t* e) {
   *e = new double(0.0);
   return hipSuccess;
 }
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { return hipEventCreate(e); }
+// every emulated launch has completed when its call returns
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
 hipError_t hipEventDestroy(hipEvent_t e) {
   delete (double*)e;
   return hipSuccess;

@@ -172,6 +172,9 @@ inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
   return hipSuccess;
 }
 hipError_t hipEventCreate(hipEvent_t* e);
+#define hipEventDisableTiming 2
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned flags);
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned flags = 0);
 hipError_t hipEventDestroy(hipEvent_t e);
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s = nullptr);
 hipError_t hipEventSynchronize(hipEvent_t e);
