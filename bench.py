@@ -155,10 +155,13 @@ def run_video(prec):
 
 
 # level-1 projection kernel of each arm: (name, source file)
+# the level-1 projection kernel of each arm on the headline stream (8-row
+# unfoldings: the short-column kernel in FP64 and FP32, the split-BF16
+# matrix-core kernel otherwise) and its source file
 PROJ_KERNEL = {
-    "fp64": ("k_proj_mfma", "proj.hip"),
-    "fp32": ("k_proj_f32", "proj_lp.hip"),
-    "bf16x3": ("k_proj_bf3", "proj_lp.hip"),
+    "fp64": ("k_proj_short<float,double>", "proj_short.hip"),
+    "fp32": ("k_proj_short<float,float>", "proj_short.hip"),
+    "bf16x3": ("k_proj_bf3<float,4,1,1>", "proj_lp.hip"),
 }
 
 
@@ -169,7 +172,7 @@ def measured_traffic(prec):
     source."""
     import hashlib
     name, src_file = PROJ_KERNEL[prec]
-    path = os.path.join(ROOT, "profiles", f"{name}_field256_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{name.split('<')[0]}_{prec}_field256_traffic.txt")
     try:
         fields = dict(line.split(":", 1) for line in open(path).read().splitlines()
                       if ":" in line and not line.startswith("#"))
@@ -185,8 +188,8 @@ def measured_traffic(prec):
 def roofline(kstats, prec):
     """Level-1 projection kernel (U_1^T Y and ||Y(b)||^2 in one pass over the
     increment): algorithmic bytes per launch = the increment read once + the
-    r_1 coefficient rows written (FP64); duration = mean of its launches'
-    own start/end events over the stream."""
+    r_1 coefficient rows and the per-column energies written (FP64);
+    duration = mean of its launches' own start/end events over the stream."""
     n = kstats.get("launches", 0)
     if not n:
         return None

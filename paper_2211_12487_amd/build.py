@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = ["csrc/kernels.hip", "csrc/eig.hip", "csrc/proj.hip", "csrc/proj_lp.hip", "csrc/ttice.hip", "csrc/server.hip",
+SRC = ["csrc/kernels.hip", "csrc/eig.hip", "csrc/proj.hip", "csrc/proj_lp.hip", "csrc/proj_short.hip", "csrc/ttice.hip", "csrc/server.hip",
        "csrc/lanczos.hip", "csrc/gemm_mx.hip", "csrc/gemm_mx_lp.hip"]
 OUT = os.path.join(HERE, "libttice.so")
 ARCH = os.environ.get("TTICE_OFFLOAD_ARCH", "gfx950")

@@ -94,6 +94,17 @@ hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, c
                         int prec = kProjFP64, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
                         int vmax = 4);
 
+// The short-column form behind proj_columns (at most kShortRows rows and
+// core columns, FP64 or FP32 arithmetic, four aligned columns per thread):
+// a vector-ALU stream of the input and outputs, for unfoldings too short
+// for a matrix-core tile.
+constexpr int kShortRows = 8;
+bool proj_short_fits(int prec, int32_t rows, int32_t r);
+template <typename TIn>
+hipError_t proj_columns_short(hipStream_t st, int prec, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z,
+                              View vz, const double* U, int64_t ldu, double* C, View vc, double* znorm2,
+                              double* rho2, hipEvent_t ev_start, hipEvent_t ev_stop);
+
 // Several independent projections (one per stream of a server) in one
 // launch: descriptor q is proj_columns' arguments for one column per lane,
 // and its column blocks are blocks start[q] .. start[q + 1] - 1 of the grid.

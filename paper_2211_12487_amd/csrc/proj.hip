@@ -242,6 +242,9 @@ hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, c
       break;
     }
   }
+  // short columns (at most 8 rows) stream through the vector-ALU kernel
+  if (vec == 4 && proj_short_fits(prec, rows, r))
+    return proj_columns_short<TIn>(st, prec, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
   if (prec != kProjFP64)
     return proj_columns_lp<TIn>(st, prec, vec, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
   if (vec == 4) return launch_rt<TIn, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);

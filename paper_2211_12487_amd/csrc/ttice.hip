@@ -745,20 +745,25 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
     const bool small = rows * Ncol <= ((int64_t)1 << 22);
     bool have_R = false;
     double* cp = occ_skip ? nullptr : as<double>(colpart);
+    // the fused pass's residual energies: in reduced precision the explicit
+    // residual (below) writes them, so the pass does not
+    double* rho_out = pp == kProjFP64 ? cp : nullptr;
     // one pass: ||(I - U U^T) z||^2 = ||z||^2 - ||U^T z||^2 (orthonormal U),
     // in the state's precision (pp) or in FP64
     auto fused_pass = [&](int pp, bool timed) -> hipError_t {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (timed) {
         if (prof_begin(&e0, &e1) != TTICE_OK) return hipErrorOutOfMemory;
-        ev_bytes.push_back((double)N * P * sizeof(TIn) + (double)r * Ncol * sizeof(double));
+        // the batch read once; the coefficients and the per-column energies written
+        ev_bytes.push_back((double)N * P * sizeof(TIn) + (double)r * Ncol * sizeof(double) +
+                           (double)Ncol * sizeof(double) * ((bn ? 1 : 0) + (rho_out ? 1 : 0)));
       }
       const int vmax = l1_served ? 1 : 4;
       if (zin_is_input)
         return proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p, Ui.ld, out,
-                                 vout, bn, cp, pp, e0, e1, vmax);
+                                 vout, bn, rho_out, pp, e0, e1, vmax);
       return proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz, Ui.p, Ui.ld,
-                                  out, vout, bn, cp, pp, e0, e1, vmax);
+                                  out, vout, bn, rho_out, pp, e0, e1, vmax);
     };
     // R = Z - U C with per-column energies (eq:first_resid, eq:ithresidual),
     // FP64; written to rbuf when small enough to keep for the SVD
@@ -790,7 +795,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         dsc.ldu = Ui.ld;
         dsc.C = out;
         dsc.znorm2 = bn;
-        dsc.rho2 = cp;
+        dsc.rho2 = rho_out;
         if (l1_mode == 1) {
           l1_desc = dsc;
           l1_key = serve_key(pp, (int32_t)rows, (int32_t)r, sizeof(TIn) == sizeof(float));

@@ -7,7 +7,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
-SRCS = [os.path.join(ROOT, "paper_2211_12487_amd", "csrc", f) for f in ("kernels.hip", "eig.hip", "proj.hip", "ttice.hip", "server.hip",
+SRCS = [os.path.join(ROOT, "paper_2211_12487_amd", "csrc", f) for f in ("kernels.hip", "eig.hip", "proj.hip", "proj_short.hip", "ttice.hip", "server.hip",
                                                                           "lanczos.hip", "gemm_mx.hip")]
 
 

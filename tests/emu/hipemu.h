@@ -115,6 +115,11 @@ inline double __longlong_as_double(long long x) {
 // clang's 4 x double vector type, as GCC's generic vector of the same size
 // (the kernels only use it for FP64 MFMA accumulators)
 #define ext_vector_type(n) vector_size((n) * sizeof(double))
+// a cache hint only: a plain load on the host
+template <typename T>
+inline T __builtin_nontemporal_load(const T* p) {
+  return *p;
+}
 // FP64 16x16x4 matrix FMA over the 64 lanes of a wave: lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[l / 16 + 4 i][l % 16]
 inline hipemu::d4 __builtin_amdgcn_mfma_f64_16x16x4f64(double a, double b, hipemu::d4 c, int, int, int) {
