@@ -94,28 +94,35 @@ enum ttice_option {
                               counters); 0 = off                               */
   TTICE_OPT_SVD = 7        /* int32_t, solver of the residual's truncated SVD
                               (eq:svdfirst): 1 (default) = residuals whose
-                              Gram matrix is wider than 256 first try block
-                              Lanczos for the leading singular pairs (the
-                              truncation rank needs only those: the discarded
-                              energy is ||R||_F^2 minus their sum), accepted
-                              only when the residuals of its Ritz pairs
-                              certify the rank and the kept subspace, else
-                              the dense eigensolver runs; 0 = dense only;
+                              Gram matrix is wider than 256 and than twice
+                              the Krylov basis (4 blocks of 64 to 128
+                              vectors, sized from the core's last r_R) first
+                              try block Lanczos for the leading singular
+                              pairs (the truncation rank needs only those:
+                              the discarded energy is ||R||_F^2 minus their
+                              sum), accepted only when the residuals of its
+                              Ritz pairs certify the rank and the kept
+                              subspace (else once more with twice the block,
+                              then the dense eigensolver); 0 = dense only;
                               2 = as 1 for every Gram matrix wider than the
-                              Krylov basis (128)                             */
+                              basis, blocks from 32 vectors                  */
 };
 
 /* Kernels whose launches TTICE_OPT_PROFILE times. */
 enum ttice_kernel {
   TTICE_KERNEL_PROJ_L1 = 0 /* fused projection of level 1: one pass over each
                               increment giving U_1^T Y, ||Y(b)||^2 and the
-                              residual energy (eq:first_resid)               */
+                              residual energy (eq:first_resid); every such
+                              launch of an update in the state's precision,
+                              Algorithm 2's projections of the whole batch
+                              included                                       */
 };
 
 /* Accumulated timing of one kernel since profiling was enabled.  bytes is
  * the algorithmic HBM traffic of the launches: the increment read once
  * (n * prod(dims) * sizeof(element)) plus the coefficients written
- * (r_1 * n * n_2...n_d FP64). */
+ * (r_1 * n * n_2...n_d FP64) and the per-column energies the launch writes
+ * (n * n_2...n_d FP64 each). */
 struct ttice_kernel_stats {
   int64_t launches;
   double total_ms;

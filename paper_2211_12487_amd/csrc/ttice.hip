@@ -16,6 +16,7 @@
 //     the C-order reshape of eq:project_further is free in this layout.
 #include <hip/hip_runtime.h>
 
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -143,6 +144,7 @@ struct ttice_state {
   // kernel profiling (TTICE_OPT_PROFILE): event pairs recorded during one
   // update and resolved when it has completed
   bool profile = false;
+  bool in_update = false;  // an update is running (its chain projections are profiled too)
   std::vector<hipEvent_t> ev_pool;
   int ev_used = 0;
   std::vector<double> ev_bytes;
@@ -179,7 +181,7 @@ struct ttice_state {
   // candidates in W (rows x r_R, ld r_R) before re-orthogonalisation
   int dense_svd(int64_t rows, int64_t Ncol, const View& vR, bool left, double tol2, int64_t cap, int64_t* rR,
                 double* tail2, double* margin);
-  int lanczos_svd(int level, int64_t rows, int64_t Ncol, const View& vR, bool left, double tol2, int64_t cap,
+  int lanczos_svd(int level, int32_t b, int64_t rows, int64_t Ncol, const View& vR, bool left, double tol2, int64_t cap,
                   int64_t* rR, double* tail2, double* margin, bool* ok);
   int32_t lz_mode = 1;                       // 1: block Lanczos for wide Gram matrices, 0: dense only
   int64_t last_rR[TTICE_MAX_D] = {};          // last r_R decided per core (solver choice)
@@ -349,20 +351,33 @@ int32_t gram_kchunk(int32_t m, int64_t K) {
 // The last level's coefficients go to last_out (row j = frame j, stride
 // last_ld); last_out == nullptr means "into the last core after n_total".
 namespace {
-// Block-Lanczos truncated SVD: blocks of kLzBlock vectors, kLzSteps blocks
-// (a Krylov basis of kLzBasis vectors, whose projected matrix fits the
-// register tridiagonalisation); used for Gram matrices wider than kLzMinM.
-constexpr int32_t kLzBlock = 32;
+// Block-Lanczos truncated SVD: kLzSteps blocks of b vectors, a Krylov basis
+// of kLzSteps b vectors; used for Gram matrices wider than kLzMinM and than
+// twice the basis.  The block is wider than the core's last r_R + 1 by half
+// (a multiple of 32 in [64, 128], doubled once when the first result is not
+// certified): block Krylov methods converge on the leading eigenpairs at a
+// rate set by the ratio of the wanted eigenvalues to the (b+1)-st, so a
+// block that holds every wanted pair with room to spare converges in a few
+// steps even where the spectrum decays slowly.
+constexpr int32_t kLzBlockMin = 64, kLzBlockMax = 128;
+constexpr int32_t kLzBlockForced = 32;  // smallest block when the solver is forced (small test matrices)
 constexpr int32_t kLzSteps = 4;
-constexpr int32_t kLzBasis = kLzBlock * kLzSteps;
+constexpr int32_t kLzBasisMax = kLzBlockMax * kLzSteps;
 constexpr int64_t kLzMinM = 256;
-// Acceptance of the kept Ritz pairs: the bound sum eta^2 / gap of their
-// eigenvalue error within kLzTailTol of the distance of the rank decision
-// from the tolerance, and the bound ||E||_F / gap of the kept subspace's
-// angle within kLzAngleTol (E: the residuals G x - theta x).
+int32_t lz_block(int64_t last_rR, int32_t bmin) {
+  const int64_t want = (3 * (last_rR + 1) / 2 + 31) / 32 * 32;
+  return (int32_t)std::min<int64_t>(kLzBlockMax, std::max<int64_t>(bmin, want));
+}
+// Certificate: the rank decision must hold with the kept eigenvalues' error
+// bound (sum eta^2 / gap) within kLzTailTol of its distance to the tolerance,
+// and the kept subspace's angle bound ||E||_F / gap must be within
+// kLzAngleTol, or ||E||_F itself at working accuracy (kLzResUlps units of
+// roundoff of the largest eigenvalue: what the dense solver's own rounding
+// leaves; E: the residuals G x - theta x).
 constexpr double kLzTailTol = 1e-6;
 constexpr double kLzAngleTol = 1e-12;
-constexpr int kLzHost = 2 * kLzBasis + 16;  // doubles of the pinned host buffer hl
+constexpr double kLzResUlps = 64.0;
+constexpr int kLzHost = 2 * kLzBasisMax + 16;  // doubles of the pinned host buffer hl
 }  // namespace
 
 int ttice_state::dense_svd(int64_t rows, int64_t Ncol, const View& vR, bool left, double tol2, int64_t cap,
@@ -447,14 +462,14 @@ int ttice_state::dense_svd(int64_t rows, int64_t Ncol, const View& vR, bool left
 #else
 #define LZ_REJECT return TTICE_OK
 #endif
-int ttice_state::lanczos_svd(int level, int64_t rows, int64_t Ncol, const View& vR, bool left, double tol2,
+int ttice_state::lanczos_svd(int level, int32_t b, int64_t rows, int64_t Ncol, const View& vR, bool left, double tol2,
                              int64_t cap, int64_t* rR_out, double* tail2_out, double* margin_out, bool* ok) {
   hipStream_t st = stream;
   *ok = false;
   ++lz_tries;
   const int64_t m = left ? rows : Ncol;
   const int64_t mo = left ? Ncol : rows;  // the other side of R
-  const int32_t b = kLzBlock, sb = kLzBasis;
+  const int32_t sb = kLzSteps * b;
   const double* R = as<double>(rbuf);
   const View vRt = transposed(vR);
   if (!hl) {
@@ -594,9 +609,9 @@ int ttice_state::lanczos_svd(int level, int64_t rows, int64_t Ncol, const View& 
     CK((gemm<double, double, double>(st, (int32_t)m, kc, sb, sb, 1.0, Q, q, Sv, vc, 0.0, (const double*)nullptr,
                                      View(), X, vc, 0, nullptr, nullptr, gws())));
     CK(G(X, vc, kc, GX, vc));  // Y
-    // hl: [0, kLzBasis) eta_j^2 and [kLzBasis, 2 kLzBasis) theta_j of the
-    // polished pairs; then eta^2, theta of the first discarded pair; trace
-    double* hd = hl + 2 * kLzBasis;
+    // hl: [0, kLzBasisMax) eta_j^2 and [kLzBasisMax, 2 kLzBasisMax) theta_j of
+    // the polished pairs; then eta^2, theta of the first discarded pair; trace
+    double* hd = hl + 2 * kLzBasisMax;
     CK(ritz_residuals(st, (int32_t)m, 1, kc, X + kp, GX + kp, wv + kp, hd, hd + 1));
     CK(hipMemcpyAsync(hd + 2, trace, sizeof(double), hipMemcpyDeviceToHost, st));
     // two Cholesky QR passes: Y's first r_R columns -> Q (scratch) -> X
@@ -624,14 +639,14 @@ int ttice_state::lanczos_svd(int level, int64_t rows, int64_t Ncol, const View& 
                                      View(), Q, vk, 0, nullptr, nullptr, gws())));
     CK((gemm<double, double, double>(st, (int32_t)m, kp, kp, kp, 1.0, GX, vk, Sv, vk, 0.0, (const double*)nullptr,
                                      View(), GQ, vk, 0, nullptr, nullptr, gws())));
-    CK(ritz_residuals(st, (int32_t)m, kp, kp, Q, GQ, wv, hl, hl + kLzBasis));
+    CK(ritz_residuals(st, (int32_t)m, kp, kp, Q, GQ, wv, hl, hl + kLzBasisMax));
     CKS(sync_scalars(0));
     // the decision again from the polished Ritz values (lower bounds of
     // the leading eigenvalues, so trace minus their sum bounds every tail
     // from above): it must agree, and the error bounds of the kept
     // eigenvalues (sum eta^2 / gap) and of the kept subspace's angle
     // (||E||_F / gap) must not be able to move it or the result
-    const double* th = hl + kLzBasis;
+    const double* th = hl + kLzBasisMax;
     const double trv = hd[2];
     double esum = 0.0, s_prev = 0.0;
     for (int32_t j = 0; j < kp; ++j) {
@@ -655,7 +670,7 @@ int ttice_state::lanczos_svd(int level, int64_t rows, int64_t Ncol, const View& 
 #endif
     if (!(th[0] > 0.0) || !(gap > 0.0)) LZ_REJECT;
     if (!capped && esum / gap > kLzTailTol * margin * tol2) LZ_REJECT;
-    if (sqrt(esum) / gap > kLzAngleTol) LZ_REJECT;
+    if (sqrt(esum) / gap > kLzAngleTol && sqrt(esum) > kLzResUlps * DBL_EPSILON * th[0]) LZ_REJECT;
   }
   // (r_R = 0 is decided by the trace alone, which is exact)
   ++lz_accepted;
@@ -865,8 +880,14 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         // workspace for it is allocated
         if (m > sym_eig_max()) return TTICE_EINVAL;
         bool have_svd = false;
-        if (lz_mode != 0 && m > (lz_mode == 2 ? (int64_t)kLzBasis : kLzMinM) && last_rR[i] < kLzBasis / 2)
-          CKS(lanczos_svd(i, rows, Ncol, vr, left, tol2, rows - r, &rR, &tail2, &margin, &have_svd));
+        // the block from the core's last r_R, and once more with twice the
+        // block when that result is not certified
+        const int32_t bmin = lz_mode == 2 ? kLzBlockForced : kLzBlockMin;
+        for (int32_t b = lz_block(last_rR[i], bmin); lz_mode != 0 && !have_svd && b <= kLzBlockMax; b *= 2) {
+          const int64_t basis = (int64_t)kLzSteps * b;
+          if (!(m > (lz_mode == 2 ? basis : std::max<int64_t>(kLzMinM, 2 * basis)) && last_rR[i] < basis / 2)) break;
+          CKS(lanczos_svd(i, b, rows, Ncol, vr, left, tol2, rows - r, &rR, &tail2, &margin, &have_svd));
+        }
         if (!have_svd) CKS(dense_svd(rows, Ncol, vr, left, tol2, rows - r, &rR, &tail2, &margin));
         last_rR[i] = rR;
         solver = have_svd ? 2 : 1;
@@ -1026,12 +1047,19 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
     double* fsl_p = cw ? cw->fsl : fscratch(N);
     // C = U^T Z (the next level's data, eq:project_further)
     if (fused) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      // the level-1 pass in the state's arithmetic is profiled with the core loop's
+      if (profile && in_update && i == 0 && pp == proj_prec()) {
+        CKS(prof_begin(&e0, &e1));
+        ev_bytes.push_back((double)N * P * sizeof(TIn) + (double)r * Ncol * sizeof(double) +
+                           (bn ? (double)Ncol * sizeof(double) : 0.0));
+      }
       if (zin_is_input)
         CK((proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p, Ui.ld, out,
-                              vout, bn, nullptr, pp)));
+                              vout, bn, nullptr, pp, e0, e1)));
       else
         CK((proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz, Ui.p, Ui.ld,
-                                 out, vout, bn, nullptr, pp)));
+                                 out, vout, bn, nullptr, pp, e0, e1)));
     } else {
       if (zin_is_input)
         CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
@@ -1071,6 +1099,11 @@ int ttice_state::chain_project(const TIn* zin0, int64_t N, const int64_t* rks, d
 
 template <typename TIn>
 int ttice_state::update_impl(const TIn* batch, int64_t N, ttice_update_info* info) {
+  struct InUpdate {
+    bool& f;
+    ~InUpdate() { f = false; }
+  } in_scope{in_update};
+  in_update = true;
   hipStream_t st = stream;
   CKS(ensure(z[0], (size_t)N * P * sizeof(double)));
   CKS(ensure(z[1], (size_t)N * P * sizeof(double)));

@@ -4,7 +4,8 @@ workloads, through the C ABI, in the FP64 and the reduced-precision arms.
 * the video-shaped stream (2048 frames of 240x320x3 in increments of 32,
   eps = 0.1, Algorithm 1), all 64 increments, FP64 and FP32 arms;
 * the simulation-shaped stream (64^3 x 3 snapshots in increments of 16,
-  eps = 0.01), its first four full-size increments in the FP32 arm;
+  eps = 0.01), its first six increments in the FP64 and FP32 arms (the
+  block-Lanczos solver on core 2 from the second increment on);
 * the order-8 reshaped 256^3 field (8^8, increments of 8, eps = 0.005,
   Algorithm 2 with the mean rule), its first increment in the FP32 and the
   split-BF16 arms;
@@ -65,12 +66,14 @@ def oracle_run(dims, eps, batches, **kw):
     return o, infos, recs
 
 
-def gpu_against(o_infos, o_recs, dims, eps, batches, prec, label, **kw):
+def gpu_against(o_infos, o_recs, dims, eps, batches, prec, label, solvers=None, **kw):
     from paper_2211_12487_amd.ttice import TTICE
     g = TTICE(dims, eps, prec=prec, **kw)
     compared = 0
     for k, (Y, oi, orec) in enumerate(zip(batches, o_infos, o_recs)):
         gi = g.update(to_dev(Y))
+        if solvers is not None:
+            solvers.append(gi["solver"])
         margins = [m for m in oi["margin"] if m == m]
         decisive = all(m > MARGIN[prec] for m in margins) if margins else True
         if gi["ranks"][1:-1] != oi["ranks"][1:-1]:
@@ -117,13 +120,27 @@ def test_video_stream_all_increments(video_oracle, prec):
 
 # ---- the simulation-shaped stream, first four increments ------------------
 
-def test_field64_stream_fp32():
-    log("case field64 (64^3 x 3), 4 increments of 16, prec=fp32")
+@pytest.fixture(scope="module")
+def field64_oracle():
     dims, eps = (64, 64, 64, 3), 0.01
-    batches = list(synth.fourier_field_stream(64, 16, grid=64, components=3, seed=0))
+    batches = list(synth.fourier_field_stream(96, 16, grid=64, components=3, seed=0))
+    log("oracle: field64 stream, 6 increments")
     _, infos, recs = oracle_run(dims, eps, batches)
-    n = gpu_against(infos, recs, dims, eps, batches, "fp32", "field64-fp32")
+    return batches, infos, recs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_field64_stream(field64_oracle, prec):
+    """Six increments; from the second on, core 2's residual Gram matrix
+    (1088 wide, r_R about 20-40) goes to the block-Lanczos solver with a
+    64-vector block, whose certified result must match the oracle."""
+    log(f"case field64 (64^3 x 3), 6 increments of 16, prec={prec}")
+    dims, eps = (64, 64, 64, 3), 0.01
+    batches, infos, recs = field64_oracle
+    solvers = []
+    n = gpu_against(infos, recs, dims, eps, batches, prec, f"field64-{prec}", solvers=solvers)
     assert n >= 2
+    assert any(2 in s for s in solvers), solvers
 
 
 # ---- the order-8 reshaped field, first increment -------------------------
