@@ -93,7 +93,7 @@ def timed_positions(n_inc, k):
 
 def run_field_arm(increment, n_inc, prec, steps, warmup):
     """One arm over the whole stream: per-increment update wall times, the
-    timed subset, final ranks, skipped increments, FP64 rechecks and the
+    timed subset, final ranks, skipped increments and the
     level-1 projection kernel's event timings."""
     import torch
     from paper_2211_12487_amd.ttice import TTICE
@@ -107,7 +107,7 @@ def run_field_arm(increment, n_inc, prec, steps, warmup):
     g.profile(True)
     pos = timed_positions(n_inc, steps)
     lat, timed = [], []
-    skipped = rechecks = 0
+    skipped = 0
     for k in range(n_inc):
         Y = increment(k)
         torch.cuda.synchronize()
@@ -118,7 +118,6 @@ def run_field_arm(increment, n_inc, prec, steps, warmup):
         if k in pos:
             timed.append(dt)
         skipped += int(info["skipped"])
-        rechecks += int(info["star_rechecked"])
         del Y
         if k % 64 == 63:
             print(f"  {prec}: {k + 1}/{n_inc} increments, {sum(lat):.2f} s", file=sys.stderr, flush=True)
@@ -130,7 +129,7 @@ def run_field_arm(increment, n_inc, prec, steps, warmup):
     return dict(value=N * len(timed) / sum(timed), timed=len(timed), timed_seconds=sum(timed),
                 full_stream_tensors_per_s=N * n_inc / sum(lat), seconds=sum(lat),
                 p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-                ranks=ranks, skipped=skipped, fp64_rechecks=rechecks, kstats=ks)
+                ranks=ranks, skipped=skipped, kstats=ks)
 
 
 def run_video(prec):
@@ -502,7 +501,7 @@ def main():
                              f"TT-ICE* (Algorithm 2, mean rule) from empty cores",
                     snapshots=n_inc * w["batch"], batch=w["batch"], eps=w["eps"], prec=a.prec),
         full_stream_tensors_per_s=chosen["full_stream_tensors_per_s"], stream_seconds=chosen["seconds"],
-        final_ranks=chosen["ranks"], skipped_increments=chosen["skipped"], fp64_rechecks=chosen["fp64_rechecks"],
+        final_ranks=chosen["ranks"], skipped_increments=chosen["skipped"],
         p50_update_ms=chosen["p50_ms"], p99_update_ms=chosen["p99_ms"],
         fp64_arm=(dict(value=fp64["value"], full_stream_tensors_per_s=fp64["full_stream_tensors_per_s"],
                        stream_seconds=fp64["seconds"], final_ranks=fp64["ranks"],

@@ -48,21 +48,20 @@ enum ttice_status {
 
 enum ttice_dtype { TTICE_F32 = 0, TTICE_F64 = 1 };
 
-/* Arithmetic of the level projections C = U_i^T Z_i (eq:first_resid /
- * eq:project_further: the one-pass projection of narrow cores and the large
- * products of wide ones, in the update loop, the TT-ICE* chain and
- * ttice_project): FP64 matrix cores; FP32 matrix cores with FP32
- * accumulation (large products of wide cores stay FP64); or split BF16
- * (each operand as hi + lo bf16, the three products hi*hi + hi*lo + lo*hi
- * on BF16 matrix cores, FP32 accumulation).  ||Y||, the residual's SVD, the
- * re-orthogonalisation and every rank decision are FP64 in all modes.  In
- * the reduced modes the norm test's residual R = Z - U C~ is formed from the
- * rounded coefficients in FP64, so its energy ||R||^2 + ||C~ - C||^2 never
- * falls below the exact one; the TT-ICE* chain forms each level's residual
- * in the reduced arithmetic (FP64 energies), and its decisions are taken
- * again on an FP64 chain when a relative error lies within 5% (split BF16)
- * or 0.2% (FP32) of eps.  Reconstructions agree with the FP64 path to about
- * 1e-5 relative in the reduced modes. */
+/* Arithmetic of the level products (eq:first_resid / eq:project_further:
+ * C = U_i^T Z_i, the one-pass projection of narrow cores and the large
+ * products of wide ones, the new rows U_R^T Z of the next level, in the
+ * update loop, in Algorithm 2's projection of the batch after an update and
+ * in ttice_project): FP64 (matrix cores, or vector FMAs for unfoldings of at
+ * most 8 rows); FP32 with FP32 accumulation; or split BF16 (each operand as
+ * hi + lo bf16, the three products hi*hi + hi*lo + lo*hi on BF16 matrix
+ * cores, FP32 accumulation).  Everything that decides the eps guarantee is
+ * FP64 in all modes: ||Y||; the norm test's residual R = Z - U C~, formed
+ * from the rounded coefficients in FP64 (its energy ||R||^2 + ||C~ - C||^2
+ * never falls below the exact one); Algorithm 2's relative errors (an FP64
+ * chain, by telescoping); the residual's SVD and the re-orthogonalisation.
+ * Reconstructions agree with the FP64 path to about 1e-5 relative (FP32) or
+ * 3e-4 (split BF16: its operands keep 16 significant bits). */
 enum ttice_prec { TTICE_PREC_FP64 = 0, TTICE_PREC_FP32 = 1, TTICE_PREC_BF16X3 = 2 };
 
 /* Algorithm 1 (TT-ICE) or Algorithm 2 (TT-ICE*). */
@@ -155,9 +154,6 @@ struct ttice_update_info {
   int32_t solver[TTICE_MAX_D];    /* truncated SVD of core i's residual: 0 none
                                      (norm test passed or core skipped), 1 dense
                                      eigensolver, 2 block Lanczos (TTICE_OPT_SVD) */
-  int32_t star_rechecked;         /* 1 when Algorithm 2's decisions were taken
-                                     again on an FP64 chain (reduced precision:
-                                     a relative error near eps, TTICE_OPT_PREC) */
 };
 
 /* Create an empty accumulation for d-way tensors of size dims[0..d-1] with

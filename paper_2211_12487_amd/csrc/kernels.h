@@ -87,12 +87,14 @@ bool proj_fits(int32_t rows, int32_t r);
 // the kernel alone).
 constexpr int kProjFP64 = 0, kProjFP32 = 1, kProjBF16x3 = 2;
 // vmax caps the columns per lane (1, 2 or 4; the widest the alignment allows
-// up to vmax is taken).
+// up to vmax is taken).  *rho_explicit (if given) tells whether rho2 was
+// formed explicitly, ||z - U c~||^2 in FP64 from the rounded coefficients
+// (the short-column kernel), rather than by Pythagoras.
 template <typename TIn>
 hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
                         const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2,
                         int prec = kProjFP64, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
-                        int vmax = 4);
+                        int vmax = 4, bool* rho_explicit = nullptr);
 
 // The short-column form behind proj_columns (at most kShortRows rows and
 // core columns, FP64 or FP32 arithmetic, four aligned columns per thread):

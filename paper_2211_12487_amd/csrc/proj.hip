@@ -230,7 +230,8 @@ bool proj_fits(int32_t rows, int32_t r) { return r <= 64 && rows > 0; }
 template <typename TIn>
 hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, const TIn* Z, View vz,
                         const double* U, int64_t ldu, double* C, View vc, double* znorm2, double* rho2, int prec,
-                        hipEvent_t ev0, hipEvent_t ev1, int vmax) {
+                        hipEvent_t ev0, hipEvent_t ev1, int vmax, bool* rho_explicit) {
+  if (rho_explicit) *rho_explicit = false;
   if (Ncol <= 0) return hipSuccess;
   if (vz.rpf != kUnframed || vc.rpf != kUnframed || r > 64 || rows <= 0) return hipErrorInvalidValue;
   // the widest instantiation reads 16 * 4 doubles of every row of U
@@ -243,8 +244,10 @@ hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, c
     }
   }
   // short columns (at most 8 rows) stream through the vector-ALU kernel
-  if (vec == 4 && proj_short_fits(prec, rows, r))
+  if (vec == 4 && proj_short_fits(prec, rows, r)) {
+    if (rho_explicit) *rho_explicit = true;
     return proj_columns_short<TIn>(st, prec, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
+  }
   if (prec != kProjFP64)
     return proj_columns_lp<TIn>(st, prec, vec, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
   if (vec == 4) return launch_rt<TIn, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
@@ -253,9 +256,11 @@ hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, c
 }
 
 template hipError_t proj_columns<float>(hipStream_t, int32_t, int32_t, int32_t, const float*, View, const double*,
-                                        int64_t, double*, View, double*, double*, int, hipEvent_t, hipEvent_t, int);
+                                        int64_t, double*, View, double*, double*, int, hipEvent_t, hipEvent_t, int,
+                                        bool*);
 template hipError_t proj_columns<double>(hipStream_t, int32_t, int32_t, int32_t, const double*, View, const double*,
-                                         int64_t, double*, View, double*, double*, int, hipEvent_t, hipEvent_t, int);
+                                         int64_t, double*, View, double*, double*, int, hipEvent_t, hipEvent_t, int,
+                                         bool*);
 
 // ---- grouped launches (one column per lane, the single launch's shape)
 int32_t proj_shape(int prec, int32_t rows, int32_t r) {

@@ -194,14 +194,6 @@ struct ttice_state {
   double* fscratch(int64_t N) {
     return ensure(fsl, (size_t)N * kFrameSlicesMax * sizeof(double)) == TTICE_OK ? as<double>(fsl) : nullptr;
   }
-  // relative distance from eps within which a reduced-precision chain's
-  // relative errors do not decide Algorithm 2.  A level's residual R~ = Z~
-  // - U C~ is off by the product's rounding, about 2^-16 ||z|| (split BF16)
-  // or 2^-24 sqrt(K) ||z|| with K up to ~10^4 (FP32), relative to ||R|| ~
-  // eps ||z||: ~3e-3 or ~1e-4 at eps = 0.005 per level, a few levels
-  // adding; the bands keep a factor of about five above that
-  double star_band() const { return prec == TTICE_PREC_BF16X3 ? 0.05 : 0.002; }
-  int64_t lp_rechecks = 0;  // Algorithm 2 decisions taken again on an FP64 chain (reduced precision)
   // Serving (server.hip): a served state's level 1 (Algorithm 1) always
   // takes the fused projection with one column per lane, the form a grouped
   // launch over several streams computes bit for bit.  l1_mode 1 stops an
@@ -731,6 +723,10 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
 
     const double occupancy = rows > 0 ? (double)r / (double)rows : 1.0;
     const bool occ_skip = use_occ && occupancy >= tau;
+    // a core whose columns span its whole row space (r = rows: U_i square
+    // and orthogonal) leaves a zero residual: nothing to test or append
+    const bool full = r >= rows;
+    const bool no_resid = occ_skip || full;
     int64_t rR = 0;
     int32_t solver = 0;
     double rho2 = std::numeric_limits<double>::quiet_NaN(), tail2 = 0.0;
@@ -749,20 +745,23 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
     if (i == 0 && l1_mode == 2 && !l1_served) return TTICE_EDEVICE;  // the captured launch does not apply
     const bool fused = proj_fits((int32_t)rows, (int32_t)r) && (Ncol >= kFusedMinCols || l1_served);
     const int pp = proj_prec();
-    // the fused FP64 pass gives the residual energies by Pythagoras (one
-    // row of partials); in reduced precision they come from the explicit
-    // residual (partials per 64-row block)
-    const int32_t MB = (fused && pp == kProjFP64) ? 1 : gemm_row_blocks((int32_t)rows);
-    CKS(ensure(colpart, (size_t)MB * Ncol * sizeof(double)));
+    // the fused FP64 pass gives the residual energies by Pythagoras, the
+    // short-column kernel explicitly (one row of partials either way); in
+    // reduced precision they otherwise come from the explicit residual
+    // (partials per 64-row block)
+    const int32_t MB_alloc = (fused && pp == kProjFP64) ? 1 : gemm_row_blocks((int32_t)rows);
+    CKS(ensure(colpart, (size_t)MB_alloc * Ncol * sizeof(double)));
     CKS(ensure(fres, (size_t)N * sizeof(double)));
     CKS(ensure(rbuf, (size_t)std::max<int64_t>(1, rows * Ncol) * sizeof(double)));
     const View vr = unfolding(cols, rows * cols);
     const bool small = rows * Ncol <= ((int64_t)1 << 22);
     bool have_R = false;
-    double* cp = occ_skip ? nullptr : as<double>(colpart);
-    // the fused pass's residual energies: in reduced precision the explicit
+    double* cp = no_resid ? nullptr : as<double>(colpart);
+    // the fused pass's residual energies: in reduced precision only the
+    // short-column kernel's (formed explicitly); otherwise the explicit
     // residual (below) writes them, so the pass does not
-    double* rho_out = pp == kProjFP64 ? cp : nullptr;
+    double* rho_out = (pp == kProjFP64 || proj_short_fits(pp, (int32_t)rows, (int32_t)r)) ? cp : nullptr;
+    bool rho_explicit = false;
     // one pass: ||(I - U U^T) z||^2 = ||z||^2 - ||U^T z||^2 (orthonormal U),
     // in the state's precision (pp) or in FP64
     auto fused_pass = [&](int pp, bool timed) -> hipError_t {
@@ -776,9 +775,9 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       const int vmax = l1_served ? 1 : 4;
       if (zin_is_input)
         return proj_columns<TIn>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const TIn*)zin, vz, Ui.p, Ui.ld, out,
-                                 vout, bn, rho_out, pp, e0, e1, vmax);
+                                 vout, bn, rho_out, pp, e0, e1, vmax, &rho_explicit);
       return proj_columns<double>(st, (int32_t)rows, (int32_t)r, (int32_t)Ncol, (const double*)zin, vz, Ui.p, Ui.ld,
-                                  out, vout, bn, rho_out, pp, e0, e1, vmax);
+                                  out, vout, bn, rho_out, pp, e0, e1, vmax, &rho_explicit);
     };
     // R = Z - U C with per-column energies (eq:first_resid, eq:ithresidual),
     // FP64; written to rbuf when small enough to keep for the SVD
@@ -810,7 +809,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         dsc.ldu = Ui.ld;
         dsc.C = out;
         dsc.znorm2 = bn;
-        dsc.rho2 = rho_out;
+        dsc.rho2 = pp == kProjFP64 ? cp : nullptr;
         if (l1_mode == 1) {
           l1_desc = dsc;
           l1_key = serve_key(pp, (int32_t)rows, (int32_t)r, sizeof(TIn) == sizeof(float));
@@ -821,7 +820,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       } else {
         CK(fused_pass(pp, profile && i == 0));
       }
-      if (pp != kProjFP64 && !occ_skip) CK(residual());
+      if (pp != kProjFP64 && !no_resid && !rho_explicit) CK(residual());
     } else {
       if (zin_is_input) {
         CK((gemm<TIn, TIn, double>(st, (int32_t)r, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Ui.p,
@@ -832,8 +831,9 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
                                          Ui.p, vUt, (const double*)zin, vz, 0.0, (const double*)nullptr,
                                          View(), out, vout, 0, nullptr, bn, gws(), pp)));
       }
-      if (!occ_skip) CK(residual());
+      if (!no_resid) CK(residual());
     }
+    const int32_t MB = (fused && (pp == kProjFP64 || rho_explicit)) ? 1 : gemm_row_blocks((int32_t)rows);
 
     if (i == 0 && tol2 < 0) {
       CKS(ensure(fy2, (size_t)N * sizeof(double)));
@@ -841,9 +841,11 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
       CK(total_sum(st, as<double>(fy2), N, hs + 2));
     }
 
-    if (!occ_skip) {
-      CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres), fscratch(N)));
-      CK(total_sum(st, as<double>(fres), N, hs));
+    if (!no_resid || (i == 0 && tol2 < 0)) {
+      if (!no_resid) {
+        CK(frame_sums(st, as<double>(colpart), MB, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres), fscratch(N)));
+        CK(total_sum(st, as<double>(fres), N, hs));
+      }
       CKS(sync_scalars(4));
       if (i == 0 && tol2 < 0) {
         const double ny2 = hs[2];
@@ -853,6 +855,9 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         tol2 = tol * tol;
         if (info) info->eps_core = tol;
       }
+    }
+    if (full && !occ_skip) rho2 = 0.0;
+    if (!no_resid) {
       rho2 = hs[0];
       if (hs[1] != 0.0 || !isfinite(rho2)) return TTICE_EINVAL;
       rho2 = std::max(rho2, 0.0);
@@ -1123,27 +1128,23 @@ int ttice_state::update_impl(const TIn* batch, int64_t N, ttice_update_info* inf
       info->achieved2 = a;
     }
   } else {
-    // Algorithm 2: relative errors with the existing cores (eq:relerror)
+    // Algorithm 2: relative errors with the existing cores (eq:relerror).
+    // They decide the skip and the subset D (the eps guarantee of the
+    // stored tensors), so they come from an FP64 chain in every precision:
+    // each step is an orthogonal projection and the residual energy of a
+    // tensor is the telescoping difference ||Y(b)||^2 - ||c(b)||^2, with no
+    // residual formed at any level.  (The coefficients it leaves in the
+    // last core are those of a skipped increment.)
     CKS(ensure(e2acc, (size_t)N * sizeof(double)));
     CKS(ensure(fy2, (size_t)N * sizeof(double)));
     CKS(ensure(dlist, (size_t)N * sizeof(int32_t)));
     int nonfinite = 0;
     CKS(chain_project<TIn>(batch, N, rkp, Gt.p + n_total * Gt.ld, Gt.ld, as<double>(e2acc), as<double>(fy2),
-                           &nonfinite, nullptr, proj_prec()));
+                           &nonfinite, nullptr, kProjFP64));
     if (nonfinite) return TTICE_EINVAL;
     CK(star_decide(st, (int32_t)N, as<double>(e2acc), as<double>(fy2), eps, as<int32_t>(dlist),
                    hs));
     CKS(sync_scalars(7));
-    if (proj_prec() != kProjFP64 && hs[6] <= star_band()) {
-      // a relative error within the reduced arithmetic's band of eps: the
-      // decisions (skip, the subset D) are taken on the FP64 chain instead
-      CKS(chain_project<TIn>(batch, N, rkp, Gt.p + n_total * Gt.ld, Gt.ld, as<double>(e2acc), as<double>(fy2),
-                             nullptr, nullptr, kProjFP64));
-      CK(star_decide(st, (int32_t)N, as<double>(e2acc), as<double>(fy2), eps, as<int32_t>(dlist), hs));
-      CKS(sync_scalars(7));
-      ++lp_rechecks;
-      if (info) info->star_rechecked = 1;
-    }
     const double mean_rel = hs[0], batch_rel = hs[1], sdc = hs[2], nd2 = hs[3];
     const int64_t nD = (int64_t)hs[4];
     const double ny2 = hs[5];

@@ -77,7 +77,6 @@ class UpdateInfo(ctypes.Structure):
         ("margin", ctypes.c_double * TTICE_MAX_D),
         ("achieved2", ctypes.c_double),
         ("solver", ctypes.c_int32 * TTICE_MAX_D),
-        ("star_rechecked", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -89,7 +88,6 @@ class UpdateInfo(ctypes.Structure):
             tail2=list(self.tail2[:d]), margin=list(self.margin[:d]),
             achieved2=(self.achieved2 if self.achieved2 >= 0 else None),
             solver=list(self.solver[:d]),
-            star_rechecked=bool(self.star_rechecked),
         )
 
 

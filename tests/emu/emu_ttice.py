@@ -25,7 +25,6 @@ class UpdateInfo(ctypes.Structure):
         ("rho2", ctypes.c_double * TTICE_MAX_D), ("tail2", ctypes.c_double * TTICE_MAX_D),
         ("margin", ctypes.c_double * TTICE_MAX_D), ("achieved2", ctypes.c_double),
         ("solver", ctypes.c_int32 * TTICE_MAX_D),
-        ("star_rechecked", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -35,8 +34,7 @@ class UpdateInfo(ctypes.Structure):
                     ranks=list(self.ranks[: d + 2]), rR=list(self.r_new[:d]), rho2=list(self.rho2[:d]),
                     tail2=list(self.tail2[:d]), margin=list(self.margin[:d]),
                     achieved2=(self.achieved2 if self.achieved2 >= 0 else None),
-                    solver=list(self.solver[:d]),
-                    star_rechecked=bool(self.star_rechecked))
+                    solver=list(self.solver[:d]))
 
 
 class EmuError(RuntimeError):
