@@ -179,7 +179,10 @@ __device__ void split_finish(double (&acc)[4][4], int32_t M, int32_t N, int32_t 
         const int32_t m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
         if (m < M && n < N) part[(int64_t)blockIdx.z * MN + (int64_t)m * N + n] = acc[i][j];
       }
+    // every thread's partials are visible device-wide before the block's
+    // arrival is counted
     __threadfence();
+    __syncthreads();
     __shared__ int last;
     const int tile = (int)(blockIdx.y * gridDim.x + blockIdx.x);
     if (t == 0) last = atomicAdd(&cnt[tile], 1) == S - 1;
