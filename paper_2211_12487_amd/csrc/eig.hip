@@ -393,7 +393,10 @@ __global__ __launch_bounds__(NW * 64) void k_tridiag_rw(int32_t n, int32_t ksw, 
     }
   };
 
-  // column 0
+  // column 0; the slots of both column buffers past the rows the waves
+  // hold start at zero (never left to what an earlier kernel put there)
+  for (int i = (int)threadIdx.x; i < 2 * NC; i += NW * 64) xcol[i / NC][i % NC] = 0.0;
+  __syncthreads();
   if (l == 0 && r0 < n) {
     dbl2* dst = (dbl2*)&xcol[0][r0];
 #pragma unroll
@@ -418,7 +421,7 @@ __global__ __launch_bounds__(NW * 64) void k_tridiag_rw(int32_t n, int32_t ksw, 
       for (int c = 0; c < CPL; ++c) {
         const int32_t j = l + 64 * c;
         x[c] = fma(-wk, vc[c], xcol[buf][j] - wc[c]);
-        s = fma(x[c], (j >= k + 2 && j < n) ? x[c] : 0.0, s);
+        if (j >= k + 2 && j < n) s = fma(x[c], x[c], s);
       }
       const double sigma = wave_sum(s);
       const double alpha = readlane_f64(x[SK1], kl1);
@@ -745,10 +748,12 @@ __global__ __launch_bounds__(256) void k_bisect(int32_t m, const double* __restr
                                                 RankSelect sel) {
   HIP_DYNAMIC_SHARED(double, lds);
   __shared__ double rlo[4], rhi[4], remax[4];
+  __shared__ int rbad[4];
   double* dS = lds;
   double* e2S = lds + m;  // e2S[i] = e[i-1]^2, e2S[0] = 0
   const int t = threadIdx.x;
   double lo = 1e300, hi = -1e300, emax = 0.0;
+  bool nonfin = false;
   for (int32_t i = t; i < m; i += 256) {
     const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < m ? fabs(e[i]) : 0.0);
     dS[i] = d[i];
@@ -756,7 +761,10 @@ __global__ __launch_bounds__(256) void k_bisect(int32_t m, const double* __restr
     lo = fmin(lo, d[i] - r);
     hi = fmax(hi, d[i] + r);
     if (i + 1 < m) emax = fmax(emax, e[i] * e[i]);
+    if (!isfinite(d[i] + r)) nonfin = true;
   }
+  // (fmin and fmax drop NaN: a non-finite entry is recorded on its own)
+  const bool wbad = __ballot(nonfin) != 0;
   for (int off = 32; off > 0; off >>= 1) {
     lo = fmin(lo, __shfl_down(lo, off, 64));
     hi = fmax(hi, __shfl_down(hi, off, 64));
@@ -766,8 +774,10 @@ __global__ __launch_bounds__(256) void k_bisect(int32_t m, const double* __restr
     rlo[t >> 6] = lo;
     rhi[t >> 6] = hi;
     remax[t >> 6] = emax;
+    rbad[t >> 6] = wbad ? 1 : 0;
   }
   __syncthreads();
+  const bool bad = (rbad[0] | rbad[1] | rbad[2] | rbad[3]) != 0;
   lo = fmin(fmin(rlo[0], rlo[1]), fmin(rlo[2], rlo[3]));
   hi = fmax(fmax(rhi[0], rhi[1]), fmax(rhi[2], rhi[3]));
   emax = fmax(fmax(remax[0], remax[1]), fmax(remax[2], remax[3]));
@@ -802,7 +812,9 @@ __global__ __launch_bounds__(256) void k_bisect(int32_t m, const double* __restr
     lo = nlo;
     hi = nhi;
   }
-  if (t == 0) w[j] = 0.5 * (lo + hi);
+  // a non-finite tridiagonal matrix gives NaN eigenvalues, which the rank
+  // selection reports
+  if (t == 0) w[j] = bad ? __builtin_nan("") : 0.5 * (lo + hi);
   if (sel.cnt == nullptr) return;
   __shared__ int last;
   if (t == 0) {

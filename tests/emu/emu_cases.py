@@ -303,6 +303,13 @@ def case_eigensolver():
         Pref = Q[:, :4] @ Q[:, :4].T
         assert np.abs(P - Pref).max() <= 1e-9, m
         assert np.abs(X.T @ X - np.eye(4)).max() <= 1e-12
+    # a non-finite matrix gives NaN eigenvalues (which the rank selection
+    # reports as a device error), never a finite spectrum
+    for m in (12, 96, 140):
+        G = np.eye(m)
+        G[3, 5] = G[5, 3] = np.nan
+        w, _ = run(G, 0)
+        assert np.isnan(w).all(), (m, w[:4])
     # rank deficient
     B = rng.standard_normal((30, 2))
     w, X = run(B @ B.T, 2)

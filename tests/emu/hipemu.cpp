@@ -6,6 +6,10 @@
 
 #include <ucontext.h>
 
+#include <cstring>
+#include <mutex>
+#include <unordered_map>
+
 #if defined(__SANITIZE_ADDRESS__)
 #include <sanitizer/common_interface_defs.h>
 #define EMU_ASAN 1
@@ -233,7 +237,21 @@ d4 mfma_f64_16x16x4(double a, double b, d4 c) {
 
 void* dyn_lds() { return dyn.data(); }
 
+// blocks launched so far, and the block in which each static LDS variable
+// was last filled
+unsigned long long g_block_seq = 0;
+std::unordered_map<void*, unsigned long long> g_lds_block;
+
+void lds_fresh(void* p, size_t n) {
+  unsigned long long& b = g_lds_block[p];
+  if (b == g_block_seq) return;
+  b = g_block_seq;
+  memset(p, 0xff, n);
+}
+
 void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body) {
+  static std::mutex mu;  // one launch at a time (the fibers and LDS are shared)
+  std::lock_guard<std::mutex> hold(mu);
   g_gridDim = grid;
   g_blockDim = block;
   const unsigned nt = block.x * block.y * block.z;
@@ -248,6 +266,7 @@ void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& bo
       for (unsigned bx = 0; bx < grid.x; ++bx) {
         tl_blockIdx = dim3(bx, by, bz);
         dyn.assign(shmem ? shmem : 8, 0xff);  // LDS is not zeroed on the device
+        ++g_block_seq;
         for (unsigned t = 0; t < nt; ++t) {
           getcontext(&fibers[t].ctx);
           fibers[t].ctx.uc_stack.ss_sp = fibers[t].stack;

@@ -26,6 +26,11 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+// Static LDS variables: build_emu.py adds HIPEMU_LDS(name) after each
+// declaration; the first thread of a block to pass it fills the variable
+// with 0xff bytes (NaN as doubles), since on the device LDS holds whatever
+// an earlier kernel left there.
+#define HIPEMU_LDS(x) hipemu::lds_fresh((void*)&(x), sizeof(x))
 #define __align__(n) alignas(n)
 #define HIP_SYMBOL(x) ((const void*)&(x))
 #define HIP_DYNAMIC_SHARED(type, name) type* name = (type*)hipemu::dyn_lds()
@@ -62,6 +67,7 @@ double wave_reduce_add(double v);
 typedef double d4 __attribute__((vector_size(4 * sizeof(double))));
 d4 mfma_f64_16x16x4(double a, double b, d4 c);
 void* dyn_lds();
+void lds_fresh(void* p, size_t n);
 void launch(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body);
 extern long long g_fail_alloc_after;  // failure injection: fail the k-th allocation (-1: never)
 }  // namespace hipemu
