@@ -93,8 +93,8 @@ enum ttice_option {
                               counters); 0 = off                               */
   TTICE_OPT_SVD = 7        /* int32_t, solver of the residual's truncated SVD
                               (eq:svdfirst): 1 (default) = residuals whose
-                              Gram matrix is wider than 256 and than twice
-                              the Krylov basis (4 blocks of 64 to 128
+                              Gram matrix is wider than 256 and at least
+                              twice the Krylov basis (4 blocks of 32 to 128
                               vectors, sized from the core's last r_R) first
                               try block Lanczos for the leading singular
                               pairs (the truncation rank needs only those:

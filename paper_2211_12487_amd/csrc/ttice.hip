@@ -344,14 +344,16 @@ int32_t gram_kchunk(int32_t m, int64_t K) {
 // last_ld); last_out == nullptr means "into the last core after n_total".
 namespace {
 // Block-Lanczos truncated SVD: kLzSteps blocks of b vectors, a Krylov basis
-// of kLzSteps b vectors; used for Gram matrices wider than kLzMinM and than
-// twice the basis.  The block is wider than the core's last r_R + 1 by half
-// (a multiple of 32 in [64, 128], doubled once when the first result is not
+// of kLzSteps b vectors; used for Gram matrices wider than kLzMinM and at
+// least twice the basis.  The block is wider than the core's last r_R + 1 by
+// half (a multiple of 32 in [32, 128], doubled while the result is not
 // certified): block Krylov methods converge on the leading eigenpairs at a
 // rate set by the ratio of the wanted eigenvalues to the (b+1)-st, so a
 // block that holds every wanted pair with room to spare converges in a few
-// steps even where the spectrum decays slowly.
-constexpr int32_t kLzBlockMin = 64, kLzBlockMax = 128;
+// steps even where the spectrum decays slowly.  A basis of at most 128
+// vectors keeps the Rayleigh-Ritz eigenproblem on the single-launch
+// register tridiagonalisation.
+constexpr int32_t kLzBlockMin = 32, kLzBlockMax = 128;
 constexpr int32_t kLzBlockForced = 32;  // smallest block when the solver is forced (small test matrices)
 constexpr int32_t kLzSteps = 4;
 constexpr int32_t kLzBasisMax = kLzBlockMax * kLzSteps;
@@ -586,6 +588,7 @@ int ttice_state::lanczos_svd(int level, int32_t b, int64_t rows, int64_t Ncol, c
   const int64_t rR = (int64_t)hs[0];
   double tail2 = hs[1], margin = hs[2];
   if (rR >= sb) LZ_REJECT;  // the basis does not hold enough energy
+  if (rR > lz_max_block()) LZ_REJECT;  // more kept pairs than the polishing step's factorisation takes
   if (rR > 0) {
     // Ritz vectors X = Q S of the kept pairs and of the first discarded
     // one.  The kept ones carry the rounding of the Krylov blocks (those of
@@ -885,12 +888,12 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         // workspace for it is allocated
         if (m > sym_eig_max()) return TTICE_EINVAL;
         bool have_svd = false;
-        // the block from the core's last r_R, and once more with twice the
-        // block when that result is not certified
+        // the block from the core's last r_R, doubled while the result is
+        // not certified
         const int32_t bmin = lz_mode == 2 ? kLzBlockForced : kLzBlockMin;
         for (int32_t b = lz_block(last_rR[i], bmin); lz_mode != 0 && !have_svd && b <= kLzBlockMax; b *= 2) {
           const int64_t basis = (int64_t)kLzSteps * b;
-          if (!(m > (lz_mode == 2 ? basis : std::max<int64_t>(kLzMinM, 2 * basis)) && last_rR[i] < basis / 2)) break;
+          if (!(m >= (lz_mode == 2 ? basis : std::max<int64_t>(kLzMinM, 2 * basis)) && last_rR[i] < basis / 2)) break;
           CKS(lanczos_svd(i, b, rows, Ncol, vr, left, tol2, rows - r, &rR, &tail2, &margin, &have_svd));
         }
         if (!have_svd) CKS(dense_svd(rows, Ncol, vr, left, tol2, rows - r, &rR, &tail2, &margin));
