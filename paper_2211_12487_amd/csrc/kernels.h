@@ -199,6 +199,16 @@ hipError_t frame_sums(hipStream_t st, const double* part, int32_t MB, int64_t ld
                       int32_t F, double* out, double* scratch);
 // out[0] = sum_{i<n} x[i] (deterministic order); out[1] = 1 if any x is not finite.
 hipError_t total_sum(hipStream_t st, const double* x, int64_t n, double* out);
+// out[j] = sum_k X[j ld + k]^2 over the ncol entries of each of the n rows
+// (fixed order).
+hipError_t row_sumsq(hipStream_t st, int32_t n, int32_t ncol, int64_t ld, const double* X, double* out);
+// The rank (at least 1, at most n) from the tails t(r) = perp[0] +
+// sum_{j>=r} e[j] of n directions: res[0] = the smallest r with t(r) <=
+// tol2 (n when none), res[1] = t(res[0]), res[2] = the decision's margin
+// (relative distance of t(r) and t(r-1) from tol2), res[3] = 1 when a value
+// is not finite (perp[1], total_sum's flag, counts too).  res may be a pinned
+// host buffer.
+hipError_t tail_rank(hipStream_t st, int32_t n, const double* e, const double* perp, double tol2, double* res);
 // err2[b] = max(0, y2[b] - ||c(b, 0:r)||^2) for N frames (c row b at ld):
 // the chain's residual energy by the telescoping identity (FP64 path)
 hipError_t telescope(hipStream_t st, int32_t N, int32_t r, const double* c, int64_t ld, const double* y2,

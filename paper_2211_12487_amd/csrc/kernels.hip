@@ -506,6 +506,44 @@ __global__ __launch_bounds__(256) void k_total_sum(const double* __restrict__ x,
   }
 }
 
+// out[j] = sum_k X[j ld + k]^2 over the ncol entries of row j, one block per
+// row, fixed-order sums
+__global__ __launch_bounds__(256) void k_row_sumsq(int32_t ncol, int64_t ld, const double* __restrict__ X,
+                                                   double* __restrict__ out) {
+  __shared__ double red[256];
+  const double* x = X + (int64_t)blockIdx.x * ld;
+  double s = 0.0;
+  for (int32_t k = threadIdx.x; k < ncol; k += 256) s = fma(x[k], x[k], s);
+  s = block_sum_256(s, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// The rank from tails t(r) = perp + sum_{j >= r} e[j] (non-increasing in r):
+// res[0] = the smallest r in [1, n] with t(r) <= tol2 (n when t(n) is
+// above it), res[1] = t(res[0]), res[2] = min(|t(r) - tol2|, |t(r-1) -
+// tol2|) / tol2, res[3] = 1 when a value is not finite.  One thread.
+__global__ void k_tail_rank(int32_t n, const double* __restrict__ e, const double* __restrict__ perp, double tol2,
+                            double* __restrict__ res) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double t = perp[0];  // t(n)
+  bool bad = !isfinite(t) || perp[1] != 0.0;
+  int32_t best = n;
+  double tb = t;
+  for (int32_t q = n; q >= 1; --q) {
+    if (!(t <= tol2)) break;
+    best = q;
+    tb = t;
+    t += e[q - 1];  // t(q - 1)
+  }
+  for (int32_t j = 0; j < n; ++j) bad = bad || !isfinite(e[j]);
+  const double tp = tb + e[best - 1];  // t(best - 1)
+  const double t2 = tol2 > 0.0 ? tol2 : 1e-300;
+  res[0] = (double)best;
+  res[1] = tb;
+  res[2] = fmin(fabs(tb - tol2), fabs(tp - tol2)) / t2;
+  res[3] = bad ? 1.0 : 0.0;
+}
+
 // err2[b] = max(0, y2[b] - sum_j c[b ld + j]^2), one wave per frame
 __global__ __launch_bounds__(256) void k_telescope(int32_t N, int32_t r, const double* __restrict__ c, int64_t ld,
                                                    const double* __restrict__ y2, double* __restrict__ err2) {
@@ -784,6 +822,18 @@ hipError_t frame_sums(hipStream_t st, const double* part, int32_t MB, int64_t ld
 
 hipError_t total_sum(hipStream_t st, const double* x, int64_t n, double* out) {
   hipLaunchKernelGGL(k_total_sum, dim3(1), dim3(256), 0, st, x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t row_sumsq(hipStream_t st, int32_t n, int32_t ncol, int64_t ld, const double* X, double* out) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_sumsq, dim3((unsigned)n), dim3(256), 0, st, ncol, ld, X, out);
+  return hipGetLastError();
+}
+
+hipError_t tail_rank(hipStream_t st, int32_t n, const double* e, const double* perp, double tol2, double* res) {
+  if (n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tail_rank, dim3(1), dim3(64), 0, st, n, e, perp, tol2, res);
   return hipGetLastError();
 }
 

@@ -358,6 +358,9 @@ constexpr int32_t kLzBlockForced = 32;  // smallest block when the solver is for
 constexpr int32_t kLzSteps = 4;
 constexpr int32_t kLzBasisMax = kLzBlockMax * kLzSteps;
 constexpr int64_t kLzMinM = 256;
+// The explicit-residual rank check runs when tol2 < kResolveSafety m^2 u ||R||^2.
+constexpr double kResolveSafety = 4.0;
+constexpr int kResolveRounds = 8;  // passes of one level at most
 int32_t lz_block(int64_t last_rR, int32_t bmin) {
   const int64_t want = (3 * (last_rR + 1) / 2 + 31) / 32 * 32;
   return (int32_t)std::min<int64_t>(kLzBlockMax, std::max<int64_t>(bmin, want));
@@ -698,6 +701,8 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
   double tol2 = tol_in >= 0 ? tol_in * tol_in : -1.0;
   const void* zin = zin0;
   bool zin_is_input = true;
+  int64_t r_new_acc = 0;  // directions appended at the current level over its passes
+  int rounds = 0;
   for (int i = 0; i < d; ++i) {
     const int64_t rows = rk_pend[i] * dims[i];
     const int64_t cols = this->cols(i);
@@ -732,6 +737,7 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
     const bool no_resid = occ_skip || full;
     int64_t rR = 0;
     int32_t solver = 0;
+    bool again = false;  // the explicit rank check asks for another pass
     double rho2 = std::numeric_limits<double>::quiet_NaN(), tail2 = 0.0;
     double margin = std::numeric_limits<double>::infinity();
 
@@ -888,15 +894,27 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         // workspace for it is allocated
         if (m > sym_eig_max()) return TTICE_EINVAL;
         bool have_svd = false;
+        // The Gram matrix's eigenvalues carry absolute errors of about
+        // m u ||R||^2 each, so its tails (sums of up to m of them) cannot
+        // place a cut whose tolerance is below that floor, and the
+        // directions of eigenvalues at the floor are not resolved: there
+        // the candidates are the directions the Gram matrix resolves (its
+        // rank at the floor), the rank among them comes from the explicit
+        // residual energies below, and when those candidates leave more
+        // than tol2 the level runs again on the remaining residual (whose
+        // Gram matrix resolves it on its own, smaller scale).
+        const double floor2 = kResolveSafety * (double)m * (double)m * DBL_EPSILON * rho2;
+        const bool resolve = tol2 < floor2;
+        const double tol2_sel = resolve ? floor2 : tol2;
         // the block from the core's last r_R, doubled while the result is
         // not certified
         const int32_t bmin = lz_mode == 2 ? kLzBlockForced : kLzBlockMin;
         for (int32_t b = lz_block(last_rR[i], bmin); lz_mode != 0 && !have_svd && b <= kLzBlockMax; b *= 2) {
           const int64_t basis = (int64_t)kLzSteps * b;
           if (!(m >= (lz_mode == 2 ? basis : std::max<int64_t>(kLzMinM, 2 * basis)) && last_rR[i] < basis / 2)) break;
-          CKS(lanczos_svd(i, b, rows, Ncol, vr, left, tol2, rows - r, &rR, &tail2, &margin, &have_svd));
+          CKS(lanczos_svd(i, b, rows, Ncol, vr, left, tol2_sel, rows - r, &rR, &tail2, &margin, &have_svd));
         }
-        if (!have_svd) CKS(dense_svd(rows, Ncol, vr, left, tol2, rows - r, &rR, &tail2, &margin));
+        if (!have_svd) CKS(dense_svd(rows, Ncol, vr, left, tol2_sel, rows - r, &rR, &tail2, &margin));
         last_rR[i] = rR;
         solver = have_svd ? 2 : 1;
         if (rR > 0) {
@@ -926,6 +944,43 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
                                              vW, as<double>(S), vW, 1.5, Wp, vW, W2p, vW, 0, nullptr,
                                              nullptr, gws())));
             std::swap(Wp, W2p);
+          }
+          if (resolve) {
+            // With U_R orthonormal, C = U_R^T R and the residual R - U_R C,
+            // the discarded energy of keeping U_R's first r columns is
+            // ||R - U_R C||^2 + sum_{j>=r} ||C_j||^2 (C_j: row j), a sum of
+            // non-negative FP64 terms (eq:deltasvd without the Gram
+            // matrix's cancellation); the rank is the smallest r whose
+            // tail is within tol2.
+            const View vC = row_major(Ncol);
+            const int32_t MBr = gemm_row_blocks((int32_t)rows);
+            CKS(ensure(T, (size_t)Ncol * rR * sizeof(double)));
+            CKS(ensure(colpart, (size_t)MBr * Ncol * sizeof(double)));
+            CKS(ensure(lam, (size_t)rR * sizeof(double)));
+            CKS(ensure(tail, 2 * sizeof(double)));
+            CK((gemm<double, double, double>(st, (int32_t)rR, (int32_t)Ncol, (int32_t)rows, (int32_t)rows, 1.0, Wp,
+                                             transposed(vW), as<double>(rbuf), vr, 0.0, (const double*)nullptr,
+                                             View(), as<double>(T), vC, 0, nullptr, nullptr, gws())));
+            CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)Ncol, (int32_t)rR, (int32_t)rR, -1.0, Wp,
+                                             vW, as<double>(T), vC, 1.0, as<double>(rbuf), vr, (double*)nullptr,
+                                             View(), 0, as<double>(colpart), nullptr, gws())));
+            CK(frame_sums(st, as<double>(colpart), MBr, Ncol, (int32_t)cols, (int32_t)N, as<double>(fres),
+                          fscratch(N)));
+            CK(total_sum(st, as<double>(fres), N, as<double>(tail)));
+            CK(row_sumsq(st, (int32_t)rR, (int32_t)Ncol, Ncol, as<double>(T), as<double>(lam)));
+            CK(tail_rank(st, (int32_t)rR, as<double>(lam), as<double>(tail), tol2, hs));
+            CKS(sync_scalars(4));
+            if (hs[3] != 0.0) return TTICE_EDEVICE;
+            const int64_t rx = (int64_t)hs[0];
+            tail2 = hs[1];
+            margin = hs[2];
+            again = rx == rR && tail2 > tol2 && !served && rounds + 1 < kResolveRounds;
+            if (rx < rR) {
+              // U_R's first rx columns, ld rx
+              CK(gather_columns(st, (int32_t)rows, (int32_t)rx, Wp, (int32_t)rR, nullptr, nullptr, false, W2p));
+              std::swap(Wp, W2p);
+              rR = rx;
+            }
           }
           // eq:coreexpansion: U_i <- [U_i^pad, U_R] (U_R's columns sign-fixed on
           // the way), and in the same launch the zero padding below
@@ -976,13 +1031,23 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
         }
       }
     }
+    r_new_acc += rR;
     if (info) {
-      info->r_new[i] = rR;
+      info->r_new[i] = r_new_acc;
       info->rho2[i] = rho2;
       info->tail2[i] = occ_skip ? 0.0 : tail2;
       info->margin[i] = margin;
       info->solver[i] = solver;
     }
+    if (again) {
+      // the same level again with the grown core: its residual is the part
+      // the appended directions left
+      ++rounds;
+      --i;
+      continue;
+    }
+    r_new_acc = 0;
+    rounds = 0;
     zin = out;
     zin_is_input = false;
   }

@@ -22,6 +22,9 @@ Streams
 ``tt_lowrank``        an exactly low-rank stream: random TT-cores with given
                       TT-ranks, the last core supplying one column per tensor
                       (the synthetic stream of the TT-FOA comparison, App. B).
+``graded``            sums of rank-1 terms whose weights fall geometrically
+                      (a spectrum spanning many decades, for tolerances far
+                      below the square root of the unit roundoff).
 """
 from __future__ import annotations
 
@@ -37,6 +40,7 @@ __all__ = [
     "fourier_field_stream",
     "device_separable",
     "tt_lowrank_stream",
+    "graded_stream",
     "serving_trace",
     "CONFIGS",
 ]
@@ -273,6 +277,33 @@ def tt_lowrank_stream(
         out = np.moveaxis(np.tensordot(basis, cols, axes=([d], [0])), -1, 0)
         done += nb
         yield np.ascontiguousarray(out).astype(dtype, copy=False)
+
+
+def graded_stream(
+    dims: Sequence[int],
+    n_terms: int = 12,
+    ratio: float = 1.0 / 30.0,
+    n_batches: int = 3,
+    batch: int = 2,
+    seed: int = 0,
+) -> Iterator[np.ndarray]:
+    """Sum of n_terms rank-1 terms f_j1 x ... x f_jd (Gaussian factors drawn
+    once) with weights ratio**j, each tensor of an increment taking its own
+    N(0,1) coefficient per term: every unfolding has a geometrically graded
+    spectrum.  FP64."""
+    rng = np.random.default_rng(seed)
+    terms = []
+    for _ in range(n_terms):
+        t = rng.standard_normal(dims[0])
+        for n in dims[1:]:
+            t = np.multiply.outer(t, rng.standard_normal(n))
+        terms.append(t)
+    for _ in range(n_batches):
+        Y = np.zeros((batch,) + tuple(dims))
+        for j, t in enumerate(terms):
+            a = rng.standard_normal(batch).reshape((batch,) + (1,) * len(dims))
+            Y += (ratio ** j) * a * t[None]
+        yield Y
 
 
 def serving_trace(

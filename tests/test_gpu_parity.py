@@ -112,13 +112,47 @@ def test_video_prefix_fp32_input():
 
 
 def test_lowrank_stream_discovers_tt_ranks():
-    """Exactly low-rank stream (App. B shapes, TT-ranks [1,2,3,5,1]); eps is
-    1e-6 because the GPU path takes singular values from a Gram matrix."""
+    """Exactly low-rank stream at the paper's eps = 1e-8 (App. B shapes,
+    TT-ranks [1,2,3,5,1]): below the Gram matrix's resolution the rank
+    comes from the explicit residual energies; ranks as the stream's and
+    the oracle's, reconstructions within 1e-10 of the oracle's."""
+    log("case low-rank stream, eps 1e-8")
     dims = (10, 15, 20)
-    g = make(dims, 1e-6)
+    g, o = make(dims, 1e-8), Oracle(dims, 1e-8)
     for k, Y in enumerate(synth.tt_lowrank_stream(dims, (2, 3, 5), 12, 1, seed=7), start=1):
         g.update(to_dev(Y))
-        assert g.ranks()[1:-1] == [2, 3, min(k, 5)], (k, g.ranks())
+        oi = o.update(Y)
+        assert g.ranks()[1:-1] == [2, 3, min(k, 5)] == oi["ranks"][1:-1], (k, g.ranks(), oi["ranks"])
+    rg, ro = g.reconstruct().cpu().numpy(), o.reconstruct()
+    assert np.abs(rg - ro).max() <= 1e-10 * np.abs(ro).max()
+
+
+@pytest.mark.parametrize("dims,terms,ratio,nb,batch,seed", [((12, 10, 8), 12, 1.0 / 30.0, 3, 2, 41),
+                                                              ((16, 14, 12), 14, 1.0 / 20.0, 4, 3, 5)])
+def test_graded_spectrum_below_gram_resolution(dims, terms, ratio, nb, batch, seed):
+    """Spectra falling geometrically through many decades at eps = 1e-9:
+    the kept directions reach below what the first Gram matrix resolves,
+    so the level runs again on the deflated residual.  Ranks as the
+    oracle's; every increment within eps (eq:ttsvd_error) and within 2x
+    the oracle's error; reconstructions within eps/2 of the oracle's."""
+    log(f"case graded spectrum {dims}, eps 1e-9")
+    eps = 1e-9
+    batches = list(synth.graded_stream(dims, terms, ratio, nb, batch, seed=seed))
+    g, o = make(dims, eps), Oracle(dims, eps)
+    for k, Y in enumerate(batches):
+        gi = g.update(to_dev(Y))
+        oi = o.update(Y)
+        assert gi["ranks"] == oi["ranks"], (k, gi["ranks"], oi["ranks"], oi["margin"])
+    assert max(g.ranks()[1:-1]) >= 7, g.ranks()
+    rg, ro = g.reconstruct().cpu().numpy(), o.reconstruct()
+    Yall = np.concatenate(batches)
+    for k in range(nb):
+        s = slice(batch * k, batch * (k + 1))
+        eg = np.linalg.norm(rg[s] - Yall[s]) / np.linalg.norm(Yall[s])
+        eo = np.linalg.norm(ro[s] - Yall[s]) / np.linalg.norm(Yall[s])
+        assert eg <= eps and eg <= 2.0 * eo + 1e-15, (k, eg, eo)
+    for b in range(ro.shape[0]):
+        assert np.linalg.norm(rg[b] - ro[b]) <= 0.5 * eps * np.linalg.norm(ro[b]), b
 
 
 @pytest.mark.parametrize("batch", [4, 9])

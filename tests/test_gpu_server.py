@@ -111,7 +111,11 @@ def test_config4_mix_is_bit_identical_to_alone():
         mixed, single = srv.stream(sid), alone.stream(aid)
         assert mixed.ranks() == single.ranks(), s
         for i, (a, b) in enumerate(zip(cores_of(mixed, len(x["dims"])), cores_of(single, len(x["dims"])))):
-            assert torch.equal(a, b), (s, x["prec"], i)
+            if not torch.equal(a, b):
+                dd = (a - b).abs()
+                raise AssertionError(f"stream {s} {x['dims']} {x['prec']} core {i}: {int((dd > 0).sum())} entries "
+                                     f"differ, max |diff| {float(dd.max()):.3e} of max |entry| "
+                                     f"{float(a.abs().max()):.3e}")
         alone.remove_stream(aid)
     alone.close()
     srv.close()
