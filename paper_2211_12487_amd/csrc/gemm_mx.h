@@ -12,9 +12,11 @@
 //    hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32
 //    accumulation (the lo*lo term is below that sum's rounding).
 // Block tile 128 x 64 (four waves of 32 rows x 64 columns, 2 x 4 MFMA tiles
-// of 16 x 16 each), K in tiles of 32 staged through two LDS buffers (one
-// barrier per K tile, the next tile's global loads in flight during the
-// current tile's products).  Operands are rounded to the arithmetic when
+// of 16 x 16 each), K in tiles staged through two LDS buffers (one barrier
+// per K tile, the next tile's global loads in flight during the current
+// tile's products): 32 deep for the reduced arithmetics, 16 for FP64, whose
+// 52 KB of buffers let two blocks share a CU, so one block's barrier and
+// loads overlap the other's products.  Operands are rounded to the arithmetic when
 // they are written to LDS.  Views: A unframed (row or column stride 1 picks
 // the coalesced load order), B, E and D with unframed rows (columns may be
 // framed and renumbered).  The optional column energies colpart[mb N + n] =
@@ -29,6 +31,9 @@ namespace mx {
 
 constexpr int kMxF64 = kProjFP64, kMxBF3 = kProjBF16x3;
 constexpr int BM = 128, BN = 64, BK = 32;
+// K tile depth per arithmetic
+template <int P>
+constexpr int kb() { return P == kProjFP64 ? 16 : BK; }
 constexpr int kThreads = 256;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -40,39 +45,40 @@ template <int P>
 struct Tile;
 template <>
 struct Tile<kMxF64> {
-  static constexpr int PA = BK + 1;  // doubles per A row (m-major, k contiguous)
-  static constexpr int PB = BK + 1;
+  static constexpr int PA = kb<kProjFP64>() + 1;  // doubles per A row (m-major, k contiguous)
+  static constexpr int PB = kb<kProjFP64>() + 1;
   static constexpr size_t bytes = (size_t)(BM * PA + BN * PB) * sizeof(double);
 };
 
 template <int P>
 constexpr size_t lds_bytes() { return 2 * Tile<P>::bytes; }
 
-// Global loads of the K tile at k0 (clamped in-bounds positions, masked
-// when written to LDS)
-template <typename TB>
+// Global loads of the K tile at k0, KB deep (clamped in-bounds positions,
+// masked when written to LDS): KB / 2 values of A and KB / 4 of B per thread
+template <int KB, typename TB>
 __device__ __forceinline__ void load_tile(const double* __restrict__ A, const View& va, bool a_kfast, int32_t M,
                                           int32_t m0, const TB* __restrict__ B, const View& vb, int64_t bco,
-                                          int32_t k0, int32_t K, int t, double (&a)[16], double (&b)[8]) {
+                                          int32_t k0, int32_t K, int t, double (&a)[KB / 2], double (&b)[KB / 4]) {
+  static_assert(KB == 16 || KB == 32, "K tile of 16 or 32");
   if (a_kfast) {
-    const int kk = t & 31;
+    const int kk = t & (KB - 1);
     const int32_t kc = min(k0 + kk, K - 1);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int32_t m = min(m0 + (t >> 5) + 8 * u, M - 1);
+    for (int u = 0; u < KB / 2; ++u) {
+      const int32_t m = min(m0 + t / KB + (kThreads / KB) * u, M - 1);
       a[u] = A[(int64_t)m * va.rs + (int64_t)kc * va.cs];
     }
   } else {
     const int mm = t & 127;
     const int32_t m = min(m0 + mm, M - 1);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < KB / 2; ++u) {
       const int32_t kc = min(k0 + (t >> 7) + 2 * u, K - 1);
       a[u] = A[(int64_t)m * va.rs + (int64_t)kc * va.cs];
     }
   }
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
+  for (int u = 0; u < KB / 4; ++u) {
     const int32_t kc = min(k0 + (t >> 6) + 4 * u, K - 1);
     b[u] = (double)B[(int64_t)kc * vb.rs + bco];
   }
@@ -91,30 +97,32 @@ struct Ops;
 template <>
 struct Ops<kMxF64> {
   static __device__ __forceinline__ void store_tile(void* buf, bool a_kfast, int32_t M, int32_t m0, int32_t N,
-                                                    int32_t n0, int32_t k0, int32_t K, int t, const double (&a)[16],
-                                                    const double (&b)[8]) {
+                                                    int32_t n0, int32_t k0, int32_t K, int t,
+                                                    const double (&a)[kb<kMxF64>() / 2],
+                                                    const double (&b)[kb<kMxF64>() / 4]) {
     using T = Tile<kMxF64>;
+    constexpr int KB = kb<kMxF64>();
     const int bn = t & 63;
     const bool bvalid = n0 + bn < N;
     double* As = (double*)buf;
     double* Bs = As + BM * T::PA;
     if (a_kfast) {
-      const int kk = t & 31;
+      const int kk = t & (KB - 1);
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int mm = (t >> 5) + 8 * u;
+      for (int u = 0; u < KB / 2; ++u) {
+        const int mm = t / KB + (kThreads / KB) * u;
         As[mm * T::PA + kk] = (m0 + mm < M && k0 + kk < K) ? a[u] : 0.0;
       }
     } else {
       const int mm = t & 127;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < KB / 2; ++u) {
         const int kk = (t >> 7) + 2 * u;
         As[mm * T::PA + kk] = (m0 + mm < M && k0 + kk < K) ? a[u] : 0.0;
       }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < KB / 4; ++u) {
       const int kk = (t >> 6) + 4 * u;
       Bs[bn * T::PB + kk] = (bvalid && k0 + kk < K) ? b[u] : 0.0;
     }
@@ -127,7 +135,7 @@ struct Ops<kMxF64> {
     const double* As = (const double*)buf;
     const double* Bs = As + BM * T::PA;
 #pragma unroll
-    for (int s = 0; s < BK / 4; ++s) {
+    for (int s = 0; s < kb<kMxF64>() / 4; ++s) {
       const int k = 4 * s + kq;
       double av[2], bv[4];
 #pragma unroll
@@ -151,11 +159,10 @@ __device__ __forceinline__ int tile_row(int kq, int i) {
 }
 
 template <int P, typename TB, typename TE, typename TD>
-__global__ __launch_bounds__(kThreads) void k_gemm_mx(int32_t M, int32_t N, int32_t K, double alpha,
-                                                      const double* __restrict__ A, View va,
-                                                      const TB* __restrict__ B, View vb, double beta,
-                                                      const TE* __restrict__ E, View ve, TD* __restrict__ D,
-                                                      View vd, double* __restrict__ colpart) {
+__device__ __forceinline__ void gemm_mx_body(int32_t M, int32_t N, int32_t K, double alpha,
+                                             const double* __restrict__ A, View va, const TB* __restrict__ B,
+                                             View vb, double beta, const TE* __restrict__ E, View ve,
+                                             TD* __restrict__ D, View vd, double* __restrict__ colpart) {
   HIP_DYNAMIC_SHARED(unsigned char, lds);
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -170,14 +177,15 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mx(int32_t M, int32_t N, int3
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc.v[ti][tj][i] = 0;
 
-  double a[16], b[8];
-  if (K > 0) load_tile<TB>(A, va, a_kfast, M, m0, B, vb, bco, 0, K, t, a, b);
+  constexpr int KB = kb<P>();
+  double a[KB / 2], b[KB / 4];
+  if (K > 0) load_tile<KB, TB>(A, va, a_kfast, M, m0, B, vb, bco, 0, K, t, a, b);
   int buf = 0;
-  for (int32_t k0 = 0; k0 < K; k0 += BK) {
+  for (int32_t k0 = 0; k0 < K; k0 += KB) {
     void* cur = lds + buf * Tile<P>::bytes;
     Ops<P>::store_tile(cur, a_kfast, M, m0, N, n0, k0, K, t, a, b);
     __syncthreads();
-    if (k0 + BK < K) load_tile<TB>(A, va, a_kfast, M, m0, B, vb, bco, k0 + BK, K, t, a, b);
+    if (k0 + KB < K) load_tile<KB, TB>(A, va, a_kfast, M, m0, B, vb, bco, k0 + KB, K, t, a, b);
     Ops<P>::mma_tile(cur, w, lane, acc);
     buf ^= 1;
   }
@@ -228,6 +236,26 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mx(int32_t M, int32_t N, int3
     const int32_t n = n0 + c, mb = m0 / 64 + h;
     if (n < N && mb * 64 < M) colpart[(int64_t)mb * N + n] = red[(2 * h) * 64 + c] + red[(2 * h + 1) * 64 + c];
   }
+}
+
+// the reduced arithmetics (gemm_mx_lp.hip)
+template <int P, typename TB, typename TE, typename TD>
+__global__ __launch_bounds__(kThreads) void k_gemm_mx(int32_t M, int32_t N, int32_t K, double alpha,
+                                                      const double* __restrict__ A, View va,
+                                                      const TB* __restrict__ B, View vb, double beta,
+                                                      const TE* __restrict__ E, View ve, TD* __restrict__ D,
+                                                      View vd, double* __restrict__ colpart) {
+  gemm_mx_body<P, TB, TE, TD>(M, N, K, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart);
+}
+
+// FP64: registers held to three waves per SIMD, so three blocks (3 x 52 KB
+// of LDS) share a CU
+template <typename TB, typename TE, typename TD>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_mx64(
+    int32_t M, int32_t N, int32_t K, double alpha, const double* __restrict__ A, View va, const TB* __restrict__ B,
+    View vb, double beta, const TE* __restrict__ E, View ve, TD* __restrict__ D, View vd,
+    double* __restrict__ colpart) {
+  gemm_mx_body<kMxF64, TB, TE, TD>(M, N, K, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart);
 }
 
 }  // namespace mx

@@ -8,12 +8,13 @@ template <int P, typename TB, typename TE, typename TD>
 hipError_t launch_gemm_mx(hipStream_t st, int32_t M, int32_t N, int32_t K, double alpha, const double* A, View va,
                           const TB* B, View vb, double beta, const TE* E, View ve, TD* D, View vd,
                           double* colpart) {
+  static_assert(P == mx::kMxF64, "the FP64 launcher");
   constexpr size_t lds = mx::lds_bytes<P>();
-  static const hipError_t attr = hipFuncSetAttribute((const void*)mx::k_gemm_mx<P, TB, TE, TD>,
+  static const hipError_t attr = hipFuncSetAttribute((const void*)mx::k_gemm_mx64<TB, TE, TD>,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (attr != hipSuccess) return attr;
   const dim3 grid((unsigned)((N + mx::BN - 1) / mx::BN), (unsigned)((M + mx::BM - 1) / mx::BM));
-  hipLaunchKernelGGL((mx::k_gemm_mx<P, TB, TE, TD>), grid, dim3(mx::kThreads), lds, st, M, N, K, alpha, A, va, B,
+  hipLaunchKernelGGL((mx::k_gemm_mx64<TB, TE, TD>), grid, dim3(mx::kThreads), lds, st, M, N, K, alpha, A, va, B,
                      vb, beta, E, ve, D, vd, colpart);
   return hipGetLastError();
 }
