@@ -199,6 +199,9 @@ hipError_t frame_sums(hipStream_t st, const double* part, int32_t MB, int64_t ld
                       int32_t F, double* out, double* scratch);
 // out[0] = sum_{i<n} x[i] (deterministic order); out[1] = 1 if any x is not finite.
 hipError_t total_sum(hipStream_t st, const double* x, int64_t n, double* out);
+// out[0] = max |S(i, j) - [i == j]| over an n x n matrix (row stride ld),
+// out[1] = 1 when an entry is not finite.  out may be a pinned host buffer.
+hipError_t max_off_identity(hipStream_t st, int32_t n, const double* S, int32_t ld, double* out);
 // out[j] = sum_k X[j ld + k]^2 over the ncol entries of each of the n rows
 // (fixed order).
 hipError_t row_sumsq(hipStream_t st, int32_t n, int32_t ncol, int64_t ld, const double* X, double* out);

@@ -506,6 +506,35 @@ __global__ __launch_bounds__(256) void k_total_sum(const double* __restrict__ x,
   }
 }
 
+// out[0] = max_{i,j} |S(i, j) - [i == j]| over the n x n matrix S (row
+// stride ld), out[1] = 1 when an entry is not finite; one block
+__global__ __launch_bounds__(256) void k_max_off_identity(int32_t n, const double* __restrict__ S, int32_t ld,
+                                                          double* __restrict__ out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  int bad = 0;
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t e = threadIdx.x; e < nn; e += 256) {
+    const int32_t i = (int32_t)(e / n), j = (int32_t)(e - (int64_t)i * n);
+    const double v = S[(int64_t)i * ld + j] - (i == j ? 1.0 : 0.0);
+    if (!isfinite(v)) bad = 1;
+    m = fmax(m, fabs(v));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  const double mx = red[0];
+  __syncthreads();  // every thread has read red[0] before the next sum reuses red
+  const double nb = block_sum_256((double)bad, red);
+  if (threadIdx.x == 0) {
+    out[0] = mx;
+    out[1] = nb > 0 ? 1.0 : 0.0;
+  }
+}
+
 // out[j] = sum_k X[j ld + k]^2 over the ncol entries of row j, one block per
 // row, fixed-order sums
 __global__ __launch_bounds__(256) void k_row_sumsq(int32_t ncol, int64_t ld, const double* __restrict__ X,
@@ -822,6 +851,12 @@ hipError_t frame_sums(hipStream_t st, const double* part, int32_t MB, int64_t ld
 
 hipError_t total_sum(hipStream_t st, const double* x, int64_t n, double* out) {
   hipLaunchKernelGGL(k_total_sum, dim3(1), dim3(256), 0, st, x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t max_off_identity(hipStream_t st, int32_t n, const double* S, int32_t ld, double* out) {
+  if (n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_max_off_identity, dim3(1), dim3(256), 0, st, n, S, ld, out);
   return hipGetLastError();
 }
 

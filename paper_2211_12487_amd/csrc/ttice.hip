@@ -361,6 +361,9 @@ constexpr int64_t kLzMinM = 256;
 // The explicit-residual rank check runs when tol2 < kResolveSafety m^2 u ||R||^2.
 constexpr double kResolveSafety = 4.0;
 constexpr int kResolveRounds = 8;  // passes of one level at most
+// orthonormality reached by the Newton-Schulz steps on appended directions
+constexpr double kOrthTol = 1e-13;
+constexpr int kNsMaxSteps = 8;
 int32_t lz_block(int64_t last_rR, int32_t bmin) {
   const int64_t want = (3 * (last_rR + 1) / 2 + 31) / 32 * 32;
   return (int32_t)std::min<int64_t>(kLzBlockMax, std::max<int64_t>(bmin, want));
@@ -933,13 +936,21 @@ int ttice_state::core_loop(const TIn* zin0, int64_t N, const int32_t* fidx, doub
                                                nullptr, gws())));
             }
           }
-          // ... and among themselves: two Newton-Schulz steps towards the
-          // orthonormal polar factor, W <- W (3I - W^T W) / 2
+          // ... and among themselves: Newton-Schulz steps towards the
+          // orthonormal polar factor, W <- W (3I - W^T W) / 2, two at least
+          // and then until max |W^T W - I| <= kOrthTol (columns built from
+          // small singular values start far from orthonormal)
           CKS(ensure(S, (size_t)rR * rR * sizeof(double)));
-          for (int pass = 0; pass < 2; ++pass) {
+          for (int pass = 0;; ++pass) {
             CK((gemm<double, double, double>(st, (int32_t)rR, (int32_t)rR, (int32_t)rows, (int32_t)rows, 1.0, Wp,
                                              transposed(vW), Wp, vW, 0.0, (const double*)nullptr, View(),
                                              as<double>(S), vW, 0, nullptr, nullptr, gws())));
+            if (pass >= 2) {
+              CK(max_off_identity(st, (int32_t)rR, as<double>(S), (int32_t)rR, hs));
+              CKS(sync_scalars(2));
+              if (hs[1] != 0.0) return TTICE_EDEVICE;
+              if (hs[0] <= kOrthTol || pass >= kNsMaxSteps) break;
+            }
             CK((gemm<double, double, double>(st, (int32_t)rows, (int32_t)rR, (int32_t)rR, (int32_t)rR, -0.5, Wp,
                                              vW, as<double>(S), vW, 1.5, Wp, vW, W2p, vW, 0, nullptr,
                                              nullptr, gws())));

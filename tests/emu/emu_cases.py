@@ -233,6 +233,10 @@ def case_graded_spectrum():
         assert eg <= eps and eg <= 2.0 * eo + 1e-15, (k, eg, eo)
     for b in range(ro.shape[0]):
         assert np.linalg.norm(rg[b] - ro[b]) <= 0.5 * eps * np.linalg.norm(ro[b]), b
+    for i in range(g.d):
+        U = g.core(i)
+        if U.shape[1]:
+            assert np.abs(U.T @ U - np.eye(U.shape[1])).max() <= 1e-12, i
 
 
 def case_checkpoint():

@@ -153,6 +153,10 @@ def test_graded_spectrum_below_gram_resolution(dims, terms, ratio, nb, batch, se
         assert eg <= eps and eg <= 2.0 * eo + 1e-15, (k, eg, eo)
     for b in range(ro.shape[0]):
         assert np.linalg.norm(rg[b] - ro[b]) <= 0.5 * eps * np.linalg.norm(ro[b]), b
+    # directions appended from singular values near the Gram matrix's floor
+    # start far from orthonormal: the Newton-Schulz steps continue until
+    # U^T U = I to working accuracy
+    assert orthogonality(g) <= 1e-12
 
 
 @pytest.mark.parametrize("batch", [4, 9])
