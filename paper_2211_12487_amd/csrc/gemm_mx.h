@@ -14,9 +14,9 @@
 // Block tile 128 x 64 (four waves of 32 rows x 64 columns, 2 x 4 MFMA tiles
 // of 16 x 16 each), K in tiles staged through two LDS buffers (one barrier
 // per K tile, the next tile's global loads in flight during the current
-// tile's products): 32 deep for the reduced arithmetics, 16 for FP64, whose
-// 52 KB of buffers let two blocks share a CU, so one block's barrier and
-// loads overlap the other's products.  Operands are rounded to the arithmetic when
+// tile's products): 32 deep for split BF16, 16 for FP64 and FP32, whose
+// smaller buffers and prefetch registers let three blocks share a CU, so one
+// block's barrier and loads overlap the others' products.  Operands are rounded to the arithmetic when
 // they are written to LDS.  Views: A unframed (row or column stride 1 picks
 // the coalesced load order), B, E and D with unframed rows (columns may be
 // framed and renumbered).  The optional column energies colpart[mb N + n] =
@@ -31,9 +31,10 @@ namespace mx {
 
 constexpr int kMxF64 = kProjFP64, kMxBF3 = kProjBF16x3;
 constexpr int BM = 128, BN = 64, BK = 32;
-// K tile depth per arithmetic
+// K tile depth per arithmetic (split BF16 needs 32: its instruction takes 32
+// values of k)
 template <int P>
-constexpr int kb() { return P == kProjFP64 ? 16 : BK; }
+constexpr int kb() { return P == kProjBF16x3 ? BK : 16; }
 constexpr int kThreads = 256;
 
 typedef double d4 __attribute__((ext_vector_type(4)));

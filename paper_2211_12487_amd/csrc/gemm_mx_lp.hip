@@ -113,8 +113,8 @@ constexpr int kMxF32 = kProjFP32;
 
 template <>
 struct Tile<kMxF32> {
-  static constexpr int PA = BK + 1;  // floats per row (m-major, k contiguous)
-  static constexpr int PB = BK + 1;
+  static constexpr int PA = kb<kMxF32>() + 1;  // floats per row (m-major, k contiguous)
+  static constexpr int PB = kb<kMxF32>() + 1;
   static constexpr size_t bytes = (size_t)(BM * PA + BN * PB) * sizeof(float);
 };
 
@@ -126,30 +126,32 @@ struct Acc<kMxF32> {
 template <>
 struct Ops<kMxF32> {
   static __device__ __forceinline__ void store_tile(void* buf, bool a_kfast, int32_t M, int32_t m0, int32_t N,
-                                                    int32_t n0, int32_t k0, int32_t K, int t, const double (&a)[16],
-                                                    const double (&b)[8]) {
+                                                    int32_t n0, int32_t k0, int32_t K, int t,
+                                                    const double (&a)[kb<kMxF32>() / 2],
+                                                    const double (&b)[kb<kMxF32>() / 4]) {
     using T = Tile<kMxF32>;
+    constexpr int KB = kb<kMxF32>();
     const int bn = t & 63;
     const bool bvalid = n0 + bn < N;
     float* As = (float*)buf;
     float* Bs = As + BM * T::PA;
     if (a_kfast) {
-      const int kk = t & 31;
+      const int kk = t & (KB - 1);
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int mm = (t >> 5) + 8 * u;
+      for (int u = 0; u < KB / 2; ++u) {
+        const int mm = t / KB + (kThreads / KB) * u;
         As[mm * T::PA + kk] = (m0 + mm < M && k0 + kk < K) ? (float)a[u] : 0.f;
       }
     } else {
       const int mm = t & 127;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < KB / 2; ++u) {
         const int kk = (t >> 7) + 2 * u;
         As[mm * T::PA + kk] = (m0 + mm < M && k0 + kk < K) ? (float)a[u] : 0.f;
       }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < KB / 4; ++u) {
       const int kk = (t >> 6) + 4 * u;
       Bs[bn * T::PB + kk] = (bvalid && k0 + kk < K) ? (float)b[u] : 0.f;
     }
@@ -161,7 +163,7 @@ struct Ops<kMxF32> {
     const float* As = (const float*)buf;
     const float* Bs = As + BM * T::PA;
 #pragma unroll
-    for (int s = 0; s < BK / 4; ++s) {
+    for (int s = 0; s < kb<kMxF32>() / 4; ++s) {
       const int k = 4 * s + kq;
       float av[2], bv[4];
 #pragma unroll
