@@ -248,6 +248,9 @@ hipError_t proj_columns(hipStream_t st, int32_t rows, int32_t r, int32_t Ncol, c
     if (rho_explicit) *rho_explicit = true;
     return proj_columns_short<TIn>(st, prec, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
   }
+  // FP64 input: two columns per lane already load 16 bytes, and half the
+  // accumulators of four leave room for three or four waves per SIMD
+  if (sizeof(TIn) == 8 && vec == 4) vec = 2;
   if (prec != kProjFP64)
     return proj_columns_lp<TIn>(st, prec, vec, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
   if (vec == 4) return launch_rt<TIn, 4>(st, rows, r, Ncol, Z, vz, U, ldu, C, vc, znorm2, rho2, ev0, ev1);
