@@ -114,19 +114,22 @@ __device__ __forceinline__ void gemm_tile(const double (*As)[65], const double (
   }
 }
 
-// Fixed-order sum of the S K-split partials of the elements e = t, t + 256,
-// ... (EP of them) of a tile's Mt x Nt block at (m0, n0), PZ partials of
-// each element in flight; the sums go to tile_s[em * 65 + en].
+// Fixed-order sum of the S K-split partials of the elements e = e0 + t,
+// e0 + t + 256, ... (EP of them) of a tile's Mt x Nt block at (m0, n0), PZ
+// partials of each element in flight; the sums go to tile_s[em * 65 + en].
+// Each element's partials are added in the order z = 0, 1, ... whatever EP
+// and PZ.
 template <int EP, int PZ>
 __device__ __forceinline__ void split_reduce(const double* __restrict__ part, int32_t S, int64_t MN, int32_t N,
-                                             int32_t m0, int32_t n0, int32_t Nt, int32_t Et, double* tile_s) {
+                                             int32_t m0, int32_t n0, int32_t Nt, int32_t Et, double* tile_s,
+                                             int32_t e0) {
   const int t = threadIdx.x;
   double acc[EP];
   int64_t off[EP];
   int32_t slot[EP];
 #pragma unroll
   for (int i = 0; i < EP; ++i) {
-    const int32_t e = t + 256 * i;
+    const int32_t e = e0 + t + 256 * i;
     const int32_t ee = e < Et ? e : 0;  // clamped: every load stays in bounds
     const int32_t em = ee / Nt, en = ee - em * Nt;
     off[i] = (int64_t)(m0 + em) * N + (n0 + en);
@@ -191,12 +194,12 @@ __device__ void split_finish(double (&acc)[4][4], int32_t M, int32_t N, int32_t 
     __threadfence();
     const int32_t Mt = min(64, M - m0), Nt = min(64, N - n0);
     const int32_t Et = Mt * Nt;
+    // (16 values in flight per thread: more would set the register count of
+    // the whole kernel, and with it the occupancy of its K loop)
     if (Et <= 256)
-      split_reduce<1, 16>(part, S, MN, N, m0, n0, Nt, Et, tile_s);
-    else if (Et <= 1024)
-      split_reduce<4, 16>(part, S, MN, N, m0, n0, Nt, Et, tile_s);
+      split_reduce<1, 16>(part, S, MN, N, m0, n0, Nt, Et, tile_s, 0);
     else
-      split_reduce<16, 4>(part, S, MN, N, m0, n0, Nt, Et, tile_s);
+      for (int32_t e0 = 0; e0 < Et; e0 += 1024) split_reduce<4, 4>(part, S, MN, N, m0, n0, Nt, Et, tile_s, e0);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i)
