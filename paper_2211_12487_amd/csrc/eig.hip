@@ -1072,9 +1072,9 @@ __device__ void back_transform_group(int32_t m, int32_t r, int32_t klo, int32_t 
 // inverse iteration, back-transformed x = Q y with the reflectors kept in A's
 // rows.  Every vector starts on its own thread (LU + three solves from a
 // fixed start vector); vectors whose eigenvalue lies within 1e-3 ||T|| of the
-// previous one (a cluster) are then recomputed in order with modified
-// Gram-Schmidt against the earlier members of their cluster at every
-// iteration.  The back-transformation applies the reflectors in chunks
+// previous one (a cluster) are then recomputed in order with classical
+// Gram-Schmidt (two passes) against the earlier members of their cluster at
+// every iteration.  The back-transformation applies the reflectors in chunks
 // staged through LDS, one wave per column.  Output X (m x r, row-major).
 // kLdsWork: the per-vector factors and Y live in LDS (else in ws, 7*m*r
 // doubles).  back = 0: stop before the back-transformation (ws holds Y).
@@ -1168,22 +1168,52 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
     }
   }
   __syncthreads();
-  // phase 2: clustered vectors, in order
+  // phase 2: clustered vectors, in order; at every iteration two passes of
+  // classical Gram-Schmidt against the earlier members b0 .. c-1 of the
+  // cluster: all their dot products at once (one wave per member, into
+  // dots, which uses the reflector staging area: free until the
+  // back-transformation), then one update of y
+  // Without LDS work space the member's LU factors and vector sit in
+  // global memory; when they fit, they are staged in LDS (after dots) for
+  // the single-thread solves, whose every step would otherwise wait on a
+  // global load.
+  double* dots = refl;
+  const int wv = t >> 6, ln = t & 63;
+  const bool stage = !kLdsWork && 7 * (int64_t)m <= refl_cap;
   for (int32_t c = 1; c < r; ++c) {
     if (!(fabs(lam[c - 1] - lam[c]) <= ortol)) continue;
+    int32_t b0 = c - 1;
+    while (b0 > 0 && fabs(lam[b0 - 1] - lam[c]) <= ortol) --b0;
+    const int32_t np = c - b0;
     double* base = scr + (int64_t)(6 * m + 1) * c;  // odd stride: vectors on different LDS banks
+    double* yg = Y + (int64_t)c * m;
+    if (stage) {
+      double* sb = dots + m;
+      for (int32_t i = t; i < 5 * m; i += kTriThreads) sb[i] = base[i];  // DL, DD, DU, DU2, piv
+      for (int32_t i = t; i < m; i += kTriThreads) sb[5 * m + i] = yg[i];
+      __syncthreads();
+      base = sb;
+    }
     double *DL = base, *DD = base + m, *DU = base + 2 * m, *DU2 = base + 3 * m;
     int32_t* piv = (int32_t*)(base + 4 * m);
-    double* y = Y + (int64_t)c * m;
+    double* y = stage ? base + 5 * m : yg;
     for (int it = 0; it < 3; ++it) {
       if (t == 0) tri_solve(m, DL, DD, DU, DU2, piv, y);
       __syncthreads();
-      for (int32_t b = c - 1; b >= 0 && fabs(lam[b] - lam[c]) <= ortol; --b) {
-        const double* yb = Y + (int64_t)b * m;
-        double dp = 0.0;
-        for (int32_t i = t; i < m; i += kTriThreads) dp = fma(yb[i], y[i], dp);
-        dp = block_sum(dp, red);
-        for (int32_t i = t; i < m; i += kTriThreads) y[i] -= dp * yb[i];
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int32_t j = wv; j < np; j += kWaves) {
+          const double* yb = Y + (int64_t)(b0 + j) * m;
+          double dp = 0.0;
+          for (int32_t i = ln; i < m; i += 64) dp = fma(yb[i], y[i], dp);
+          dp = wave_sum(dp);
+          if (ln == 0) dots[j] = dp;
+        }
+        __syncthreads();
+        for (int32_t i = t; i < m; i += kTriThreads) {
+          double s = 0.0;
+          for (int32_t j = 0; j < np; ++j) s = fma(dots[j], Y[(int64_t)(b0 + j) * m + i], s);
+          y[i] -= s;
+        }
         __syncthreads();
       }
       double nn = 0.0;
@@ -1191,6 +1221,11 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_eigvecs(int32_t m, int32_t 
       nn = block_sum(nn, red);
       const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
       for (int32_t i = t; i < m; i += kTriThreads) y[i] *= inv;
+      __syncthreads();
+    }
+    if (stage) {
+      // back to Y before the next member reads it
+      for (int32_t i = t; i < m; i += kTriThreads) yg[i] = y[i];
       __syncthreads();
     }
   }

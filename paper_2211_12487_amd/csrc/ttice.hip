@@ -386,8 +386,10 @@ int ttice_state::dense_svd(int64_t rows, int64_t Ncol, const View& vR, bool left
   const int64_t m = left ? rows : Ncol;
   const int64_t K = left ? Ncol : rows;
   const View vRt = transposed(vR);  // Ncol x rows
-  // (m <= 32: one slice, on the matrix-core product kernel)
-  const int32_t kchunk = m <= 32 ? (int32_t)K : gram_kchunk((int32_t)m, K);
+  // (m <= 32 with K linear in memory: one slice, which the matrix-core
+  // product kernel splits itself; a frame-major K takes the slices here)
+  const bool k_linear = (left ? vR.cpf : vR.rpf) == kUnframed;
+  const int32_t kchunk = (m <= 32 && k_linear) ? (int32_t)K : gram_kchunk((int32_t)m, K);
   const int64_t Sg = (K + kchunk - 1) / kchunk;
   CKS(ensure(gpart, (size_t)Sg * m * m * sizeof(double)));
   CKS(ensure(gram, (size_t)m * m * sizeof(double)));

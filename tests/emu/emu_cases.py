@@ -348,6 +348,18 @@ def case_eigensolver():
         G[3, 5] = G[5, 3] = np.nan
         w, _ = run(G, 0)
         assert np.isnan(w).all(), (m, w[:4])
+    # one large cluster inside the kept set (a Gram matrix's small eigenvalues
+    # within 1e-3 ||T|| of each other): the kept subspace against LAPACK's
+    for m, r in ((120, 41), (300, 41)):
+        Q, _ = np.linalg.qr(rng.standard_normal((m, m)))
+        lam = np.concatenate([[1.0], np.linspace(1.1e-4, 1e-4, 40), np.linspace(1e-8, 1e-9, m - 41)])
+        G = (Q * lam) @ Q.T
+        w, X = run(G, r)
+        assert np.abs(w - lam).max() <= 1e-13, m
+        P = X @ X.T
+        Pref = Q[:, :r] @ Q[:, :r].T
+        assert np.abs(P - Pref).max() <= 1e-9, (m, np.abs(P - Pref).max())
+        assert np.abs(X.T @ X - np.eye(r)).max() <= 1e-12, (m, np.abs(X.T @ X - np.eye(r)).max())
     # rank deficient
     B = rng.standard_normal((30, 2))
     w, X = run(B @ B.T, 2)
