@@ -160,7 +160,7 @@ __device__ __forceinline__ int tile_row(int kq, int i) {
 }
 
 template <int P, typename TB, typename TE, typename TD>
-__device__ __forceinline__ void gemm_mx_body(int32_t M, int32_t N, int32_t K, double alpha,
+__device__ __forceinline__ void gemm_mx_body(int32_t M, int32_t N, int32_t kbeg, int32_t K, double alpha,
                                              const double* __restrict__ A, View va, const TB* __restrict__ B,
                                              View vb, double beta, const TE* __restrict__ E, View ve,
                                              TD* __restrict__ D, View vd, double* __restrict__ colpart) {
@@ -180,9 +180,9 @@ __device__ __forceinline__ void gemm_mx_body(int32_t M, int32_t N, int32_t K, do
 
   constexpr int KB = kb<P>();
   double a[KB / 2], b[KB / 4];
-  if (K > 0) load_tile<KB, TB>(A, va, a_kfast, M, m0, B, vb, bco, 0, K, t, a, b);
+  if (kbeg < K) load_tile<KB, TB>(A, va, a_kfast, M, m0, B, vb, bco, kbeg, K, t, a, b);
   int buf = 0;
-  for (int32_t k0 = 0; k0 < K; k0 += KB) {
+  for (int32_t k0 = kbeg; k0 < K; k0 += KB) {
     void* cur = lds + buf * Tile<P>::bytes;
     Ops<P>::store_tile(cur, a_kfast, M, m0, N, n0, k0, K, t, a, b);
     __syncthreads();
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mx(int32_t M, int32_t N, int3
                                                       const TB* __restrict__ B, View vb, double beta,
                                                       const TE* __restrict__ E, View ve, TD* __restrict__ D,
                                                       View vd, double* __restrict__ colpart) {
-  gemm_mx_body<P, TB, TE, TD>(M, N, K, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart);
+  gemm_mx_body<P, TB, TE, TD>(M, N, 0, K, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart);
 }
 
 // FP64: registers held to three waves per SIMD, so three blocks (3 x 52 KB
@@ -256,7 +256,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     int32_t M, int32_t N, int32_t K, double alpha, const double* __restrict__ A, View va, const TB* __restrict__ B,
     View vb, double beta, const TE* __restrict__ E, View ve, TD* __restrict__ D, View vd,
     double* __restrict__ colpart) {
-  gemm_mx_body<kMxF64, TB, TE, TD>(M, N, K, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart);
+  gemm_mx_body<kMxF64, TB, TE, TD>(M, N, 0, K, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart);
+}
+
+// FP64, K split over grid z: slice z (K range [z kchunk, (z+1) kchunk))
+// writes its partial product A B to part + z M N (M x N, row-major); a
+// second kernel adds the slices in order and applies the epilogue
+template <typename TB>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_mx64_part(
+    int32_t M, int32_t N, int32_t K, int32_t kchunk, const double* __restrict__ A, View va,
+    const TB* __restrict__ B, View vb, double* __restrict__ part) {
+  const int32_t kbeg = (int32_t)blockIdx.z * kchunk;
+  const int32_t kend = min(K, kbeg + kchunk);
+  View vp;
+  vp.rs = N;
+  vp.cs = 1;
+  gemm_mx_body<kMxF64, TB, double, double>(M, N, kbeg, kend, 1.0, A, va, B, vb, 0.0, (const double*)nullptr,
+                                           View(), part + (int64_t)blockIdx.z * M * N, vp, nullptr);
 }
 
 }  // namespace mx

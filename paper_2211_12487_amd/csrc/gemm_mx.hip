@@ -2,6 +2,8 @@
 // launcher behind gemm()'s route for large level contractions.
 #include "gemm_mx.h"
 
+#include <algorithm>
+
 namespace ttice {
 
 template <int P, typename TB, typename TE, typename TD>
@@ -28,6 +30,34 @@ bool gemm_mx_fits(int32_t M, int32_t N, int32_t K, const View& va, const View& v
   const int64_t tiles = (int64_t)((N + mx::BN - 1) / mx::BN) * ((M + mx::BM - 1) / mx::BM);
   return tiles >= 96 && (int64_t)M * N * (int64_t)K >= ((int64_t)1 << 24);
 }
+
+int32_t gemm_mx_split_slices(int32_t M, int32_t N, int32_t K, const View& va, const View& vb, int64_t ws_len) {
+  if (M <= 0 || N <= 0 || K < 2048) return 0;
+  if (va.rpf != kUnframed || va.cpf != kUnframed || vb.rpf != kUnframed) return 0;
+  const int64_t tiles = (int64_t)((N + mx::BN - 1) / mx::BN) * ((M + mx::BM - 1) / mx::BM);
+  // (96 tiles and more: the unsplit product fills the device)
+  if (tiles >= 96 || tiles < 8 || (int64_t)M * N * (int64_t)K < ((int64_t)1 << 27)) return 0;
+  int64_t S = (256 + tiles - 1) / tiles;  // about one block per CU
+  S = std::min<int64_t>({S, (int64_t)K / 1024, 8, ws_len / ((int64_t)M * N)});
+  return S >= 2 ? (int32_t)S : 0;
+}
+
+template <typename TB>
+hipError_t gemm_mx64_part(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t S, int32_t kchunk,
+                          const double* A, View va, const TB* B, View vb, double* part) {
+  constexpr size_t lds = mx::lds_bytes<mx::kMxF64>();
+  static const hipError_t attr = hipFuncSetAttribute((const void*)mx::k_gemm_mx64_part<TB>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  const dim3 grid((unsigned)((N + mx::BN - 1) / mx::BN), (unsigned)((M + mx::BM - 1) / mx::BM), (unsigned)S);
+  hipLaunchKernelGGL((mx::k_gemm_mx64_part<TB>), grid, dim3(mx::kThreads), lds, st, M, N, K, kchunk, A, va, B, vb,
+                     part);
+  return hipGetLastError();
+}
+template hipError_t gemm_mx64_part<double>(hipStream_t, int32_t, int32_t, int32_t, int32_t, int32_t, const double*,
+                                           View, const double*, View, double*);
+template hipError_t gemm_mx64_part<float>(hipStream_t, int32_t, int32_t, int32_t, int32_t, int32_t, const double*,
+                                          View, const float*, View, double*);
 
 template <typename TB, typename TE, typename TD>
 hipError_t gemm_mx(hipStream_t st, int prec, int32_t M, int32_t N, int32_t K, double alpha, const double* A,

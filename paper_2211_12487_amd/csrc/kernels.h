@@ -179,6 +179,14 @@ inline int32_t gemm_row_blocks(int32_t M) { return M > 0 ? (M + 63) / 64 : 1; }
 // gemm_mx_fits: the shape and views it supports without a K split.
 bool gemm_mx_fits(int32_t M, int32_t N, int32_t K, const View& va, const View& vb, const View& ve, const View& vd,
                   bool has_e, bool has_d, bool bnorm);
+// Products with too few output tiles to fill the device unsplit and a long
+// K: the number of K slices gemm() gives the FP64 matrix-core kernel (0:
+// none), at most what ws_len doubles of partials hold; and the launch that
+// writes slice z's partial product to part + z M N (row-major).
+int32_t gemm_mx_split_slices(int32_t M, int32_t N, int32_t K, const View& va, const View& vb, int64_t ws_len);
+template <typename TB>
+hipError_t gemm_mx64_part(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t S, int32_t kchunk,
+                          const double* A, View va, const TB* B, View vb, double* part);
 template <typename TB, typename TE, typename TD>
 hipError_t gemm_mx(hipStream_t st, int prec, int32_t M, int32_t N, int32_t K, double alpha, const double* A,
                    View va, const TB* B, View vb, double beta, const TE* E, View ve, TD* D, View vd,

@@ -213,6 +213,33 @@ __device__ void split_finish(double (&acc)[4][4], int32_t M, int32_t N, int32_t 
   gemm_epilogue<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, D, vd, colpart, red);
 }
 
+// The S K-slice partials of the matrix-core split (part + z M N, row-major)
+// added in the order z = 0, 1, ... per element of a 64 x 64 output tile (the
+// acc layout of the tiled products), then their epilogue: alpha, beta E, D
+// and the column energies.
+template <typename TE, typename TD>
+__global__ __launch_bounds__(256) void k_mx_split_finish(int32_t M, int32_t N, int32_t S,
+                                                         const double* __restrict__ part, double alpha, double beta,
+                                                         const TE* __restrict__ E, View ve, TD* __restrict__ D,
+                                                         View vd, double* __restrict__ colpart) {
+  __shared__ double red[256];
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  const int32_t m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int64_t MN = (int64_t)M * N;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int32_t m = min(m0 + ty + 16 * i, M - 1), n = min(n0 + tx + 16 * j, N - 1);
+      const double* p = part + (int64_t)m * N + n;
+      double s = 0.0;
+      for (int32_t z = 0; z < S; ++z) s += p[z * MN];
+      acc[i][j] = s;  // (rows and columns past the output are dropped by the epilogue)
+    }
+  gemm_epilogue<TE, TD>(acc, M, N, m0, n0, alpha, beta, E, ve, D, vd, colpart, red);
+}
+
 // ---------------------------------------------------------------------------
 // K-split product on the FP64 matrix cores for small outputs (each tile's
 // valid block at most four 16 x 16 sub-blocks: M, N <= 32, or one of them
@@ -755,6 +782,22 @@ hipError_t gemm(hipStream_t st, int32_t M, int32_t N, int32_t K, int32_t kchunk,
                 const double* A, View va, const TB* B, View vb, double beta, const TE* E, View ve,
                 TD* D, View vd, int64_t dz, double* colpart, double* bnorm, GemmWs ws, int prec) {
   if (N <= 0) return hipSuccess;
+  if ((kchunk <= 0 || kchunk >= K) && !bnorm && ws.p) {
+    // too few output tiles for the unsplit matrix-core product and a long K:
+    // FP64 partials of K slices, then their fixed-order sum and epilogue
+    const int32_t S = gemm_mx_split_slices(M, N, K, va, vb, ws.len);
+    if (S >= 2) {
+      int32_t chunk = (K + S - 1) / S;
+      chunk = (chunk + 15) / 16 * 16;
+      const int32_t Sx = (K + chunk - 1) / chunk;
+      hipError_t e = gemm_mx64_part<TB>(st, M, N, K, Sx, chunk, A, va, B, vb, ws.p);
+      if (e != hipSuccess) return e;
+      const dim3 grid((unsigned)((N + 63) / 64), (unsigned)gemm_row_blocks(M));
+      hipLaunchKernelGGL((k_mx_split_finish<TE, TD>), grid, dim3(256), 0, st, M, N, Sx, (const double*)ws.p, alpha,
+                         beta, E, ve, D, vd, colpart);
+      return hipGetLastError();
+    }
+  }
   if ((kchunk <= 0 || kchunk >= K) && gemm_mx_fits(M, N, K, va, vb, ve, vd, E != nullptr, D != nullptr, bnorm))
     return gemm_mx<TB, TE, TD>(st, prec, M, N, K, alpha, A, va, B, vb, beta, E, ve, D, vd, colpart);
   const int32_t gx = (N + 63) / 64, gy = gemm_row_blocks(M);

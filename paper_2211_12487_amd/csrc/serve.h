@@ -9,6 +9,11 @@
 
 namespace ttice {
 
+// Doubles of every state's K-split workspace (partials of the products that
+// split K: up to 3 slices of a 1400 x 512 output at level 6 of the order-8
+// stream); the server's footprint estimate counts it.
+constexpr int64_t kSplitKDoubles = (int64_t)1 << 22;
+
 // Level 1 of the state's Algorithm 1 updates always takes the fused
 // projection with one column per lane (alone or grouped: the same values).
 void serve_mark(ttice_state* st);

@@ -110,7 +110,7 @@ int64_t projected_bytes(int32_t d, const int64_t* dims, int64_t N, int64_t T) {
   }
   cores += (double)T * (double)rb[d] + ttice::kProjTail;  // last core: stored tensors x r_d
   mmax = std::min(mmax, 4096.0);
-  const double bytes = 4.0 * 8.0 * (double)N * P + 16.0 * 8.0 * mmax * mmax + 8.0 * cores + 8.0 * (1 << 20);
+  const double bytes = 4.0 * 8.0 * (double)N * P + 16.0 * 8.0 * mmax * mmax + 8.0 * cores + 8.0 * (double)ttice::kSplitKDoubles;
   return (int64_t)std::min(bytes, 9.0e18);
 }
 

@@ -165,7 +165,7 @@ struct ttice_state {
   // K-split products' workspace: partials, and arrival counters that start
   // at zero and are left at zero by every product
   int gemm_ws() {
-    CKS(ensure(splitk, ((size_t)1 << 20) * sizeof(double)));
+    CKS(ensure(splitk, (size_t)kSplitKDoubles * sizeof(double)));
     if (!tilecnt.p) {
       CKS(ensure(tilecnt, kTileCounters * sizeof(int)));
       CK(hipMemsetAsync(tilecnt.p, 0, kTileCounters * sizeof(int), stream));

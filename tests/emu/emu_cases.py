@@ -394,6 +394,28 @@ def case_gemm_mx():
         assert np.abs(D - ref).max() <= 1e-12 * np.abs(ref).max(), (M, N, K)
         cref = np.array([(ref[64 * b:64 * (b + 1)] ** 2).sum(0) for b in range(MB)])
         assert np.abs(cp - cref).max() <= 1e-12 * np.abs(cref).max(), (M, N, K)
+    # few output tiles and a long K: FP64 partials of K slices, their
+    # fixed-order sum and the epilogue (beta E, column energies)
+    L.hipemu_gemm_ws.argtypes = [c_int, c_int, c_int, c_dbl, vp, vp, c_dbl, vp, vp, vp, vp, ctypes.c_long, vp]
+    L.hipemu_gemm_split_slices.argtypes = [c_int, c_int, c_int, ctypes.c_long]
+    M, N, K = 200, 256, 2630
+    ws_len = 1 << 20
+    assert L.hipemu_gemm_split_slices(M, N, K, ws_len) == 2
+    assert L.hipemu_gemm_split_slices(M, N, K, M * N) == 0  # workspace for one slice only: unsplit
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    E = rng.standard_normal((M, N))
+    D = np.zeros((M, N))
+    MB = (M + 63) // 64
+    cp = np.zeros((MB, N))
+    ws = np.zeros(ws_len)
+    cnt = np.zeros(256, dtype=np.int32)
+    assert L.hipemu_gemm_ws(M, N, K, -1.0, A.ctypes.data, B.ctypes.data, 1.0, E.ctypes.data, D.ctypes.data,
+                            cp.ctypes.data, ws.ctypes.data, ws_len, cnt.ctypes.data) == 0
+    ref = E - A @ B
+    assert np.abs(D - ref).max() <= 1e-12 * np.abs(ref).max()
+    cref = np.array([(ref[64 * b:64 * (b + 1)] ** 2).sum(0) for b in range(MB)])
+    assert np.abs(cp - cref).max() <= 1e-12 * np.abs(cref).max()
 
 
 def case_proj_kernel():

@@ -18,3 +18,25 @@ extern "C" int hipemu_gemm_mx(int M, int N, int K, double alpha, const double* A
              ? 0
              : -1;
 }
+
+// The same through gemm() with a K-split workspace of ws_len doubles (the
+// matrix-core split for products with few output tiles and a long K):
+// A (M x K) row-major, B (K x N) row-major, E, D row-major M x N.
+extern "C" int hipemu_gemm_ws(int M, int N, int K, double alpha, const double* A, const double* B, double beta,
+                              const double* E, double* D, double* colpart, double* ws, long ws_len, int* cnt) {
+  ttice::GemmWs g;
+  g.p = ws;
+  g.len = ws_len;
+  g.cnt = cnt;
+  g.ncnt = 256;
+  const ttice::View va = ttice::row_major(K), vb = ttice::row_major(N), vd = ttice::row_major(N);
+  return ttice::gemm<double, double, double>(nullptr, M, N, K, K, alpha, A, va, B, vb, beta, E, vd, D, vd, 0,
+                                             colpart, nullptr, g) == hipSuccess
+             ? 0
+             : -1;
+}
+
+// the number of K slices gemm() gives such a product (0: unsplit)
+extern "C" int hipemu_gemm_split_slices(int M, int N, int K, long ws_len) {
+  return ttice::gemm_mx_split_slices(M, N, K, ttice::row_major(K), ttice::row_major(N), ws_len);
+}
