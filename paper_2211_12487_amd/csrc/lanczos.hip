@@ -99,9 +99,17 @@ __global__ __launch_bounds__(256) void k_chol_inv(int32_t b, const double* __res
     for (int i = c + 1; i < b; ++i) {
       double s = 0.0;
       if (!dead[i]) {
-        s = -A[i * la + c] * dinv[c];
-        for (int k = c + 1; k < i; ++k) s = fma(-A[i * la + k], A[c * la + k], s);
-        s /= A[i * la + i];
+        // four partial sums (added in a fixed order) break the FMA chain
+        double s0 = -A[i * la + c] * dinv[c], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int k = c + 1;
+        for (; k + 3 < i; k += 4) {
+          s0 = fma(-A[i * la + k], A[c * la + k], s0);
+          s1 = fma(-A[i * la + k + 1], A[c * la + k + 1], s1);
+          s2 = fma(-A[i * la + k + 2], A[c * la + k + 2], s2);
+          s3 = fma(-A[i * la + k + 3], A[c * la + k + 3], s3);
+        }
+        for (; k < i; ++k) s0 = fma(-A[i * la + k], A[c * la + k], s0);
+        s = ((s0 + s1) + (s2 + s3)) / A[i * la + i];
       }
       A[c * la + i] = s;
     }
