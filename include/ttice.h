@@ -186,8 +186,11 @@ int ttice_reserve(ttice_state* st, int64_t max_batch);
 
 /* Write the approximations of stored tensors first .. first+count-1
  * (eq:last_core_latent) to out: device pointer, [count][n_1]...[n_d] C-order,
- * element type dtype.  Errors: EINVAL (range outside [0, n_total), bad
- * dtype, null out with count > 0), ENOMEM, EDEVICE, ESTATE. */
+ * element type dtype.  out is written on the state's stream (TTICE_OPT_STREAM)
+ * and the call returns once it is written; work the caller still has queued
+ * on out's memory on other streams must be complete first.  Errors: EINVAL
+ * (range outside [0, n_total), bad dtype, null out with count > 0), ENOMEM,
+ * EDEVICE, ESTATE. */
 int ttice_reconstruct(ttice_state* st, int64_t first, int64_t count, void* out,
                       int32_t dtype);
 
@@ -228,8 +231,10 @@ int ttice_ranks(const ttice_state* st, int64_t* ranks, int64_t* n_total);
  * i in [0, d): U_{i+1}, shape (r_i n_{i+1}) x r_{i+1};
  * i == d: the last core TRANSPOSED, shape N_total x r_d (row j = latent
  * vector of stored tensor j).  rows/cols (host, may be NULL) receive the
- * shape; out may be NULL to query the shape only.  Errors: ESTATE, EINVAL,
- * EDEVICE. */
+ * shape; out may be NULL to query the shape only.  out is written on the
+ * state's stream and the call returns once it is written (the caller's work
+ * on out's memory on other streams must be complete first).  Errors: ESTATE,
+ * EINVAL, EDEVICE. */
 int ttice_get_core(ttice_state* st, int32_t i, double* out, int64_t* rows, int64_t* cols);
 
 /* Checkpoint / resume.  The cores are the compressed store of the stream

@@ -95,6 +95,14 @@ class KernelStats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+def _output_ready(out: torch.Tensor) -> None:
+    """The library writes `out` on the state's own stream (for a served state,
+    a worker's non-blocking stream), unordered with torch's current stream:
+    work torch has queued on that memory (an allocation's previous user)
+    must be done first.  The library call returns after its write."""
+    torch.cuda.current_stream(out.device).synchronize()
+
+
 class TTICEError(RuntimeError):
     def __init__(self, code: int, what: str):
         super().__init__(f"{what}: {_strerror(code)} ({code})")
@@ -274,6 +282,7 @@ class TTICE:
             count = self.n_total - first
         out = torch.empty((count,) + self.dims, dtype=dtype,
                           device=device if device is not None else torch.device("cuda"))
+        _output_ready(out)
         _check(lib().ttice_reconstruct(self._h, first, count, ctypes.c_void_p(out.data_ptr()),
                                        _dtype_code(dtype)), "ttice_reconstruct")
         return out
@@ -295,8 +304,9 @@ class TTICE:
         """Core i (0..d-1: U_{i+1}, (r_i n_{i+1}) x r_{i+1}); i == d: last core transposed."""
         rows, cols = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().ttice_get_core(self._h, i, None, ctypes.byref(rows), ctypes.byref(cols)), "ttice_get_core")
-        out = torch.zeros((rows.value, cols.value), dtype=torch.float64, device="cuda")
+        out = torch.empty((rows.value, cols.value), dtype=torch.float64, device="cuda")
         if out.numel():
+            _output_ready(out)
             _check(lib().ttice_get_core(self._h, i, ctypes.c_void_p(out.data_ptr()), None, None), "ttice_get_core")
         return out
 
